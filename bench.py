@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Benchmark of the PID hot path on one MI355X.
+
+Default (headline) workload: the 2D soft-mask ensemble, N = 256 members on a
+512 x 512 grid (M = 262,144 points), FP32 masks.  One step = the whole hot
+path on that batch: all-pairs PID (FP16 MFMA Gram numerators, FP64 masses,
+ratios, depths, ranks) plus PID-mean (one streaming pass, depths, ranks).
+``value`` = N^2 * M / (seconds per step), pair*points/s, inputs resident in
+HBM.  The line also carries the roofline of the dominant kernel measured with
+HIP events inside the timed region, the FP64 CPU oracle timed on the host, the
+measured depth errors, and side measurements of the other workloads (FP32
+comparator, BF16 split, fused scalar-field extraction with its binary INT8
+variant, large 3D PID-mean in GB/s, 2D FP64).
+
+``--mode serve`` runs the serving workload instead (Poisson arrivals of mixed
+requests) and prints p50/p99 latency and requests/s.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "all-pairs PID pair·points/s (MFMA vs FP32) at ≤1e-4 err; PID-mean GB/s; p99 ms"
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SOURCES = ["paper_2512_15187_amd/csrc/gram_kernel.h", "paper_2512_15187_amd/csrc/device_common.h",
+                  "paper_2512_15187_amd/csrc/k_gram.hip", "paper_2512_15187_amd/csrc/k_gram_f32.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_f16_2d_n256_m262144_traffic.txt")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the gram kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_ms(pid, name):
+    ms, n = pid.pid_timing_get(name)
+    return (ms / n if n else float("nan")), n
+
+
+def cpu_baseline(U_host, budget_s=12.0):
+    """The FP64 oracle (untuned) on the same step: all-pairs PID + PID-mean."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    U64 = U_host.astype(np.float64)
+    n, m = U64.shape
+    reps, t_tot = 0, 0.0
+    ref = refm = None
+    while reps == 0 or (t_tot < budget_s and reps < 20):
+        t0 = time.perf_counter()
+        ref = oracle.pid(U64)
+        refm = oracle.pid_mean(U64)
+        t_tot += time.perf_counter() - t0
+        reps += 1
+    t = t_tot / reps
+    return dict(value=n * n * m / t, unit="pair*points/s", cores=int(threads), kind="oracle",
+                sample=f"the full workload ({n} x {m} FP64), all-pairs PID + PID-mean, mean of {reps} runs",
+                seconds_per_step=t), ref, refm
+
+
+def headline(args):
+    import numpy as np
+    import torch
+
+    import paper_2512_15187_amd as pid
+    import synth
+
+    dev = "cuda:0"
+    log("generating the 2D soft-mask ensemble N=256 on 512x512 (FP32)")
+    U, _ = synth.config1(device=dev)
+    n, m = U.shape
+    pairs = pid.PreparedCall("pairs", U, gemm="f16", inclusion=True)
+    mean = pid.PreparedCall("mean", U)
+
+    def step():
+        pairs.run()
+        mean.run()
+
+    log("timing the step")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    pid.pid_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    kt = {k: kernel_ms(pid, k) for k in ("gram", "gram_reduce", "pairs_inclusion", "pairs_depths",
+                                          "pidmean", "pidmean_finalize", "rank")}
+    pid.pid_timing_enable(False)
+    log(f"step {t_step * 1e3:.3f} ms; kernels " + ", ".join(f"{k} {v[0] * 1e3:.1f} us" for k, v in kt.items()))
+
+    gram_ms = kt["gram"][0]
+    algo_bytes = n * m * 4
+    achieved = algo_bytes / (gram_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=read_traffic(), kernel="gram (FP16 MFMA)",
+                kernel_avg_us=round(gram_ms * 1e3, 2), algorithmic_bytes=algo_bytes)
+
+    res_pairs = {k: v.clone() for k, v in pairs.out.items()}
+    res_mean = {k: v.clone() for k, v in mean.out.items()}
+    U_host = U.cpu().numpy()
+
+    extra = {}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host")
+        cpu, ref, refm = cpu_baseline(U_host)
+        extra["depth_err_pairs_f16"] = float(np.max(np.abs(res_pairs["depth"].cpu().numpy() - ref["depth"])))
+        extra["in_err_pairs_f16"] = float(max(np.max(np.abs(res_pairs["in_in"].cpu().numpy() - ref["in_in"])),
+                                              np.max(np.abs(res_pairs["in_out"].cpu().numpy() - ref["in_out"]))))
+        extra["inclusion_err_pairs_f16"] = float(np.max(np.abs(res_pairs["inclusion"].cpu().numpy() - ref["inclusion"])))
+        extra["depth_err_mean"] = float(np.max(np.abs(res_mean["depth"].cpu().numpy() - refm["depth"])))
+        from oracle import rank_order
+        extra["ranks_equal_pairs"] = bool((res_pairs["rank"].cpu().numpy() == rank_order(ref["depth"])[0]).all())
+        extra["ranks_equal_mean"] = bool((res_mean["rank"].cpu().numpy() == rank_order(refm["depth"])[0]).all())
+        cpu.pop("seconds_per_step", None)
+
+    if not args.no_extras:
+        extra.update(side_measurements(pid, torch, np, synth, U, args, ref if cpu else None))
+
+    line = {
+        "metric": METRIC, "value": n * n * m / t_step, "unit": "pair*points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "2D soft masks, N=256 on 512x512 (M=262144), FP32 masks; all-pairs PID "
+                               "(FP16 MFMA Gram, FP64 normalisation) + PID-mean, with ranks",
+                   "n": n, "m": m, "scheme": "f16", "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def side_measurements(pid, torch, np, synth, U, args, ref):
+    out = {}
+    dev = "cuda:0"
+    n, m = U.shape
+    k = max(3, args.steps // 4)
+    # FP32 comparator and BF16 split on the same ensemble
+    for scheme in ("f32", "bf16_split", "bf16"):
+        call = pid.PreparedCall("pairs", U, gemm=scheme)
+        pid.pid_timing_enable(True)
+        t = timed(call.run, k, 2, torch)
+        g, _ = kernel_ms(pid, "gram")
+        pid.pid_timing_enable(False)
+        out[f"pairs_{scheme}_pp_per_s"] = n * n * m / t
+        out[f"gram_{scheme}_us"] = g * 1e3
+        if ref is not None:
+            out[f"depth_err_pairs_{scheme}"] = float(np.max(np.abs(call.out["depth"].cpu().numpy() - ref["depth"])))
+    pf16 = pid.PreparedCall("pairs", U, gemm="f16")
+    pid.pid_timing_enable(True)
+    t16 = timed(pf16.run, k, 2, torch)
+    g16, _ = kernel_ms(pid, "gram")
+    pid.pid_timing_enable(False)
+    out["pairs_f16_pp_per_s"] = n * n * m / t16
+    out["gram_f16_us"] = g16 * 1e3
+    out["mfma_f16_vs_fp32_call"] = out["pairs_f16_pp_per_s"] / out["pairs_f32_pp_per_s"]
+    out["mfma_f16_vs_fp32_gram"] = out["gram_f32_us"] / out["gram_f16_us"]
+    out["mfma_bf16split_vs_fp32_gram"] = out["gram_f32_us"] / out["gram_bf16_split_us"]
+    # issued MFMA utilisation of the split scheme (3 products per unique MAC on the upper sub-tiles)
+    nbt = (n + 31) // 32
+    sub_macs = nbt * (nbt + 1) // 2 * 1024 * m
+    out["bf16_split_issued_tflops"] = 3 * 2 * sub_macs / (out["gram_bf16_split_us"] * 1e-6) / 1e12
+    out["bf16_split_issued_frac_of_2500"] = out["bf16_split_issued_tflops"] / 2500.0
+    out["f16_issued_tflops"] = 2 * sub_macs / (out["gram_f16_us"] * 1e-6) / 1e12
+
+    # 3D PID-mean, N=64 FP16 on 256^3 with weights (HBM streaming)
+    log("3D PID-mean workload N=64 on 256^3 (FP16 + FP32 weights)")
+    U3, w3 = synth.config3(device=dev)
+    n3, m3 = U3.shape
+    call = pid.PreparedCall("mean", U3, w3)
+    pid.pid_timing_enable(True)
+    t = timed(call.run, max(5, args.steps // 2), 2, torch)
+    km, _ = kernel_ms(pid, "pidmean")
+    pid.pid_timing_enable(False)
+    b3 = n3 * m3 * 2 + m3 * 4
+    out["mean3d_call_ms"] = t * 1e3
+    out["mean3d_kernel_us"] = km * 1e3
+    out["mean3d_GBps"] = b3 / (km * 1e-3) / 1e9
+    out["mean3d_frac_hbm"] = out["mean3d_GBps"] / HBM_PEAK_GBPS
+    out["mean3d_call_GBps"] = b3 / t / 1e9
+    callu = pid.PreparedCall("mean", U3)
+    pid.pid_timing_enable(True)
+    timed(callu.run, max(5, args.steps // 2), 2, torch)
+    kmu, _ = kernel_ms(pid, "pidmean")
+    pid.pid_timing_enable(False)
+    out["mean3d_unweighted_GBps"] = n3 * m3 * 2 / (kmu * 1e-3) / 1e9
+    del U3, w3, call, callu
+
+    # scalar fields -> fuzzy contours, N=128 on 128^3, fused extraction
+    log("scalar-field workload N=128 on 128^3 (FP32 fields, fused Phi)")
+    F, iso = synth.config2(device=dev)
+    nf, mf = F.shape
+    giso = dict(kind="gaussian", c=iso["c"], sigma=iso["sigma"], side=iso["side"])
+    siso = dict(kind="step", c=iso["c"], side=iso["side"])
+    for name, call in (("fields_pairs_f16", pid.PreparedCall("pairs", F, iso=giso, gemm="f16")),
+                       ("fields_pairs_i8", pid.PreparedCall("pairs", F, iso=siso, gemm="i8")),
+                       ("fields_mean", pid.PreparedCall("mean", F, iso=giso)),
+                       ("fields_mean_binary", pid.PreparedCall("mean", F, iso=siso))):
+        pid.pid_timing_enable(True)
+        t = timed(call.run, k, 2, torch)
+        kn = "gram" if "pairs" in name else "pidmean"
+        kk, _ = kernel_ms(pid, kn)
+        pid.pid_timing_enable(False)
+        out[f"{name}_call_ms"] = t * 1e3
+        out[f"{name}_kernel_GBps"] = nf * mf * 4 / (kk * 1e-3) / 1e9
+        if "pairs" in name:
+            out[f"{name}_pp_per_s"] = nf * nf * mf / t
+    del F
+
+    # 2D FP64 plain PID, N=50 on 128x128
+    U0, _ = synth.config0(device=dev)
+    p0 = pid.PreparedCall("pairs", U0, gemm="f64")
+    m0 = pid.PreparedCall("mean", U0)
+    t = timed(lambda: (p0.run(), m0.run()), k, 2, torch)
+    out["fp64_2d_n50_step_ms"] = t * 1e3
+    return out
+
+
+def serve(args):
+    from serve_bench import run_serving  # noqa: E402  (kept beside this file)
+    print(json.dumps(run_serving(args)), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", choices=["headline", "serve"], default="headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--requests", type=int, default=400, help="serve mode: number of requests")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the PID hot path is built and timed on a single "
+              "MI355X; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.mode == "serve":
+        serve(args)
+    else:
+        headline(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * pid.h -- C ABI of the MI355X (gfx950) Probabilistic Inclusion Depth library.
+ *
+ * The library computes, for an ensemble of N fuzzy contours given as
+ * membership probabilities on M grid points, the Probabilistic Inclusion Depth
+ * (PID) and its linear-time variant PID-mean, together with ranks.
+ *
+ * Notation (paper sections in parentheses):
+ *   u_i(x) in [0,1]        membership probability of member i at point x (Sec. 3.2)
+ *   w_x >= 0               volume of the cell of point x; 1 on uniform grids (Sec. 3.4)
+ *   m_i = sum_x w_x u_i(x) mass of member i (Sec. 3.2)
+ *   u <_p v = sum_x w u v / sum_x w u, and 0 when m(u) = 0
+ *                           probabilistic inclusion operator (Sec. 3.2, Eqs.
+ *                           expectation_form / prob_contain; Sec. 3.4 weighted form)
+ *   PID:  IN_in(i) = (1/N) sum_j u_i <_p u_j,  IN_out(i) = (1/N) sum_j u_j <_p u_i,
+ *         depth = min(IN_in, IN_out)            (Sec. 3.2, Eq. pid; the sums include j = i)
+ *   PID-mean: ubar = (1/N) sum_i u_i; IN_in = u_i <_p ubar, IN_out = ubar <_p u_i,
+ *         depth = min                             (Sec. 4.1)
+ *   Fuzzy contour of a scalar field f with isovalue ~ N(c, sigma^2):
+ *         u = Phi(side * (f - c) / sigma)          (Sec. 3.5, isovalue distribution)
+ *   Rank: 0 = deepest; equal depths are ordered by the lower member index
+ *         (ranking by depth, Sec. 5.1).
+ *
+ * Conventions of every call:
+ *   - All array pointers are DEVICE pointers owned by the caller; the library
+ *     never frees or keeps them.  The depth calls allocate no device memory:
+ *     the caller passes a workspace of at least pid_workspace_size() bytes.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *     stream).  Outputs are valid after that stream is synchronised.  Inputs
+ *     are never modified.
+ *   - Every call returns a pid_status.  Shape, dtype, pointer and scheme errors
+ *     are detected on the host before anything is launched; the text of the
+ *     last error of the calling thread is returned by pid_last_error().
+ *   - Results are deterministic: the same inputs, shapes and scheme give
+ *     bitwise identical outputs on the same device, whatever else runs.
+ */
+#ifndef PID_H_
+#define PID_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PID_OK = 0,
+  PID_ERR_INVALID_ARG = 1,          /* bad shape, null pointer, bad enum value        */
+  PID_ERR_UNSUPPORTED = 2,          /* valid request this library does not implement  */
+  PID_ERR_WORKSPACE_TOO_SMALL = 3,  /* ws_bytes < pid_workspace_size()                */
+  PID_ERR_DEVICE = 4,               /* a HIP runtime call failed                      */
+  PID_ERR_VALUE_RANGE = 5,          /* PID_FLAG_VALIDATE found a value out of range   */
+  PID_ERR_OVER_BUDGET = 6,          /* serving: request larger than the whole arena   */
+  PID_ERR_CANCELLED = 7,            /* serving: server stopped before the request ran */
+  PID_ERR_INTERNAL = 8
+} pid_status;
+
+/* Element type of the stored ensemble. */
+typedef enum {
+  PID_F64 = 0, PID_F32 = 1, PID_F16 = 2, PID_BF16 = 3,
+  PID_U8 = 4   /* binary masks: every value must be 0 or 1 */
+} pid_dtype;
+
+/* How stored values become membership probabilities (Sec. 3.5). */
+typedef enum {
+  PID_ISO_NONE = 0,      /* values already are probabilities in [0,1] (soft masks)          */
+  PID_ISO_GAUSSIAN = 1,  /* scalar field, isovalue ~ N(c, sigma^2): u = Phi(side*(f-c)/sigma) */
+  PID_ISO_STEP = 2       /* scalar field, sharp isovalue: u = 1 iff side*(f-c) > 0, else 0   */
+} pid_iso_kind;
+
+/* Arithmetic of the all-pairs numerators G_ij = sum_x w u_i u_j. */
+typedef enum {
+  PID_GEMM_AUTO = 0,        /* I8 for unweighted binary input, F64 for F64 input, else F16    */
+  PID_GEMM_F64 = 1,         /* FP64 vector FMA                                                */
+  PID_GEMM_F32 = 2,         /* FP32 vector FMA (plain FP32 comparator)                        */
+  PID_GEMM_F16 = 3,         /* FP16 MFMA, FP32 accumulation (inputs rounded to FP16 once)     */
+  PID_GEMM_BF16 = 4,        /* BF16 MFMA, FP32 accumulation (inputs rounded to BF16 once)     */
+  PID_GEMM_BF16_SPLIT = 5,  /* BF16 MFMA on hi/lo split inputs, three products, FP32 acc.     */
+  PID_GEMM_I8 = 6           /* INT8 MFMA, INT32 accumulation: binary masks, no weights; exact */
+} pid_gemm;
+
+/* Flags of pid_ensemble.flags. */
+#define PID_FLAG_VALIDATE 1u  /* check values first (probabilities in [0,1], U8 in {0,1},
+                                 finite fields, weights finite and >= 0); the call then
+                                 synchronises `stream` and returns PID_ERR_VALUE_RANGE
+                                 without computing anything if a check fails            */
+
+/* The ensemble: N members x M grid points, member-major.  Element (i, x) is at
+ * data[i * ld + x] (ld >= M, in elements).  Rows whose byte address is a
+ * multiple of 16 take the vectorised path; others are read element by element.
+ * weights: M floats (w_x >= 0), or NULL for a uniform grid (w = 1). */
+typedef struct {
+  int64_t n;
+  int64_t m;
+  int64_t ld;
+  int32_t dtype;    /* pid_dtype */
+  uint32_t flags;   /* PID_FLAG_* */
+  const void* data;
+  const float* weights;
+} pid_ensemble;
+
+/* Isovalue model.  side = +1: f > c is inside (p = Phi((f - c)/sigma));
+ * side = -1: f < c is inside (the sublevel set of Sec. 3.1 Eq. 2).
+ * sigma is used by PID_ISO_GAUSSIAN only and must be > 0 there. */
+typedef struct {
+  int32_t kind;     /* pid_iso_kind */
+  int32_t side;     /* +1 or -1 */
+  double c;
+  double sigma;
+} pid_iso;
+
+/* Outputs (device pointers; any may be NULL to skip it).
+ *   inclusion: N x N row-major, inclusion[i*N + j] = u_i <_p u_j (all-pairs only)
+ *   mass, in_in, in_out, depth: N doubles; rank, order: N int32
+ *   (rank[i] = position of member i, 0 = deepest; order[k] = member at position k). */
+typedef struct {
+  double* inclusion;
+  double* mass;
+  double* in_in;
+  double* in_out;
+  double* depth;
+  int32_t* rank;
+  int32_t* order;
+} pid_out;
+
+/* Bytes of device workspace needed by pid_all_pairs (variant 0) or pid_mean
+ * (variant 1) for this ensemble, isovalue model and scheme.  The size depends
+ * on n, m, dtype, iso kind, weights (NULL or not) and scheme only.
+ * iso may be NULL (= PID_ISO_NONE). */
+pid_status pid_workspace_size(const pid_ensemble* ens, const pid_iso* iso, int variant,
+                              int gemm, size_t* bytes);
+
+/* All-pairs PID (Sec. 3.2 Eq. pid with the weighted sums of Sec. 3.4).
+ * The numerators G_ij are one symmetric Gram product of the N x M membership
+ * matrix (scaled by sqrt(w)) computed with `gemm`; masses, ratios and depths are
+ * FP64.  Fuzzy extraction (iso) is applied to each value as it is loaded.
+ * PID_GEMM_I8 (and AUTO on unweighted U8 / STEP input) is exact: G and m are
+ * integers and depths are bitwise reproducible from them (IN_in = S_i/(N m_i)
+ * with S_i = sum_j G_ij; IN_out = (sum over ascending j of G_ij/m_j) / N). */
+pid_status pid_all_pairs(const pid_ensemble* ens, const pid_iso* iso, int gemm,
+                         const pid_out* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* PID-mean (Sec. 4.1): one streaming pass over the ensemble computes, for
+ * every member, m_i and A_i = sum_x w u_i(x) s(x) with s(x) = sum_j u_j(x);
+ * then IN_in = A_i / (N m_i), IN_out = A_i / sum_k m_k.  FP32 inside a point
+ * tile, FP64 across tiles; exact integers for unweighted binary input.
+ * out->inclusion is ignored. */
+pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+/* Fuzzy-contour extraction alone (Sec. 3.5): writes u = model(value) for the
+ * N x M ensemble into `u_out` (dense N x M, row stride M) as float (out_dtype
+ * PID_F32) or double (PID_F64).  Same arithmetic as the fused loaders. */
+pid_status pid_extract(const pid_ensemble* ens, const pid_iso* iso, void* u_out, int out_dtype,
+                       void* stream);
+
+/* Ranks from depths (device arrays of n): rank 0 = deepest, ties by index. */
+pid_status pid_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: requests of uneven ensemble and grid size, admitted by device-memory
+ * footprint and run concurrently (continuous batching).
+ *
+ * The server owns no device memory of its own: `arena` is a caller-allocated
+ * device buffer of `arena_bytes` from which each admitted request's workspace
+ * is carved; a request waits in the admission queue until its workspace fits
+ * and one of `max_slots` execution slots (HIP streams) is free.  The ensemble
+ * and output buffers of a request stay owned by the caller and must stay valid
+ * until the request completes.  Results of a request are bitwise identical to
+ * the same request run alone through pid_all_pairs / pid_mean.
+ * ------------------------------------------------------------------------- */
+typedef struct pid_server pid_server;
+
+typedef struct {
+  int32_t variant;   /* 0 = all-pairs, 1 = PID-mean */
+  int32_t gemm;      /* pid_gemm (all-pairs only)   */
+  pid_ensemble ens;
+  pid_iso iso;
+  pid_out out;
+} pid_request;
+
+pid_status pid_server_create(int device, void* arena, size_t arena_bytes, int max_slots,
+                             pid_server** server);
+/* Non-blocking: validates the request, queues it and returns a ticket. */
+pid_status pid_submit(pid_server* server, const pid_request* req, uint64_t* ticket);
+/* done = 1 once the request finished; result = its status (PID_OK or an error). */
+pid_status pid_poll(pid_server* server, uint64_t ticket, int* done, pid_status* result);
+/* Blocks until the request finished. */
+pid_status pid_wait(pid_server* server, uint64_t ticket, pid_status* result);
+/* Times in seconds on the server's clock: submission, start of its launch, completion. */
+pid_status pid_request_times(pid_server* server, uint64_t ticket, double* t_submit,
+                             double* t_start, double* t_done);
+/* Stops admitting, lets running requests finish, cancels queued ones
+ * (PID_ERR_CANCELLED), joins the scheduler thread and frees host resources. */
+pid_status pid_server_destroy(pid_server* server);
+
+/* Per-kernel timing (diagnostics for benchmarks).  When on, every kernel the
+ * library launches is bracketed by a pair of HIP events recorded on its
+ * stream.  pid_timing_enable() clears the accumulated times (and waits for
+ * pending events); pid_timing_get() waits for the pending events and returns
+ * the total milliseconds and launch count of one kernel: "gram" (all-pairs
+ * numerators), "gram_reduce", "pairs_inclusion", "pairs_depths", "pidmean"
+ * (the streaming PID-mean pass), "pidmean_colsum", "pidmean_finalize",
+ * "rank", "extract".  Unknown names report 0. */
+pid_status pid_timing_enable(int on);
+pid_status pid_timing_get(const char* kernel, double* total_ms, int64_t* launches);
+
+/* Diagnostics. */
+const char* pid_status_string(pid_status s);
+const char* pid_last_error(void);   /* thread-local text of the last failed call */
+int pid_abi_version(void);          /* 1 */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PID_H_ */

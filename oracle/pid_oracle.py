@@ -197,18 +197,29 @@ def eid_sets(masks):
 
 
 # ---------------------------------------------------------------- binary, exact
-def binary_pid(B):
+def binary_pid(B, float_product=False):
     """PID of binary masks with integer sums and one fixed FP64 finishing order.
+
+    ``float_product=True`` forms the integer products ``G = B B^T`` with a
+    float64 matrix product, which is exact while every count is below 2^53
+    (0/1 entries, so every partial sum is an integer of at most M); it is the
+    same integer matrix, computed faster for large M.
 
     ``G`` and ``m`` are exact int64.  ``P_ij = fl(G_ij / m_i)``;
     ``IN_in(i) = fl(S_i / (N m_i))`` with ``S_i = sum_j G_ij`` (one rounding of
     the exact mean of row i); ``IN_out(i) = fl(sum_j fl(G_ij / m_j)) / N`` with
     the sum taken in ascending j, one rounding per addition.  Zero-mass rows are
     0 (Sec. 3.2 convention)."""
-    Bi = np.asarray(B).astype(np.int64)
-    n = Bi.shape[0]
-    G = Bi @ Bi.T
-    m = Bi.sum(axis=1)
+    if float_product:
+        Bf = np.asarray(B).astype(np.float64)
+        assert Bf.shape[1] < 2 ** 53
+        G = (Bf @ Bf.T).astype(np.int64)
+        m = Bf.sum(axis=1).astype(np.int64)
+    else:
+        Bi = np.asarray(B).astype(np.int64)
+        G = Bi @ Bi.T
+        m = Bi.sum(axis=1)
+    n = G.shape[0]
     S = G.sum(axis=1)
     P = np.zeros((n, n), dtype=np.float64)
     in_in = np.zeros(n)

@@ -1,0 +1,297 @@
+// C ABI of the PID library: argument checks, scheme selection, workspace
+// layout and launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/pid.h"
+#include "pid_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pid_status fail(pid_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+pid_status hip_fail(hipError_t e, const char* what) {
+  return fail(PID_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int elem_bytes(int dtype) {
+  switch (dtype) {
+    case PID_F64: return 8;
+    case PID_F32: return 4;
+    case PID_F16: case PID_BF16: return 2;
+    case PID_U8: return 1;
+    default: return 0;
+  }
+}
+
+pid_status check_ensemble(const pid_ensemble* e, const pid_iso* iso, int* iso_kind) {
+  if (!e) return fail(PID_ERR_INVALID_ARG, "ensemble is NULL");
+  if (e->n < 1) return fail(PID_ERR_INVALID_ARG, "n must be >= 1 (got %lld)", (long long)e->n);
+  if (e->n > (1 << 30)) return fail(PID_ERR_UNSUPPORTED, "n too large (%lld)", (long long)e->n);
+  if (e->m < 1) return fail(PID_ERR_INVALID_ARG, "m must be >= 1 (got %lld)", (long long)e->m);
+  if (e->ld < e->m) return fail(PID_ERR_INVALID_ARG, "ld (%lld) < m (%lld)", (long long)e->ld, (long long)e->m);
+  const int eb = elem_bytes(e->dtype);
+  if (eb == 0) return fail(PID_ERR_INVALID_ARG, "unknown dtype %d", e->dtype);
+  if (e->ld > (int64_t(1) << 56) / e->n / eb) return fail(PID_ERR_INVALID_ARG, "n * ld overflows");
+  if (!e->data) return fail(PID_ERR_INVALID_ARG, "data is NULL");
+  if (e->flags & ~PID_FLAG_VALIDATE) return fail(PID_ERR_INVALID_ARG, "unknown flags 0x%x", e->flags);
+  int kind = iso ? iso->kind : PID_ISO_NONE;
+  if (kind != PID_ISO_NONE && kind != PID_ISO_GAUSSIAN && kind != PID_ISO_STEP)
+    return fail(PID_ERR_INVALID_ARG, "unknown iso kind %d", kind);
+  if (kind != PID_ISO_NONE) {
+    if (iso->side != 1 && iso->side != -1) return fail(PID_ERR_INVALID_ARG, "iso side must be +1 or -1");
+    if (!std::isfinite(iso->c)) return fail(PID_ERR_INVALID_ARG, "iso c must be finite");
+    if (kind == PID_ISO_GAUSSIAN && !(iso->sigma > 0.0 && std::isfinite(iso->sigma)))
+      return fail(PID_ERR_INVALID_ARG, "iso sigma must be finite and > 0");
+  }
+  *iso_kind = kind;
+  return PID_OK;
+}
+
+pidk::ExtractHost make_extract(const pid_iso* iso) {
+  pidk::ExtractHost x{};
+  if (!iso || iso->kind == PID_ISO_NONE) { x.side = 1; return x; }
+  x.side = iso->side;
+  x.cd = iso->c;
+  x.cf = (float)iso->c;
+  if (iso->kind == PID_ISO_GAUSSIAN) {
+    x.ad = -(double)iso->side / (iso->sigma * std::sqrt(2.0));
+    x.af = (float)x.ad;
+  }
+  // largest float <= c and smallest float >= c (exact comparisons of float fields)
+  float cf = (float)iso->c;
+  float dn = cf, up = cf;
+  if ((double)cf > iso->c) dn = std::nextafter(cf, -INFINITY);
+  if ((double)cf < iso->c) up = std::nextafter(cf, INFINITY);
+  x.c_dn = dn;
+  x.c_up = up;
+  return x;
+}
+
+bool is_binary_input(const pid_ensemble* e, int kind) {
+  return kind == PID_ISO_STEP || (e->dtype == PID_U8 && kind == PID_ISO_NONE);
+}
+
+pid_status resolve_scheme(const pid_ensemble* e, int kind, int gemm, int* scheme) {
+  const bool bin = is_binary_input(e, kind);
+  switch (gemm) {
+    case PID_GEMM_AUTO:
+      if (bin && !e->weights) *scheme = pidk::SCH_I8;
+      else if (e->dtype == PID_F64) *scheme = pidk::SCH_F64;
+      else if (e->dtype == PID_BF16) *scheme = pidk::SCH_BF16;
+      else *scheme = pidk::SCH_F16;
+      return PID_OK;
+    case PID_GEMM_F64: *scheme = pidk::SCH_F64; return PID_OK;
+    case PID_GEMM_F32: *scheme = pidk::SCH_F32; return PID_OK;
+    case PID_GEMM_F16: *scheme = pidk::SCH_F16; return PID_OK;
+    case PID_GEMM_BF16: *scheme = pidk::SCH_BF16; return PID_OK;
+    case PID_GEMM_BF16_SPLIT: *scheme = pidk::SCH_BF16_SPLIT; return PID_OK;
+    case PID_GEMM_I8:
+      if (!bin) return fail(PID_ERR_INVALID_ARG, "PID_GEMM_I8 needs binary input (U8 masks or PID_ISO_STEP)");
+      if (e->weights) return fail(PID_ERR_INVALID_ARG, "PID_GEMM_I8 is exact only without weights");
+      *scheme = pidk::SCH_I8;
+      return PID_OK;
+    default:
+      return fail(PID_ERR_INVALID_ARG, "unknown gemm scheme %d", gemm);
+  }
+}
+
+// Extra workspace after the kernels' own: depth scratch (for ranks) and the
+// validation flag.
+size_t extra_bytes(int64_t n) { return ((size_t)n * 8 + 255) / 256 * 256 + 256 + 256; }
+
+struct Extras {
+  double* depth;
+  unsigned int* flag;
+};
+
+Extras carve_extras(void* ws, size_t kernel_bytes, int64_t n) {
+  char* base = static_cast<char*>(ws) + ((kernel_bytes + 255) / 256) * 256;
+  Extras x;
+  x.depth = reinterpret_cast<double*>(base);
+  x.flag = reinterpret_cast<unsigned int*>(base + ((size_t)n * 8 + 255) / 256 * 256);
+  return x;
+}
+
+pid_status run_validate(const pid_ensemble* e, int kind, unsigned int* flag, hipStream_t st) {
+  hipError_t err = pidk::launch_validate(*e, kind, flag, st);
+  if (err != hipSuccess) return hip_fail(err, "validate launch");
+  err = hipStreamSynchronize(st);
+  if (err != hipSuccess) return hip_fail(err, "validate sync");
+  unsigned int h = 0;
+  err = hipMemcpy(&h, flag, sizeof(h), hipMemcpyDeviceToHost);
+  if (err != hipSuccess) return hip_fail(err, "validate copy");
+  static const char* what[] = {"", "a probability outside [0,1] or NaN", "a U8 value other than 0/1",
+                               "a non-finite field value", "a negative or non-finite weight"};
+  if (h) return fail(PID_ERR_VALUE_RANGE, "input holds %s", h < 5 ? what[h] : "an invalid value");
+  return PID_OK;
+}
+
+}  // namespace
+
+namespace pidk {
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+}  // namespace pidk
+
+// Internal entry points shared with the server (same arithmetic as the ABI calls).
+namespace pidapi {
+
+pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int variant, int gemm,
+                          size_t* bytes) {
+  int kind = 0;
+  pid_status s = check_ensemble(ens, iso, &kind);
+  if (s != PID_OK) return s;
+  if (!bytes) return fail(PID_ERR_INVALID_ARG, "bytes is NULL");
+  size_t kb = 0;
+  if (variant == 0) {
+    int scheme = 0;
+    s = resolve_scheme(ens, kind, gemm, &scheme);
+    if (s != PID_OK) return s;
+    if (!pidk::pairs_supported(ens->dtype, kind, scheme))
+      return fail(PID_ERR_UNSUPPORTED, "scheme %d is not built for dtype %d with iso kind %d", gemm, ens->dtype, kind);
+    pidk::PairsPlan p = pidk::pairs_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr, scheme);
+    kb = pidk::pairs_workspace(p, ens->n);
+  } else if (variant == 1) {
+    pidk::MeanPlan p = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
+    kb = pidk::mean_workspace(p, ens->n, ens->m);
+  } else {
+    return fail(PID_ERR_INVALID_ARG, "variant must be 0 (all-pairs) or 1 (PID-mean)");
+  }
+  *bytes = ((kb + 255) / 256) * 256 + extra_bytes(ens->n);
+  return PID_OK;
+}
+
+pid_status run(int variant, const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* out,
+               void* ws, size_t ws_bytes, void* stream) {
+  int kind = 0;
+  pid_status s = check_ensemble(ens, iso, &kind);
+  if (s != PID_OK) return s;
+  if (!out) return fail(PID_ERR_INVALID_ARG, "out is NULL");
+  if (!ws) return fail(PID_ERR_INVALID_ARG, "workspace is NULL");
+  size_t need = 0;
+  s = workspace_size(ens, iso, variant, gemm, &need);
+  if (s != PID_OK) return s;
+  if (ws_bytes < need)
+    return fail(PID_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  size_t kb = need - extra_bytes(ens->n);
+  Extras x = carve_extras(ws, kb, ens->n);
+  if (ens->flags & PID_FLAG_VALIDATE) {
+    s = run_validate(ens, kind, x.flag, st);
+    if (s != PID_OK) return s;
+  }
+  pid_out o = *out;
+  const bool want_rank = o.rank || o.order;
+  if (want_rank && !o.depth) o.depth = x.depth;
+  pidk::ExtractHost ex = make_extract(iso);
+  hipError_t err;
+  if (variant == 0) {
+    int scheme = 0;
+    resolve_scheme(ens, kind, gemm, &scheme);
+    pidk::PairsPlan p = pidk::pairs_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr, scheme);
+    err = pidk::launch_pid_pairs(p, *ens, kind, ex, o, ws, st);
+  } else {
+    pidk::MeanPlan p = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
+    err = pidk::launch_pid_mean(p, *ens, kind, ex, o, ws, st);
+  }
+  if (err != hipSuccess) return hip_fail(err, variant == 0 ? "pid_all_pairs launch" : "pid_mean launch");
+  if (want_rank) {
+    err = pidk::launch_rank(o.depth, ens->n, o.rank, o.order, st);
+    if (err != hipSuccess) return hip_fail(err, "rank launch");
+  }
+  return PID_OK;
+}
+
+}  // namespace pidapi
+
+extern "C" {
+
+pid_status pid_workspace_size(const pid_ensemble* ens, const pid_iso* iso, int variant, int gemm,
+                              size_t* bytes) {
+  return pidapi::workspace_size(ens, iso, variant, gemm, bytes);
+}
+
+pid_status pid_all_pairs(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* out,
+                         void* workspace, size_t ws_bytes, void* stream) {
+  return pidapi::run(0, ens, iso, gemm, out, workspace, ws_bytes, stream);
+}
+
+pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  return pidapi::run(1, ens, iso, PID_GEMM_AUTO, out, workspace, ws_bytes, stream);
+}
+
+pid_status pid_extract(const pid_ensemble* ens, const pid_iso* iso, void* u_out, int out_dtype,
+                       void* stream) {
+  int kind = 0;
+  pid_status s = check_ensemble(ens, iso, &kind);
+  if (s != PID_OK) return s;
+  if (!u_out) return fail(PID_ERR_INVALID_ARG, "u_out is NULL");
+  if (out_dtype != PID_F32 && out_dtype != PID_F64)
+    return fail(PID_ERR_INVALID_ARG, "out_dtype must be PID_F32 or PID_F64");
+  hipError_t err = pidk::launch_extract(*ens, kind, make_extract(iso), u_out, out_dtype,
+                                        reinterpret_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "pid_extract launch");
+  return PID_OK;
+}
+
+pid_status pid_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, void* stream) {
+  if (!depth) return fail(PID_ERR_INVALID_ARG, "depth is NULL");
+  if (n < 1 || n > (1 << 30)) return fail(PID_ERR_INVALID_ARG, "bad n %lld", (long long)n);
+  if (!rank && !order) return PID_OK;
+  hipError_t err = pidk::launch_rank(depth, n, rank, order, reinterpret_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "pid_rank launch");
+  return PID_OK;
+}
+
+const char* pid_status_string(pid_status s) {
+  switch (s) {
+    case PID_OK: return "PID_OK";
+    case PID_ERR_INVALID_ARG: return "PID_ERR_INVALID_ARG";
+    case PID_ERR_UNSUPPORTED: return "PID_ERR_UNSUPPORTED";
+    case PID_ERR_WORKSPACE_TOO_SMALL: return "PID_ERR_WORKSPACE_TOO_SMALL";
+    case PID_ERR_DEVICE: return "PID_ERR_DEVICE";
+    case PID_ERR_VALUE_RANGE: return "PID_ERR_VALUE_RANGE";
+    case PID_ERR_OVER_BUDGET: return "PID_ERR_OVER_BUDGET";
+    case PID_ERR_CANCELLED: return "PID_ERR_CANCELLED";
+    case PID_ERR_INTERNAL: return "PID_ERR_INTERNAL";
+    default: return "PID_ERR_UNKNOWN";
+  }
+}
+
+const char* pid_last_error(void) { return g_last_error.c_str(); }
+
+int pid_abi_version(void) { return 1; }
+
+}  // extern "C"
+
+// Used by the server to record its own errors in the calling thread's slot.
+namespace pidapi {
+pid_status set_error(pid_status s, const char* msg) { return fail(s, "%s", msg); }
+}  // namespace pidapi

@@ -1,0 +1,147 @@
+// Device-side helpers shared by the PID kernels for gfx950 (CDNA4):
+// element types, fuzzy extraction of membership probabilities (Sec. 3.5),
+// vector loads and 64-lane wavefront reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pidk {
+
+typedef _Float16 f16;
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef int intx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Stored bf16 is handled as raw 16-bit patterns.
+struct bf16_t { uint16_t bits; };
+
+enum Mode { MODE_NONE = 0, MODE_GAUSS = 1, MODE_STEP = 2 };
+
+// Parameters of the isovalue model, prepared on the host.
+//   GAUSS: u = 0.5 * erfc((f - c) * a) with a = -side / (sigma * sqrt(2)),
+//          i.e. u = Phi(side * (f - c) / sigma).
+//   STEP:  u = [side * (f - c) > 0].  For values that widen exactly to float,
+//          f > c  <=>  f > c_dn  (c_dn = largest float <= c) and
+//          f < c  <=>  f < c_up  (c_up = smallest float >= c).
+struct Extract {
+  int side;
+  float cf, af;
+  float c_dn, c_up;
+  double cd, ad;
+};
+
+__device__ __forceinline__ float to_float(float v) { return v; }
+__device__ __forceinline__ float to_float(f16 v) { return (float)v; }
+__device__ __forceinline__ float to_float(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+__device__ __forceinline__ float to_float(uint8_t v) { return (float)v; }
+__device__ __forceinline__ float to_float(double v) { return (float)v; }
+
+__device__ __forceinline__ double to_double(double v) { return v; }
+template <typename T>
+__device__ __forceinline__ double to_double(T v) { return (double)to_float(v); }
+
+// Membership probability in float from a stored value (all input types but
+// double; doubles use extract_d).
+template <int MODE, typename T>
+__device__ __forceinline__ float extract_f(T raw, const Extract& e) {
+  float f = to_float(raw);
+  if constexpr (MODE == MODE_NONE) {
+    return f;
+  } else if constexpr (MODE == MODE_GAUSS) {
+    return 0.5f * erfcf((f - e.cf) * e.af);
+  } else {
+    return (e.side > 0) ? (f > e.c_dn ? 1.0f : 0.0f) : (f < e.c_up ? 1.0f : 0.0f);
+  }
+}
+
+template <int MODE, typename T>
+__device__ __forceinline__ double extract_d(T raw, const Extract& e) {
+  double f = to_double(raw);
+  if constexpr (MODE == MODE_NONE) {
+    return f;
+  } else if constexpr (MODE == MODE_GAUSS) {
+    return 0.5 * erfc((f - e.cd) * e.ad);
+  } else {
+    return (e.side > 0) ? (f > e.cd ? 1.0 : 0.0) : (f < e.cd ? 1.0 : 0.0);
+  }
+}
+
+// Binary decision as an integer (STEP on fields, or U8 masks with MODE_NONE).
+template <int MODE, typename T>
+__device__ __forceinline__ int extract_bit(T raw, const Extract& e) {
+  if constexpr (MODE == MODE_STEP) {
+    if constexpr (sizeof(T) == 8) {
+      double f = to_double(raw);
+      return (e.side > 0) ? (f > e.cd) : (f < e.cd);
+    } else {
+      float f = to_float(raw);
+      return (e.side > 0) ? (f > e.c_dn) : (f < e.c_up);
+    }
+  } else {
+    return (int)to_float(raw);
+  }
+}
+
+// 16-byte vector of stored elements.
+template <typename T>
+struct Vec16 {
+  static constexpr int N = 16 / sizeof(T);
+  T v[N];
+};
+
+template <typename T>
+__device__ __forceinline__ Vec16<T> load16(const T* p) {
+  uint4 r = *reinterpret_cast<const uint4*>(p);
+  return __builtin_bit_cast(Vec16<T>, r);
+}
+
+template <typename T>
+__device__ __forceinline__ Vec16<T> load16_nt(const T* p) {
+  u32x4 r = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  return __builtin_bit_cast(Vec16<T>, r);
+}
+
+// Element-wise guarded load of up to Vec16<T>::N values starting at index x0
+// of a row with m valid entries; missing entries read as zero bits.
+template <typename T>
+__device__ __forceinline__ Vec16<T> load16_guarded(const T* row, int64_t x0, int64_t m) {
+  Vec16<T> out{};
+#pragma unroll
+  for (int p = 0; p < Vec16<T>::N; ++p)
+    if (x0 + p < m) out.v[p] = row[x0 + p];
+  return out;
+}
+
+// ---- wavefront (64-lane) sums; fixed butterfly order => deterministic ----
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---- float -> 16-bit conversions (round to nearest even) ----
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
+  // Round-to-nearest-even on the upper 16 bits; inputs here are finite
+  // probabilities (NaN is not a valid membership value).
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+}  // namespace pidk

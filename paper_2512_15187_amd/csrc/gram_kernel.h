@@ -1,0 +1,411 @@
+// Gram kernel template for the all-pairs PID numerators (see k_gram.hip for
+// the algorithm); included by the per-input-type translation units.
+#pragma once
+#include "device_common.h"
+#include "pid_internal.h"
+#include "pid_timing.h"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace pidk {
+
+// MFMA input flavours
+enum MType { MT_F16 = 0, MT_BF16 = 1, MT_BF16X3 = 2, MT_I8 = 3, MT_F32 = 4, MT_F64 = 5 };
+
+template <int MT> struct MTraits;
+template <> struct MTraits<MT_F16>   { using E = f16;      static constexpr int EB = 2; static constexpr int KK = 16; static constexpr int PLANES = 1; };
+template <> struct MTraits<MT_BF16>  { using E = uint16_t; static constexpr int EB = 2; static constexpr int KK = 16; static constexpr int PLANES = 1; };
+template <> struct MTraits<MT_BF16X3>{ using E = uint16_t; static constexpr int EB = 2; static constexpr int KK = 16; static constexpr int PLANES = 2; };
+template <> struct MTraits<MT_I8>    { using E = int8_t;   static constexpr int EB = 1; static constexpr int KK = 32; static constexpr int PLANES = 1; };
+template <> struct MTraits<MT_F32>   { using E = float;    static constexpr int EB = 4; static constexpr int KK = 4;  static constexpr int PLANES = 1; };
+template <> struct MTraits<MT_F64>   { using E = double;   static constexpr int EB = 8; static constexpr int KK = 4;  static constexpr int PLANES = 1; };
+
+// Store NB bytes (NB a multiple of 4, at least 4-byte aligned destination) to
+// LDS with the widest aligned stores the size allows.
+template <int NB>
+__device__ __forceinline__ void store_lds(unsigned char* dst, const void* src) {
+  const unsigned char* s8 = reinterpret_cast<const unsigned char*>(src);
+  if constexpr (NB % 16 == 0) {
+#pragma unroll
+    for (int o = 0; o < NB; o += 16) {
+      uint4 v;
+      __builtin_memcpy(&v, s8 + o, 16);
+      *reinterpret_cast<uint4*>(dst + o) = v;
+    }
+  } else if constexpr (NB % 8 == 0) {
+#pragma unroll
+    for (int o = 0; o < NB; o += 8) {
+      uint2 v;
+      __builtin_memcpy(&v, s8 + o, 8);
+      *reinterpret_cast<uint2*>(dst + o) = v;
+    }
+  } else {
+#pragma unroll
+    for (int o = 0; o < NB; o += 4) {
+      uint32_t v;
+      __builtin_memcpy(&v, s8 + o, 4);
+      *reinterpret_cast<uint32_t*>(dst + o) = v;
+    }
+  }
+}
+
+struct GramArgs {
+  const void* U;
+  int64_t ld;
+  int n;
+  int64_t m;
+  const float* w;
+  Extract ex;
+  int nbt;             // 32-row blocks covering n
+  int sb;              // row blocks per super-block (<= 8)
+  int nsuper;          // super-blocks
+  int ntiles_super;    // super-tiles
+  int np;              // packed upper sub-tiles
+  int nsplit;
+  int64_t slabs;       // total slabs
+  int64_t slabs_per_split;
+  int vec;             // rows are 16-byte aligned
+  void* part;          // [nsplit][np][1024] (float / int / double)
+  double* part_mass;   // [nsplit][n]
+};
+
+// Super-tile index -> (I, J), I <= J, column-major over J.
+__device__ __forceinline__ void super_ij(int t, int& I, int& J) {
+  int j = 0;
+  while ((j + 1) * (j + 2) / 2 <= t) ++j;
+  J = j;
+  I = t - j * (j + 1) / 2;
+}
+
+template <typename Tin, int MT, int MODE, int MAXT, int CPR, int CH>
+__global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
+  const bool WEIGHTED = a.w != nullptr;
+  const bool VEC = a.vec != 0;
+  using TR = MTraits<MT>;
+  using E = typename TR::E;
+  constexpr int EPC = 16 / sizeof(Tin);          // elements per 16-byte chunk
+  constexpr int KS = CPR * EPC;                  // points per slab
+  constexpr int ROWB = KS * TR::EB + 16;         // LDS row stride in bytes (padded)
+  constexpr bool IS_MFMA = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3 || MT == MT_I8);
+  constexpr bool BIN = (MT == MT_I8);
+  using AccE = typename std::conditional<MT == MT_F64, double, float>::type;
+  extern __shared__ __align__(16) unsigned char lds[];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+
+  // --- XCD-aware decode of the block index
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int q = b >> 3;
+  const int st = q % a.ntiles_super;
+  const int split = (q / a.ntiles_super) * 8 + xcd;
+  int SI, SJ;
+  super_ij(st, SI, SJ);
+  const bool diag = (SI == SJ);
+  const int na = min(a.sb, a.nbt - a.sb * SI);   // row blocks on the I side
+  const int nb = min(a.sb, a.nbt - a.sb * SJ);   // row blocks on the J side
+  const int rowsI = 32 * na;
+  const int rows = diag ? rowsI : rowsI + 32 * nb;
+  const int PLANE = rows * ROWB;                 // bytes of one LDS plane
+
+  // --- this wave's sub-tiles
+  const int T = diag ? na * (na + 1) / 2 : na * nb;
+  const int t0 = (wave * T) / 8, t1 = ((wave + 1) * T) / 8;
+  const int nt = t1 - t0;
+  int ir[MAXT], ic[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    int k = min(t0 + t, T - 1);
+    if (diag) {
+      int c = 0;
+      while ((c + 1) * (c + 2) / 2 <= k) ++c;
+      ic[t] = c;
+      ir[t] = k - c * (c + 1) / 2;
+    } else {
+      ir[t] = k / nb;
+      ic[t] = k % nb;
+    }
+  }
+
+  // --- K range of this split
+  const int64_t s_begin = min((int64_t)split * a.slabs_per_split, a.slabs);
+  const int64_t s_end = min(s_begin + a.slabs_per_split, a.slabs);
+
+  // --- loader geometry: chunk q = tid + 512*ci -> row tid/CPR + (512/CPR)*ci, column tid%CPR
+  const int ccol = tid % CPR;
+  const int crow0 = tid / CPR;
+  constexpr int RSTEP = 512 / CPR;
+  const Tin* U = reinterpret_cast<const Tin*>(a.U);
+  auto grow = [&](int lrow) -> int {
+    return (lrow < rowsI) ? (32 * a.sb * SI + lrow) : (32 * a.sb * SJ + lrow - rowsI);
+  };
+
+  Vec16<Tin> pre[CH];
+  auto load_slab = [&](int64_t s) {
+    const int64_t x0 = s * KS + (int64_t)ccol * EPC;
+    const bool full = (x0 + EPC <= a.m);
+#pragma unroll
+    for (int ci = 0; ci < CH; ++ci) {
+      const int lr = crow0 + RSTEP * ci;
+      const int gr = grow(lr);
+      if (lr < rows && gr < a.n) {
+        const Tin* p = U + (int64_t)gr * a.ld;
+        if (VEC && full) pre[ci] = load16(p + x0);
+        else pre[ci] = load16_guarded(p, x0, a.m);
+      } else {
+        pre[ci] = Vec16<Tin>{};
+      }
+    }
+  };
+
+  // masses (diagonal super-tiles only): one accumulator per chunk slot
+  double macc[CH];
+#pragma unroll
+  for (int ci = 0; ci < CH; ++ci) macc[ci] = 0.0;
+
+  auto store_slab = [&](int64_t s) {
+    const int64_t x0 = s * KS + (int64_t)ccol * EPC;
+    const bool full = (x0 + EPC <= a.m);
+    float wv[EPC], sw[EPC];
+    if (WEIGHTED) {
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) {
+        wv[e] = (x0 + e < a.m) ? a.w[x0 + e] : 0.0f;
+        sw[e] = sqrtf(wv[e]);
+      }
+    }
+#pragma unroll
+    for (int ci = 0; ci < CH; ++ci) {
+      const int lr = crow0 + RSTEP * ci;
+      if (lr >= rows) continue;
+      const bool rvalid = grow(lr) < a.n;
+      unsigned char* dst = lds + (size_t)lr * ROWB + (size_t)ccol * EPC * TR::EB;
+      if constexpr (BIN) {
+        int8_t o[EPC];
+        int cnt = 0;
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+          int bit = rvalid ? extract_bit<MODE>(pre[ci].v[e], a.ex) : 0;
+          if (!full) bit = (x0 + e < a.m) ? bit : 0;
+          o[e] = (int8_t)bit;
+          cnt += bit;
+        }
+        macc[ci] += (double)cnt;
+        store_lds<EPC>(dst, o);
+      } else {
+        AccE uv[EPC];
+        AccE msum = AccE(0);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+          AccE u;
+          if constexpr (MT == MT_F64 || sizeof(Tin) == 8) u = (AccE)extract_d<MODE>(pre[ci].v[e], a.ex);
+          else u = (AccE)extract_f<MODE>(pre[ci].v[e], a.ex);
+          if (!rvalid) u = AccE(0);
+          if (MODE != MODE_NONE && !full) u = (x0 + e < a.m) ? u : AccE(0);
+          if (WEIGHTED) { msum += (AccE)wv[e] * u; uv[e] = (AccE)sw[e] * u; }
+          else { msum += u; uv[e] = u; }
+        }
+        macc[ci] += (double)msum;
+        if constexpr (MT == MT_F16) {
+          f16 o[EPC];
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) o[e] = (f16)uv[e];
+          store_lds<2 * EPC>(dst, o);
+        } else if constexpr (MT == MT_BF16) {
+          uint16_t o[EPC];
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) o[e] = f32_to_bf16_bits((float)uv[e]);
+          store_lds<2 * EPC>(dst, o);
+        } else if constexpr (MT == MT_BF16X3) {
+          uint16_t hi[EPC], lo[EPC];
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) {
+            float v = (float)uv[e];
+            hi[e] = f32_to_bf16_bits(v);
+            lo[e] = f32_to_bf16_bits(v - bf16_bits_to_f32(hi[e]));
+          }
+          store_lds<2 * EPC>(dst, hi);
+          store_lds<2 * EPC>(dst + PLANE, lo);
+        } else {
+          store_lds<(int)sizeof(AccE) * EPC>(dst, uv);
+        }
+      }
+    }
+  };
+
+  // --- accumulators
+  constexpr int ACCN = IS_MFMA ? 16 : 16;
+  using AccV = typename std::conditional<BIN, intx16, floatx16>::type;
+  AccV acc[MAXT];
+  AccE vacc[IS_MFMA ? 1 : MAXT][IS_MFMA ? 1 : ACCN];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    if constexpr (IS_MFMA) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[t][r] = 0;
+    } else {
+#pragma unroll
+      for (int r = 0; r < ACCN; ++r) vacc[t][r] = AccE(0);
+    }
+  }
+
+  const int jrow_base = diag ? 0 : rowsI;  // LDS row of J-side block 0
+
+  auto compute_slab = [&]() {
+    if constexpr (IS_MFMA) {
+      constexpr int KSTEPS = KS / TR::KK;
+      constexpr int FE = 16 / TR::EB;   // elements per lane per fragment (16 bytes)
+#pragma unroll
+      for (int kk = 0; kk < KSTEPS; ++kk) {
+        const int koff = kk * TR::KK + (lane >> 5) * FE;   // element offset in the row
+        uint4 fa[TR::PLANES], fb[TR::PLANES];
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+          if (t < nt) {
+            const bool newa = (t == 0) || (ir[t] != ir[t - 1]);
+            const bool newb = (t == 0) || (ic[t] != ic[t - 1]);
+            if (newa) {
+              const unsigned char* pa = lds + (size_t)(ir[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
+              fa[0] = *reinterpret_cast<const uint4*>(pa);
+              if constexpr (TR::PLANES == 2) fa[1] = *reinterpret_cast<const uint4*>(pa + PLANE);
+            }
+            if (newb) {
+              const unsigned char* pb = lds + (size_t)(jrow_base + ic[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
+              fb[0] = *reinterpret_cast<const uint4*>(pb);
+              if constexpr (TR::PLANES == 2) fb[1] = *reinterpret_cast<const uint4*>(pb + PLANE);
+            }
+            if constexpr (MT == MT_F16) {
+              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, fa[0]),
+                                                               __builtin_bit_cast(half8, fb[0]), acc[t], 0, 0, 0);
+            } else if constexpr (MT == MT_BF16) {
+              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
+                                                                __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
+            } else if constexpr (MT == MT_BF16X3) {
+              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
+                                                                __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
+              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
+                                                                __builtin_bit_cast(bf16x8, fb[1]), acc[t], 0, 0, 0);
+              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[1]),
+                                                                __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
+            } else {
+              acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(intx4, fa[0]),
+                                                              __builtin_bit_cast(intx4, fb[0]), acc[t], 0, 0, 0);
+            }
+          }
+        }
+      }
+    } else {
+      // Vector FMA: lane owns a 4x4 block of each 32x32 sub-tile
+      // (rows 4*(lane/8) .. +3, cols 4*(lane%8) .. +3).
+      const int rr = (lane >> 3) * 4, cc = (lane & 7) * 4;
+#pragma unroll 1
+      for (int k = 0; k < KS; k += 4) {
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+          if (t < nt) {
+            AccE av[4][4], bv[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const AccE* pa = reinterpret_cast<const AccE*>(lds + (size_t)(ir[t] * 32 + rr + i) * ROWB) + k;
+              const AccE* pb = reinterpret_cast<const AccE*>(lds + (size_t)(jrow_base + ic[t] * 32 + cc + i) * ROWB) + k;
+#pragma unroll
+              for (int kk = 0; kk < 4; ++kk) { av[i][kk] = pa[kk]; bv[i][kk] = pb[kk]; }
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) vacc[t][i * 4 + j] += av[i][kk] * bv[j][kk];
+          }
+        }
+      }
+    }
+  };
+
+  // --- main loop: registers hold slab s+1 while slab s is multiplied
+  if (s_begin < s_end) load_slab(s_begin);
+  for (int64_t s = s_begin; s < s_end; ++s) {
+    store_slab(s);
+    __syncthreads();
+    if (s + 1 < s_end) load_slab(s + 1);
+    compute_slab();
+    __syncthreads();
+  }
+
+  // --- partial sub-tiles
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    if (t < nt) {
+      const int R = a.sb * SI + ir[t], C = a.sb * SJ + ic[t];
+      const size_t pidx = ((size_t)split * a.np + (size_t)(C * (C + 1) / 2 + R)) * 1024;
+      if constexpr (IS_MFMA) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int j = lane & 31;
+          if constexpr (BIN) reinterpret_cast<int*>(a.part)[pidx + i * 32 + j] = acc[t][r];
+          else reinterpret_cast<float*>(a.part)[pidx + i * 32 + j] = acc[t][r];
+        }
+      } else {
+        const int rr = (lane >> 3) * 4, cc = (lane & 7) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            reinterpret_cast<AccE*>(a.part)[pidx + (rr + i) * 32 + cc + j] = vacc[t][i * 4 + j];
+      }
+    }
+  }
+
+  // --- partial masses (rows of the I side of diagonal super-tiles)
+  if (diag) {
+#pragma unroll
+    for (int ci = 0; ci < CH; ++ci) {
+      double v = macc[ci];
+#pragma unroll
+      for (int o = CPR / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+      const int lr = crow0 + RSTEP * ci;
+      const int gr = 32 * a.sb * SI + lr;
+      if (ccol == 0 && lr < rowsI && gr < a.n) a.part_mass[(size_t)split * a.n + gr] = v;
+    }
+  }
+}
+
+
+// Launch one instantiation; the caller has checked that the combination is
+// supported.  maxt: register tiles per wave (5 for one diagonal super-tile of
+// 5..8 row blocks, else 2).
+template <typename Tin, int MT, int MODE>
+void launch_gram_t(const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st) {
+  constexpr int EB = sizeof(Tin);
+  constexpr int EPC = 16 / EB;
+  constexpr int MB = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) ? 2 : (MT == MT_I8 ? 1 : (MT == MT_F32 ? 4 : 8));
+  constexpr int CPR = (16 * EPC * MB <= 256) ? 16 : ((8 * EPC * MB <= 256) ? 8 : ((4 * EPC * MB <= 256) ? 4 : 2));
+  constexpr int CH = (256 * CPR / 512) > 0 ? 256 * CPR / 512 : 1;   // up to 256 rows per workgroup
+  if (maxt > 2) {
+    auto k = gram_kernel<Tin, MT, MODE, 5, CPR, CH>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    KernelTimer tm("gram", st);
+    hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
+  } else {
+    auto k = gram_kernel<Tin, MT, MODE, 2, CPR, CH>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    KernelTimer tm("gram", st);
+    hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
+  }
+}
+
+// Per-input-type dispatchers (one translation unit each); return false when
+// the (MFMA type, extraction mode) combination is not provided.
+bool gram_dispatch_f32(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_f16(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_bf16(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_f64(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_u8(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
+bool gram_supported(int dtype, int mt, int mode);
+
+}  // namespace pidk

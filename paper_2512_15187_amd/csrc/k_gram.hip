@@ -1,0 +1,282 @@
+// All-pairs PID numerators: G_ij = sum_x w_x u_i(x) u_j(x)  (Sec. 3.2 / 3.4).
+//
+// The inclusion numerators of every ordered pair are one symmetric Gram
+// product of the N x M membership matrix (each column scaled by sqrt(w_x)),
+// so only the upper triangle of 32x32 sub-tiles is computed.  The reduction
+// dimension M (grid points) is split across workgroups (split-K); every
+// workgroup streams its range of points in slabs: the slab is loaded from HBM
+// with 16-byte loads into registers one slab ahead, run through the isovalue
+// model, scaled, converted to the MFMA input type and stored to LDS, where the
+// waves read 32-row fragments for their sub-tiles.  Masses m_i are summed in
+// the same loader (FP32 per chunk, FP64 across slabs) by the workgroups of the
+// diagonal super-tiles.  Partial sums (FP32, or INT32 for binary input) are
+// written per split and reduced in a fixed order in FP64 by gram_reduce.
+//
+// Rows are grouped in super-blocks: one block of up to 8 row blocks when
+// N <= 256, otherwise blocks of 4 row blocks (128 rows); a workgroup owns one
+// super-tile (I <= J, at most 256 rows) and one split.  Sub-tiles of a super-tile are
+// dealt out to 8 waves in contiguous runs (column-major on the diagonal,
+// row-major off it) so that consecutive sub-tiles of a wave share a fragment.
+// Workgroups are dispatched round-robin over the 8 XCDs; block b is mapped so
+// that the super-tiles of one split land on the same XCD and share its L2.
+#include "gram_kernel.h"
+#include "pid_timing.h"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace pidk {
+
+// ---------------------------------------------------------------------------
+// Fixed-order FP64 reduction of the split partials into the full symmetric
+// G (N x N, row-major) and the masses.
+template <typename PT>
+__global__ __launch_bounds__(256) void gram_reduce(const PT* __restrict__ part,
+                                                   const double* __restrict__ part_mass, int nsplit,
+                                                   int np, int n, double* __restrict__ G,
+                                                   double* __restrict__ mass) {
+  const int64_t tot = (int64_t)np * 1024;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot + n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < tot) {
+      const int p = (int)(e >> 10);
+      const int ij = (int)(e & 1023);
+      int C = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+      while (C * (C + 1) / 2 > p) --C;
+      while ((C + 1) * (C + 2) / 2 <= p) ++C;
+      const int R = p - C * (C + 1) / 2;
+      const int i = R * 32 + (ij >> 5), j = C * 32 + (ij & 31);
+      if (i >= n || j >= n) continue;
+      if (R == C && i > j) continue;   // diagonal sub-tile: take the upper copy
+      double s = 0.0;
+      for (int k = 0; k < nsplit; ++k) s += (double)part[((size_t)k * np) * 1024 + e];
+      G[(size_t)i * n + j] = s;
+      G[(size_t)j * n + i] = s;
+    } else {
+      const int i = (int)(e - tot);
+      double s = 0.0;
+      for (int k = 0; k < nsplit; ++k) s += part_mass[(size_t)k * n + i];
+      mass[i] = s;
+    }
+  }
+}
+
+// Inclusion matrix P_ij = G_ij / m_i (0 when m_i = 0); one block per row.
+__global__ __launch_bounds__(256) void pairs_inclusion(const double* __restrict__ G,
+                                                       const double* __restrict__ mass, int n,
+                                                       double* __restrict__ P) {
+  const int i = blockIdx.x;
+  const double mi = mass[i];
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+    P[(size_t)i * n + j] = (mi > 0.0) ? G[(size_t)i * n + j] / mi : 0.0;
+}
+
+// Depths, one thread per member, sums in ascending j (the fixed order that
+// makes binary results bitwise reproducible):
+//   IN_in(i)  = S_i / (N m_i),  S_i = sum_j G_ij
+//   IN_out(i) = (sum_j G_ji / m_j) / N   (terms with m_j = 0 are 0)
+__global__ __launch_bounds__(256) void pairs_depths(const double* __restrict__ G,
+                                                    const double* __restrict__ mass, int n,
+                                                    double* __restrict__ m_out,
+                                                    double* __restrict__ in_in,
+                                                    double* __restrict__ in_out,
+                                                    double* __restrict__ depth) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double S = 0.0, O = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double g = G[(size_t)j * n + i];   // = G_ij (symmetric); coalesced over i
+    S = S + g;
+    const double mj = mass[j];
+    if (mj > 0.0) O = O + g / mj;
+  }
+  const double mi = mass[i];
+  const double ii = (mi > 0.0) ? S / ((double)n * mi) : 0.0;
+  const double oo = O / (double)n;
+  if (m_out) m_out[i] = mi;
+  if (in_in) in_in[i] = ii;
+  if (in_out) in_out[i] = oo;
+  if (depth) depth[i] = ii < oo ? ii : oo;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+static int elem_bytes_g(int dtype) {
+  switch (dtype) {
+    case PID_F64: return 8;
+    case PID_F32: return 4;
+    case PID_F16: case PID_BF16: return 2;
+    default: return 1;
+  }
+}
+
+static int mtype_of(int scheme) {
+  switch (scheme) {
+    case SCH_F16: return MT_F16;
+    case SCH_BF16: return MT_BF16;
+    case SCH_BF16_SPLIT: return MT_BF16X3;
+    case SCH_I8: return MT_I8;
+    case SCH_F32: return MT_F32;
+    default: return MT_F64;
+  }
+}
+
+static int mt_bytes(int mt) {
+  switch (mt) {
+    case MT_F16: case MT_BF16: case MT_BF16X3: return 2;
+    case MT_I8: return 1;
+    case MT_F32: return 4;
+    default: return 8;
+  }
+}
+
+// chunks (16 B of input) per row per slab
+static int cpr_of(int eb_in, int mt) {
+  // slab rows of at most 256 bytes in LDS per plane, and of 256 bytes of input
+  int cpr = 16;
+  const int epc = 16 / eb_in;
+  while (cpr > 1 && cpr * epc * mt_bytes(mt) > 256) cpr >>= 1;
+  return cpr;
+}
+
+// (input dtype, MFMA type, extraction mode) combinations that are built.
+bool gram_supported(int dtype, int mt, int mode) {
+  switch (dtype) {
+    case PID_F32:
+      if (mt == MT_I8) return mode == MODE_STEP;
+      if (mt == MT_F16 || mt == MT_F32) return true;
+      return mode != MODE_STEP;                       // BF16, BF16x3, F64
+    case PID_F16:
+      if (mt == MT_I8) return mode == MODE_STEP;
+      if (mt == MT_F16) return true;
+      if (mt == MT_F32) return mode != MODE_STEP;
+      if (mt == MT_F64) return mode == MODE_NONE;
+      return false;
+    case PID_BF16:
+      return (mt == MT_BF16 || mt == MT_F32) && mode == MODE_NONE;
+    case PID_F64:
+      if (mt == MT_F64) return true;
+      return (mt == MT_F32 || mt == MT_F16) && mode == MODE_NONE;
+    case PID_U8:
+      if (mt == MT_I8) return mode == MODE_NONE || mode == MODE_STEP;
+      return (mt == MT_F16 || mt == MT_F32) && mode == MODE_NONE;
+    default:
+      return false;
+  }
+}
+
+bool pairs_supported(int dtype, int iso_kind, int scheme) {
+  const int mode = iso_kind == PID_ISO_GAUSSIAN ? MODE_GAUSS : (iso_kind == PID_ISO_STEP ? MODE_STEP : MODE_NONE);
+  return gram_supported(dtype, mtype_of(scheme), mode);
+}
+
+PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted, int scheme) {
+  PairsPlan p{};
+  p.scheme = scheme;
+  const int mt = mtype_of(scheme);
+  const int eb = elem_bytes_g(dtype);
+  p.nbt = (int)((n + 31) / 32);
+  // one diagonal super-tile of up to 8 row blocks when N <= 256, else
+  // super-blocks of 4 row blocks (128 rows) and all their pairs I <= J
+  p.sb = (p.nbt <= 8) ? p.nbt : 4;
+  p.nsuper = (p.nbt + p.sb - 1) / p.sb;
+  p.ntiles_super = p.nsuper * (p.nsuper + 1) / 2;
+  p.np = p.nbt * (p.nbt + 1) / 2;
+  const int tmax = (p.nsuper > 1) ? p.sb * p.sb : p.sb * (p.sb + 1) / 2;
+  p.maxt = ((tmax + 7) / 8 <= 2) ? 2 : 5;
+  const int cpr = cpr_of(eb, mt);
+  p.ks = cpr * (16 / eb);
+  p.slabs = (m + p.ks - 1) / p.ks;
+  // splits: about one workgroup of 8 waves per CU, at least 2 slabs per split
+  // and at most 16384 points of FP32 accumulation per split.
+  const int cus = device_cu_count();
+  int64_t want = std::max<int64_t>(1, (int64_t)cus / p.ntiles_super);
+  want = std::min<int64_t>(want, std::max<int64_t>(1, p.slabs / 2));
+  const int64_t min_splits = (m + 16383) / 16384;
+  if (mt != MT_I8 && mt != MT_F64) want = std::max(want, min_splits);
+  p.nsplit = (int)(((want + 7) / 8) * 8);
+  p.slabs_per_split = (p.slabs + p.nsplit - 1) / p.nsplit;
+  const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;
+  const int rowb = p.ks * mt_bytes(mt) + 16;
+  const int planes = (mt == MT_BF16X3) ? 2 : 1;
+  p.lds_bytes = (size_t)planes * rows * rowb;
+  p.part_elem = (mt == MT_F64) ? 8 : 4;
+  (void)iso_kind; (void)weighted;
+  return p;
+}
+
+size_t pairs_workspace(const PairsPlan& p, int64_t n) {
+  Carve c(nullptr);
+  c.take<char>((size_t)p.nsplit * p.np * 1024 * p.part_elem);
+  c.take<double>((size_t)p.nsplit * n);   // partial masses
+  c.take<double>((size_t)n * n);          // G
+  c.take<double>((size_t)n);              // masses
+  return c.off + 256;
+}
+
+hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,
+                            const ExtractHost& exh, const pid_out& out, void* ws, hipStream_t st) {
+  Carve c(ws);
+  GramArgs ga{};
+  ga.U = e.data;
+  ga.ld = e.ld;
+  ga.n = (int)e.n;
+  ga.m = e.m;
+  ga.w = e.weights;
+  ga.ex = __builtin_bit_cast(Extract, exh);
+  ga.nbt = p.nbt;
+  ga.sb = p.sb;
+  ga.nsuper = p.nsuper;
+  ga.ntiles_super = p.ntiles_super;
+  ga.np = p.np;
+  ga.nsplit = p.nsplit;
+  ga.slabs = p.slabs;
+  ga.slabs_per_split = p.slabs_per_split;
+  ga.part = c.take<char>((size_t)p.nsplit * p.np * 1024 * p.part_elem);
+  ga.part_mass = c.take<double>((size_t)p.nsplit * e.n);
+  double* G = c.take<double>((size_t)e.n * e.n);
+  double* mass = c.take<double>((size_t)e.n);
+  const int eb = elem_bytes_g(e.dtype);
+  ga.vec = (((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
+            (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0)) ? 1 : 0;
+  const int mt = mtype_of(p.scheme);
+  const int mode = iso_kind == PID_ISO_GAUSSIAN ? MODE_GAUSS : (iso_kind == PID_ISO_STEP ? MODE_STEP : MODE_NONE);
+  const int grid = p.nsplit * p.ntiles_super;
+  bool ok = false;
+  switch (e.dtype) {
+    case PID_F64: ok = gram_dispatch_f64(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
+    case PID_F32: ok = gram_dispatch_f32(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
+    case PID_F16: ok = gram_dispatch_f16(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
+    case PID_BF16: ok = gram_dispatch_bf16(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
+    default: ok = gram_dispatch_u8(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
+  }
+  if (!ok) return hipErrorNotSupported;
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int64_t work = (int64_t)p.np * 1024 + e.n;
+  const int rgrid = (int)std::min<int64_t>((work + 255) / 256, 4096);
+  {
+  KernelTimer tm("gram_reduce", st);
+  if (p.part_elem == 8)
+    hipLaunchKernelGGL(gram_reduce<double>, rgrid, 256, 0, st, (const double*)ga.part, ga.part_mass,
+                       p.nsplit, p.np, (int)e.n, G, mass);
+  else if (mtype_of(p.scheme) == MT_I8)
+    hipLaunchKernelGGL(gram_reduce<int>, rgrid, 256, 0, st, (const int*)ga.part, ga.part_mass,
+                       p.nsplit, p.np, (int)e.n, G, mass);
+  else
+    hipLaunchKernelGGL(gram_reduce<float>, rgrid, 256, 0, st, (const float*)ga.part, ga.part_mass,
+                       p.nsplit, p.np, (int)e.n, G, mass);
+  }
+  if (out.inclusion) {
+    KernelTimer tm("pairs_inclusion", st);
+    hipLaunchKernelGGL(pairs_inclusion, (int)e.n, 256, 0, st, G, mass, (int)e.n, out.inclusion);
+  }
+  KernelTimer tm("pairs_depths", st);
+  hipLaunchKernelGGL(pairs_depths, (int)((e.n + 255) / 256), 256, 0, st, G, mass, (int)e.n,
+                     out.mass, out.in_in, out.in_out, out.depth);
+  return hipGetLastError();
+}
+
+}  // namespace pidk

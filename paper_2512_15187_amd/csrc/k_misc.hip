@@ -1,0 +1,136 @@
+// Standalone extraction (Sec. 3.5), ranks by depth (Sec. 5.1) and the opt-in
+// value-range check of the inputs.
+#include "device_common.h"
+#include "pid_internal.h"
+#include "pid_timing.h"
+
+#include <algorithm>
+
+namespace pidk {
+
+template <typename T, int MODE, typename OT>
+__global__ __launch_bounds__(256) void extract_kernel(const T* __restrict__ U, int64_t ld, int64_t n,
+                                                      int64_t m, Extract ex, OT* __restrict__ out) {
+  const int64_t tot = n * m;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / m, x = e - i * m;
+    const T v = U[i * ld + x];
+    if constexpr (sizeof(OT) == 8) out[e] = extract_d<MODE>(v, ex);
+    else if constexpr (sizeof(T) == 8) out[e] = (float)extract_d<MODE>(v, ex);
+    else out[e] = extract_f<MODE>(v, ex);
+  }
+}
+
+template <typename T, int MODE>
+static void launch_extract_t(const pid_ensemble& e, const Extract& ex, void* out, int odt, hipStream_t st) {
+  const int64_t tot = e.n * e.m;
+  const int grid = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+  const T* U = reinterpret_cast<const T*>(e.data);
+  if (odt == PID_F64)
+    hipLaunchKernelGGL((extract_kernel<T, MODE, double>), grid, 256, 0, st, U, e.ld, e.n, e.m, ex, (double*)out);
+  else
+    hipLaunchKernelGGL((extract_kernel<T, MODE, float>), grid, 256, 0, st, U, e.ld, e.n, e.m, ex, (float*)out);
+}
+
+template <typename T>
+static void launch_extract_m(const pid_ensemble& e, int kind, const Extract& ex, void* out, int odt, hipStream_t st) {
+  switch (kind) {
+    case PID_ISO_GAUSSIAN: launch_extract_t<T, MODE_GAUSS>(e, ex, out, odt, st); break;
+    case PID_ISO_STEP: launch_extract_t<T, MODE_STEP>(e, ex, out, odt, st); break;
+    default: launch_extract_t<T, MODE_NONE>(e, ex, out, odt, st); break;
+  }
+}
+
+hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost& exh, void* u_out,
+                          int out_dtype, hipStream_t st) {
+  Extract ex = __builtin_bit_cast(Extract, exh);
+  KernelTimer tm("extract", st);
+  switch (e.dtype) {
+    case PID_F64: launch_extract_m<double>(e, iso_kind, ex, u_out, out_dtype, st); break;
+    case PID_F32: launch_extract_m<float>(e, iso_kind, ex, u_out, out_dtype, st); break;
+    case PID_F16: launch_extract_m<f16>(e, iso_kind, ex, u_out, out_dtype, st); break;
+    case PID_BF16: launch_extract_m<bf16_t>(e, iso_kind, ex, u_out, out_dtype, st); break;
+    default: launch_extract_m<uint8_t>(e, iso_kind, ex, u_out, out_dtype, st); break;
+  }
+  return hipGetLastError();
+}
+
+// rank[i] = #{ j : d_j > d_i  or  (d_j == d_i and j < i) };  order[rank[i]] = i.
+__global__ __launch_bounds__(256) void rank_kernel(const double* __restrict__ d, int n,
+                                                   int32_t* __restrict__ rank,
+                                                   int32_t* __restrict__ order) {
+  __shared__ double tile[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double di = (i < n) ? d[i] : 0.0;
+  int r = 0;
+  for (int j0 = 0; j0 < n; j0 += 256) {
+    const int j = j0 + threadIdx.x;
+    tile[threadIdx.x] = (j < n) ? d[j] : 0.0;
+    __syncthreads();
+    const int lim = min(256, n - j0);
+    for (int k = 0; k < lim; ++k) {
+      const double dj = tile[k];
+      const int jj = j0 + k;
+      r += (dj > di) || (dj == di && jj < i);
+    }
+    __syncthreads();
+  }
+  if (i < n) {
+    if (rank) rank[i] = r;
+    if (order) order[r] = i;
+  }
+}
+
+hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st) {
+  KernelTimer tm("rank", st);
+  hipLaunchKernelGGL(rank_kernel, (int)((n + 255) / 256), 256, 0, st, depth, (int)n, rank, order);
+  return hipGetLastError();
+}
+
+// Value checks: codes 1 = probability outside [0,1] or NaN, 2 = U8 value not
+// 0/1, 3 = non-finite field value, 4 = negative or non-finite weight.
+template <typename T>
+__global__ __launch_bounds__(256) void validate_kernel(const T* __restrict__ U, int64_t ld, int64_t n,
+                                                       int64_t m, int kind, const float* __restrict__ w,
+                                                       unsigned int* __restrict__ flag) {
+  const int64_t tot = n * m;
+  unsigned int code = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / m, x = e - i * m;
+    const double v = to_double(U[i * ld + x]);
+    if constexpr (sizeof(T) == 1) {
+      if (kind == PID_ISO_NONE && !(v == 0.0 || v == 1.0)) code = 2;
+    } else {
+      if (kind == PID_ISO_NONE) {
+        if (!(v >= 0.0 && v <= 1.0)) code = 1;
+      } else if (!isfinite(v)) {
+        code = 3;
+      }
+    }
+    if (w && i == 0) {
+      const float wx = w[x];
+      if (!(wx >= 0.0f) || !isfinite(wx)) code = 4;
+    }
+  }
+  if (code) atomicMax(flag, code);
+}
+
+__global__ void zero_flag_kernel(unsigned int* flag) { *flag = 0u; }
+
+hipError_t launch_validate(const pid_ensemble& e, int iso_kind, unsigned int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(zero_flag_kernel, 1, 1, 0, st, flag);
+  const int64_t tot = e.n * e.m;
+  const int grid = (int)std::min<int64_t>((tot + 255) / 256, 16384);
+  switch (e.dtype) {
+    case PID_F64: hipLaunchKernelGGL(validate_kernel<double>, grid, 256, 0, st, (const double*)e.data, e.ld, e.n, e.m, iso_kind, e.weights, flag); break;
+    case PID_F32: hipLaunchKernelGGL(validate_kernel<float>, grid, 256, 0, st, (const float*)e.data, e.ld, e.n, e.m, iso_kind, e.weights, flag); break;
+    case PID_F16: hipLaunchKernelGGL(validate_kernel<f16>, grid, 256, 0, st, (const f16*)e.data, e.ld, e.n, e.m, iso_kind, e.weights, flag); break;
+    case PID_BF16: hipLaunchKernelGGL(validate_kernel<bf16_t>, grid, 256, 0, st, (const bf16_t*)e.data, e.ld, e.n, e.m, iso_kind, e.weights, flag); break;
+    default: hipLaunchKernelGGL(validate_kernel<uint8_t>, grid, 256, 0, st, (const uint8_t*)e.data, e.ld, e.n, e.m, iso_kind, e.weights, flag); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pidk

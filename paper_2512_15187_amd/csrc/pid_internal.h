@@ -1,0 +1,86 @@
+// Host-side interface between the C ABI (api.cpp) and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pid.h"
+
+namespace pidk {
+
+struct Extract;  // device_common.h
+
+// Host copy of the isovalue model, converted once per call.
+struct ExtractHost {
+  int side;
+  float cf, af;
+  float c_dn, c_up;
+  double cd, ad;
+};
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// ---------------------------------------------------------------- PID-mean
+struct MeanPlan {
+  int mpw;          // members per wave
+  int nwaves;       // waves per workgroup
+  int two_pass;     // 1: column sums s(x) go through memory (N too large for one pass)
+  int groups;       // member groups (grid.y) in the two-pass case
+  int64_t ntiles;   // point tiles of 64 * (16 / elem_bytes) points
+  int grid;         // workgroups along the points
+  int binary;       // exact integer arithmetic
+  size_t lds_bytes;
+};
+MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted);
+size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m);
+hipError_t launch_pid_mean(const MeanPlan& p, const pid_ensemble& e, int iso_kind,
+                           const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st);
+
+// ---------------------------------------------------------------- all-pairs
+enum Scheme { SCH_F64 = 1, SCH_F32 = 2, SCH_F16 = 3, SCH_BF16 = 4, SCH_BF16_SPLIT = 5, SCH_I8 = 6 };
+
+struct PairsPlan {
+  int scheme;
+  int nbt;          // 32-row blocks covering N
+  int sb;           // row blocks per super-block
+  int nsuper;       // super-blocks
+  int ntiles_super; // super-tiles (I <= J)
+  int np;           // upper 32x32 sub-tiles (packed)
+  int maxt;         // sub-tiles per wave (register tiles)
+  int nsplit;       // K splits (multiple of 8)
+  int64_t slabs;    // slabs of points along M
+  int64_t slabs_per_split;
+  int ks;           // points per slab
+  size_t lds_bytes;
+  int part_elem;    // bytes per partial element (4 or 8)
+};
+PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted, int scheme);
+size_t pairs_workspace(const PairsPlan& p, int64_t n);
+// True when the Gram kernel is built for this input dtype, scheme and iso kind.
+bool pairs_supported(int dtype, int iso_kind, int scheme);
+hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,
+                            const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st);
+
+// ---------------------------------------------------------------- misc
+hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, void* u_out,
+                          int out_dtype, hipStream_t st);
+hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st);
+// Writes 0 to *flag_dev when all values pass, else a nonzero code.
+hipError_t launch_validate(const pid_ensemble& e, int iso_kind, unsigned int* flag_dev, hipStream_t st);
+
+int device_cu_count();
+
+}  // namespace pidk

@@ -1,0 +1,86 @@
+"""The C-ABI library loads and exports every symbol include/pid.h declares;
+host-side argument checks reject bad input before any device work.  CPU only:
+no compute call is made."""
+import ctypes
+import os
+
+import pytest
+
+import paper_2512_15187_amd as pid
+
+
+def _lib():
+    if not os.path.exists(pid.LIB_PATH):
+        pytest.fail("libpid.so is not built (python -m paper_2512_15187_amd.build)")
+    return pid.load_library()
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib()
+    names = pid.declared_symbols()
+    expected = {"pid_workspace_size", "pid_all_pairs", "pid_mean", "pid_extract", "pid_rank",
+                "pid_server_create", "pid_submit", "pid_poll", "pid_wait", "pid_request_times",
+                "pid_server_destroy", "pid_status_string", "pid_last_error", "pid_abi_version",
+                "pid_timing_enable", "pid_timing_get"}
+    assert expected <= set(names), set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.pid_abi_version() == 1
+    assert lib.pid_status_string(5) == b"PID_ERR_VALUE_RANGE"
+
+
+def _ens(**kw):
+    e = pid.pid_ensemble(4, 10, 10, pid.PID_F32, 0, 0x1000, None)
+    for k, v in kw.items():
+        setattr(e, k, v)
+    return e
+
+
+@pytest.mark.parametrize("kw,iso,msg", [
+    (dict(n=0), None, "n must be"),
+    (dict(m=0), None, "m must be"),
+    (dict(ld=5), None, "ld"),
+    (dict(dtype=9), None, "unknown dtype"),
+    (dict(data=None), None, "data is NULL"),
+    (dict(flags=8), None, "unknown flags"),
+    ({}, pid.pid_iso(7, 1, 0.5, 0.1), "unknown iso kind"),
+    ({}, pid.pid_iso(pid.PID_ISO_GAUSSIAN, 1, 0.5, 0.0), "sigma"),
+    ({}, pid.pid_iso(pid.PID_ISO_GAUSSIAN, 3, 0.5, 0.1), "side"),
+    ({}, pid.pid_iso(pid.PID_ISO_STEP, 1, float("nan"), 0.0), "finite"),
+])
+def test_invalid_arguments_rejected_on_host(kw, iso, msg):
+    lib = _lib()
+    e = _ens(**kw)
+    i = iso if iso is not None else pid.pid_iso(0, 1, 0.0, 0.0)
+    nbytes = ctypes.c_size_t(0)
+    st = lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 0, 0, ctypes.byref(nbytes))
+    assert st == pid.PID_ERR_INVALID_ARG
+    assert msg in lib.pid_last_error().decode()
+
+
+def test_scheme_checks_on_host():
+    lib = _lib()
+    e = _ens()
+    i = pid.pid_iso(0, 1, 0.0, 0.0)
+    nbytes = ctypes.c_size_t(0)
+    # INT8 needs binary input
+    assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 0, pid.GEMM["i8"], ctypes.byref(nbytes)) \
+        == pid.PID_ERR_INVALID_ARG
+    # INT8 is exact only without weights
+    eb = _ens(dtype=pid.PID_U8, weights=0x2000)
+    assert lib.pid_workspace_size(ctypes.byref(eb), ctypes.byref(i), 0, pid.GEMM["i8"], ctypes.byref(nbytes)) \
+        == pid.PID_ERR_INVALID_ARG
+    # unknown scheme / variant
+    assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 0, 42, ctypes.byref(nbytes)) \
+        == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 3, 0, ctypes.byref(nbytes)) \
+        == pid.PID_ERR_INVALID_ARG
+    # NULL pointers
+    assert lib.pid_all_pairs(None, None, 0, None, None, 0, None) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_rank(None, 3, None, None, None) == pid.PID_ERR_INVALID_ARG
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    with pytest.raises((RuntimeError, ValueError)):
+        pid.pid_mean(torch.zeros(3, 5))

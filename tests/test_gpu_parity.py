@@ -1,0 +1,252 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle on
+seeded inputs that span several tiles and ragged tails, plus edge cases."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2512_15187_amd as pid
+import synth
+from tests.gpu_helpers import (TOL_F32, TOL_F64, TOL_MIXED, assert_bitwise, assert_close,
+                               assert_ranks, np64)
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(t):
+    return t.to(DEV)
+
+
+def _soft(n, m, seed, dtype):
+    return synth.random_soft(n, m, seed, dtype=torch.float64).to(dtype)
+
+
+def _fields(n, m, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return torch.from_numpy(rng.normal(0.5, 0.08, size=(n, m)).astype(np.float32))
+
+
+def _weights(m, seed):
+    return synth.volume_weights(m, seed)
+
+
+def _ref_input(U):
+    """Exactly the stored values, widened to float64."""
+    return U.to(torch.float64).numpy()
+
+
+TOL_OF = {"f16": TOL_MIXED, "bf16": 3e-3, "bf16_split": TOL_MIXED, "f32": TOL_F32, "f64": TOL_F64}
+
+
+# ------------------------------------------------------------------ extraction
+@pytest.mark.parametrize("side", [1, -1])
+def test_extract_gaussian_f32(side):
+    F = _fields(7, 3001, 1)
+    iso = dict(kind="gaussian", c=0.5, sigma=0.05, side=side)
+    u = pid.pid_extract(_dev(F), iso, torch.float32)
+    ref = oracle.extract(F.numpy(), iso)
+    err = np.max(np.abs(np64(u) - ref))
+    assert err < 1e-6, err
+
+
+def test_extract_step_exact_and_f64():
+    F = _fields(5, 2000, 2)
+    F[0, :10] = 0.5                      # ties at the isovalue are outside
+    for side in (1, -1):
+        iso = dict(kind="step", c=0.5, side=side)
+        u = pid.pid_extract(_dev(F), iso, torch.float32)
+        assert (np64(u) == oracle.extract(F.numpy(), iso)).all()
+    F64 = F.to(torch.float64)
+    iso = dict(kind="gaussian", c=0.5, sigma=0.05, side=1)
+    u = pid.pid_extract(_dev(F64), iso, torch.float64)
+    assert np.max(np.abs(np64(u) - oracle.extract(F64.numpy(), iso))) < 1e-15
+
+
+# ------------------------------------------------------------------ PID-mean
+MEAN_CASES = [
+    # (name, n, m, dtype, weighted, tol)
+    ("f32_w", 37, 5003, torch.float32, True, TOL_MIXED),
+    ("f16", 64, 8191, torch.float16, False, TOL_MIXED),
+    ("f16_w", 64, 8192 + 513, torch.float16, True, TOL_MIXED),
+    ("bf16", 20, 3000, torch.bfloat16, False, TOL_MIXED),
+    ("f64", 50, 4097, torch.float64, False, TOL_F64),
+    ("f64_w", 9, 777, torch.float64, True, TOL_F64),
+    ("f32_n1", 1, 999, torch.float32, False, TOL_MIXED),
+    ("f32_m1", 6, 1, torch.float32, False, TOL_MIXED),
+    ("f16_n200", 200, 4000, torch.float16, True, TOL_MIXED),
+    ("f16_twopass", 300, 4001, torch.float16, False, TOL_MIXED),
+    ("f32_twopass_w", 280, 2100, torch.float32, True, TOL_MIXED),
+]
+
+
+@pytest.mark.parametrize("name,n,m,dtype,weighted,tol", MEAN_CASES, ids=[c[0] for c in MEAN_CASES])
+def test_pid_mean_soft(name, n, m, dtype, weighted, tol):
+    U = _soft(n, m, 100 + n, dtype)
+    w = _weights(m, 5) if weighted else None
+    res = pid.pid_mean(_dev(U), None if w is None else _dev(w))
+    ref = oracle.pid_mean(_ref_input(U), None if w is None else w.numpy())
+    assert_close(res, ref, tol, label=name)
+    assert_ranks(res["rank"], ref["depth"], tol, label=name)
+
+
+def test_pid_mean_gaussian_fields():
+    F = _fields(128, 4096 + 7, 3)
+    iso = dict(kind="gaussian", c=0.5, sigma=0.05, side=1)
+    res = pid.pid_mean(_dev(F), iso=iso)
+    ref = oracle.pid_mean(oracle.extract(F.numpy(), iso))
+    assert_close(res, ref, TOL_MIXED, label="gauss")
+
+
+@pytest.mark.parametrize("n,m,kind", [(33, 3001, "step"), (70, 2000, "u8"), (5, 17, "u8"),
+                                      (300, 1500, "u8"), (260, 999, "step")])
+def test_pid_mean_binary_bitexact(n, m, kind):
+    if kind == "u8":
+        B = synth.random_binary(n, m, 7 + n)
+        res = pid.pid_mean(_dev(B))
+    else:
+        F = _fields(n, m, 8 + n)
+        iso = dict(kind="step", c=0.5, side=1)
+        res = pid.pid_mean(_dev(F), iso=iso)
+        B = torch.from_numpy(oracle.extract(F.numpy(), iso).astype(np.uint8))
+    ref = oracle.binary_pid_mean(B.numpy())
+    assert_bitwise(res, ref, keys=("in_in", "in_out", "depth", "mass"), label=f"mean-bin {kind}")
+    assert_ranks(res["rank"], ref["depth"], 0)
+
+
+# ------------------------------------------------------------------ all-pairs
+PAIR_CASES = [
+    # (n, m, dtype, weighted, scheme)
+    (5, 300, torch.float32, False, "f16"),
+    (33, 5003, torch.float32, True, "f16"),
+    (70, 2049, torch.float32, False, "bf16_split"),
+    (70, 2049, torch.float32, True, "f32"),
+    (100, 3000, torch.float32, False, "bf16"),
+    (130, 1000, torch.float64, False, "f64"),
+    (256, 4096, torch.float16, False, "f16"),
+    (230, 3333, torch.float16, True, "f16"),
+    (300, 2000, torch.float32, False, "f16"),
+    (300, 2000, torch.float32, True, "f32"),
+    (41, 1111, torch.bfloat16, False, "bf16"),
+    (1, 500, torch.float32, False, "f16"),
+    (7, 1, torch.float32, False, "f32"),
+]
+
+
+@pytest.mark.parametrize("n,m,dtype,weighted,scheme", PAIR_CASES,
+                         ids=[f"{c[0]}x{c[1]}-{str(c[2])[6:]}-{'w' if c[3] else 'u'}-{c[4]}" for c in PAIR_CASES])
+def test_all_pairs_soft(n, m, dtype, weighted, scheme):
+    U = _soft(n, m, 200 + n + m, dtype)
+    w = _weights(m, 6) if weighted else None
+    res = pid.pid_all_pairs(_dev(U), None if w is None else _dev(w), gemm=scheme)
+    ref = oracle.pid(_ref_input(U), None if w is None else w.numpy())
+    tol = TOL_OF[scheme]
+    if scheme == "bf16" and dtype == torch.bfloat16:
+        tol = TOL_MIXED          # exact BF16 inputs: only accumulation error
+    assert_close(res, ref, tol, label=f"pairs {scheme}")
+    assert_ranks(res["rank"], ref["depth"], tol, label=f"pairs {scheme}")
+
+
+@pytest.mark.parametrize("scheme", ["f16", "bf16_split", "f32"])
+def test_all_pairs_gaussian_fields(scheme):
+    F = _fields(96, 3000 + 5, 9)
+    iso = dict(kind="gaussian", c=0.5, sigma=0.05, side=-1)
+    w = _weights(3005, 4)
+    res = pid.pid_all_pairs(_dev(F), _dev(w), iso=iso, gemm=scheme)
+    ref = oracle.pid(oracle.extract(F.numpy(), iso), w.numpy())
+    assert_close(res, ref, TOL_OF[scheme], label=f"gauss {scheme}")
+
+
+@pytest.mark.parametrize("n,m,kind", [(3, 100, "u8"), (40, 5000, "u8"), (129, 3001, "step"),
+                                      (300, 1700, "u8"), (257, 2222, "step")])
+def test_all_pairs_binary_bitexact(n, m, kind):
+    if kind == "u8":
+        B = synth.random_binary(n, m, 30 + n)
+        res = pid.pid_all_pairs(_dev(B), gemm="i8")
+    else:
+        F = _fields(n, m, 31 + n)
+        iso = dict(kind="step", c=0.5, side=1)
+        res = pid.pid_all_pairs(_dev(F), iso=iso)          # AUTO -> INT8
+        B = torch.from_numpy(oracle.extract(F.numpy(), iso).astype(np.uint8))
+    ref = oracle.binary_pid(B.numpy())
+    assert_bitwise(res, ref, label=f"pairs-bin {kind}")
+    assert_ranks(res["rank"], ref["depth"], 0)
+
+
+def test_binary_reduces_to_eid_on_gpu():
+    B = synth.random_binary(12, 700, 77)
+    res = pid.pid_all_pairs(_dev(B))
+    _, _, edep = oracle.eid_sets(B.numpy())
+    assert np.max(np.abs(np64(res["depth"]) - np.array([float(v) for v in edep]))) < 1e-15
+
+
+# ------------------------------------------------------------------ edge cases
+def test_strided_and_unaligned_rows():
+    base = _soft(40, 1203, 41, torch.float32)
+    big = torch.zeros(40, 1301, dtype=torch.float32)
+    big[:, :1203] = base
+    view = _dev(big)[:, :1203]                     # ld = 1301: rows not 16-byte aligned
+    ref = oracle.pid(_ref_input(base))
+    assert_close(pid.pid_all_pairs(view, gemm="f16"), ref, TOL_MIXED, label="strided pairs")
+    refm = oracle.pid_mean(_ref_input(base))
+    assert_close(pid.pid_mean(view), refm, TOL_MIXED, label="strided mean")
+
+
+def test_zero_mass_and_identical_members():
+    U = _soft(10, 900, 51, torch.float32)
+    U[3] = 0.0
+    U[7] = U[2]
+    for scheme in ("f16", "f32"):
+        res = pid.pid_all_pairs(_dev(U), gemm=scheme)
+        ref = oracle.pid(_ref_input(U))
+        assert_close(res, ref, TOL_OF[scheme], label="zero-mass")
+        assert np64(res["depth"])[3] == 0.0 and np64(res["in_in"])[3] == 0.0
+    rm = pid.pid_mean(_dev(U))
+    assert np64(rm["depth"])[3] == 0.0
+    Z = torch.zeros(4, 64)
+    rz = pid.pid_mean(_dev(Z))
+    assert (np64(rz["depth"]) == 0).all()
+    rz = pid.pid_all_pairs(_dev(Z))
+    assert (np64(rz["depth"]) == 0).all()
+
+
+def test_deterministic_repeat():
+    U = _dev(_soft(200, 20000, 61, torch.float16))
+    a = pid.pid_all_pairs(U)
+    b = pid.pid_all_pairs(U)
+    for k in ("inclusion", "depth", "in_in", "in_out"):
+        assert torch.equal(a[k], b[k]), k
+    a = pid.pid_mean(U)
+    b = pid.pid_mean(U)
+    assert torch.equal(a["depth"], b["depth"])
+
+
+def test_validate_flag():
+    U = _soft(4, 100, 71, torch.float32)
+    U[1, 5] = 1.5
+    with pytest.raises(pid.PidError) as ei:
+        pid.pid_mean(_dev(U), validate=True)
+    assert ei.value.status == pid.PID_ERR_VALUE_RANGE
+    B = synth.random_binary(4, 100, 72)
+    B[0, 0] = 3
+    with pytest.raises(pid.PidError):
+        pid.pid_all_pairs(_dev(B), validate=True)
+    ok = pid.pid_mean(_dev(_soft(4, 100, 73, torch.float32)), validate=True)
+    assert np.isfinite(np64(ok["depth"])).all()
+
+
+def test_scheme_errors():
+    U = _dev(_soft(4, 100, 81, torch.float32))
+    with pytest.raises(pid.PidError) as ei:
+        pid.pid_all_pairs(U, gemm="i8")
+    assert ei.value.status == pid.PID_ERR_INVALID_ARG
+    with pytest.raises(pid.PidError) as ei:
+        pid.pid_all_pairs(_dev(synth.random_binary(4, 100, 3)), weights=_dev(_weights(100, 1)), gemm="i8")
+    assert ei.value.status == pid.PID_ERR_INVALID_ARG
+
+
+def test_rank_entry_point():
+    d = torch.tensor([0.5, 0.7, 0.5, 0.9, 0.1, 0.7], dtype=torch.float64)
+    rank, order = pid.pid_rank(_dev(d))
+    r, o = oracle.rank_order(d.numpy())
+    assert rank.cpu().tolist() == r.tolist() and order.cpu().tolist() == o.tolist()

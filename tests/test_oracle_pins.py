@@ -385,3 +385,11 @@ def test_generators_deterministic():
     assert U.shape == (4, 512) and w.shape == (512,) and float(w.min()) >= 0.5
     reqs = synth.serving_requests(50)
     assert all(r.arrival_s > 0 for r in reqs) and reqs == synth.serving_requests(50)
+
+
+def test_binary_float_product_is_the_integer_product():
+    B = synth.random_binary(9, 3000, 17).numpy()
+    a, b = oracle.binary_pid(B), oracle.binary_pid(B, float_product=True)
+    assert (a["gram"] == b["gram"]).all()
+    for key in ("in_in", "in_out", "depth", "inclusion"):
+        assert (a[key] == b[key]).all()
