@@ -265,9 +265,79 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
     return out
 
 
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
+
+
+def run_server(pid, torch, pool, reqs, slots, arena_bytes, t_warm):
+    """Submit ``reqs`` at their arrival times to a server with ``slots``
+    execution slots; returns per-request latencies (ms) after the warm-up."""
+    srv = pid.PidServer(arena_bytes, max_slots=slots)
+    tickets = []
+    t0 = time.perf_counter()
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if r.arrival_s > now:
+            time.sleep(r.arrival_s - now)
+        U = pool[(r.kind, r.side)][: r.n]
+        t, _ = srv.pid_submit(U, variant=r.variant)
+        tickets.append((r, t))
+    lat, t_first, t_last = [], None, 0.0
+    for r, t in tickets:
+        srv.pid_wait(t)
+        ts, tb, td = srv.pid_request_times(t)
+        if r.arrival_s >= t_warm:
+            lat.append((td - ts) * 1e3)
+            t_first = ts if t_first is None else min(t_first, ts)
+            t_last = max(t_last, td)
+        srv.release(t)
+    srv.pid_server_destroy()
+    n = len(lat)
+    return dict(requests=n, p50_ms=percentile(lat, 50), p90_ms=percentile(lat, 90),
+                p99_ms=percentile(lat, 99), mean_ms=float(sum(lat) / max(1, n)),
+                req_per_s=n / max(1e-9, t_last - t_first))
+
+
 def serve(args):
-    from serve_bench import run_serving  # noqa: E402  (kept beside this file)
-    print(json.dumps(run_serving(args)), flush=True)
+    import torch
+
+    import paper_2512_15187_amd as pid
+    import synth
+
+    dev = "cuda:0"
+    warm_s = 1.0
+    total = args.requests + int(200 * warm_s)
+    reqs = synth.serving_requests(total)
+    keys = sorted({(r.kind, r.side) for r in reqs})
+    log(f"generating the request pool: {len(keys)} (kind, side) ensembles")
+    pool = {}
+    for kind, side in keys:
+        pool[(kind, side)] = synth.serving_pool(kind, side, 512 if kind == "2d" else 128, device=dev)
+    torch.cuda.synchronize()
+    arena = 2 << 30
+    # warm the kernels once per (kind, variant)
+    for kind, side in keys[:2] + keys[-2:]:
+        pid.pid_all_pairs(pool[(kind, side)][:32])
+        pid.pid_mean(pool[(kind, side)][:32])
+    torch.cuda.synchronize()
+    log("serving with 4 slots (continuous batching)")
+    mixed = run_server(pid, torch, pool, reqs, 4, arena, warm_s)
+    log(f"  {mixed}")
+    log("serving one request at a time (1 slot)")
+    single = run_server(pid, torch, pool, reqs, 1, arena, warm_s)
+    log(f"  {single}")
+    line = {
+        "metric": METRIC, "value": mixed["p99_ms"], "unit": "ms (p99 latency)", "n_gpus": 1,
+        "steps": mixed["requests"], "warmup": int(200 * warm_s), "ms_per_step": mixed["mean_ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "serving: Poisson 200 req/s; 60% 2D (N 32..512, 128^2..1024^2), 40% 3D "
+                               "(N 16..128, 64^3..192^3), FP16 soft masks, all-pairs / PID-mean 50/50",
+                   "slots": 4, "arena_bytes": arena},
+        "serving": {"continuous_batching": mixed, "one_at_a_time": single,
+                    "p99_speedup": single["p99_ms"] / mixed["p99_ms"] if mixed["p99_ms"] else None},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -278,7 +348,7 @@ def main():
     ap.add_argument("--mode", choices=["headline", "serve"], default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--requests", type=int, default=400, help="serve mode: number of requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serve mode: timed requests (after 1 s warm-up)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PID hot path is built and timed on a single "
