@@ -117,6 +117,17 @@ __device__ __forceinline__ Vec16<T> load16_guarded(const T* row, int64_t x0, int
   return out;
 }
 
+// Hide a 16-byte register vector from common-subexpression elimination, so
+// that values derived from it are recomputed instead of kept live.
+template <typename T>
+__device__ __forceinline__ void opaque(Vec16<T>& v) {
+  uint4 q = __builtin_bit_cast(uint4, v);
+  asm volatile("" : "+v"(q.x), "+v"(q.y), "+v"(q.z), "+v"(q.w));
+  v = __builtin_bit_cast(Vec16<T>, q);
+}
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // ---- wavefront (64-lane) sums; fixed butterfly order => deterministic ----
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

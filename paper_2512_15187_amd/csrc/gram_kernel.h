@@ -94,7 +94,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = wave_id();
 
   // --- XCD-aware decode of the block index
   const int b = blockIdx.x;
@@ -143,8 +143,10 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     return (lrow < rowsI) ? (32 * a.sb * SI + lrow) : (32 * a.sb * SJ + lrow - rowsI);
   };
 
-  Vec16<Tin> pre[CH];
-  auto load_slab = [&](int64_t s) {
+  // two register buffers: slab s+1 stays in flight while slab s is stored,
+  // and the loads for slab s+2 are issued as soon as slab s left its buffer
+  Vec16<Tin> preA[CH], preB[CH];
+  auto load_slab = [&](Vec16<Tin>* pre, int64_t s) {
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
     const bool full = (x0 + EPC <= a.m);
 #pragma unroll
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 #pragma unroll
   for (int ci = 0; ci < CH; ++ci) macc[ci] = 0.0;
 
-  auto store_slab = [&](int64_t s) {
+  auto store_slab = [&](const Vec16<Tin>* pre, int64_t s) {
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
     const bool full = (x0 + EPC <= a.m);
     float wv[EPC], sw[EPC];
@@ -326,14 +328,22 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     }
   };
 
-  // --- main loop: registers hold slab s+1 while slab s is multiplied
-  if (s_begin < s_end) load_slab(s_begin);
-  for (int64_t s = s_begin; s < s_end; ++s) {
-    store_slab(s);
+  // --- main loop (unrolled by two over the register buffers)
+  if (s_begin < s_end) load_slab(preA, s_begin);
+  if (s_begin + 1 < s_end) load_slab(preB, s_begin + 1);
+  for (int64_t s = s_begin; s < s_end; s += 2) {
+    store_slab(preA, s);
     __syncthreads();
-    if (s + 1 < s_end) load_slab(s + 1);
+    if (s + 2 < s_end) load_slab(preA, s + 2);
     compute_slab();
     __syncthreads();
+    if (s + 1 < s_end) {
+      store_slab(preB, s + 1);
+      __syncthreads();
+      if (s + 3 < s_end) load_slab(preB, s + 3);
+      compute_slab();
+      __syncthreads();
+    }
   }
 
   // --- partial sub-tiles

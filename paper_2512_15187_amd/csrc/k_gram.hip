@@ -29,36 +29,69 @@ namespace pidk {
 
 // ---------------------------------------------------------------------------
 // Fixed-order FP64 reduction of the split partials into the full symmetric
-// G (N x N, row-major) and the masses.
+// G (N x N, row-major) and the masses.  A block owns 32 consecutive partial
+// elements; its 8 thread groups sum the splits k = g, g+8, g+16, ... (each in
+// ascending k, four loads in flight), and group 0 adds the 8 group sums in
+// order g = 0..7.  The order depends on nsplit only, so results are
+// deterministic.
+constexpr int RED_ELEMS = 32;
+constexpr int RED_GROUPS = 8;
+
 template <typename PT>
 __global__ __launch_bounds__(256) void gram_reduce(const PT* __restrict__ part,
                                                    const double* __restrict__ part_mass, int nsplit,
                                                    int np, int n, double* __restrict__ G,
                                                    double* __restrict__ mass) {
+  __shared__ double red[RED_GROUPS][RED_ELEMS];
   const int64_t tot = (int64_t)np * 1024;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot + n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    if (e < tot) {
-      const int p = (int)(e >> 10);
-      const int ij = (int)(e & 1023);
-      int C = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
-      while (C * (C + 1) / 2 > p) --C;
-      while ((C + 1) * (C + 2) / 2 <= p) ++C;
-      const int R = p - C * (C + 1) / 2;
-      const int i = R * 32 + (ij >> 5), j = C * 32 + (ij & 31);
-      if (i >= n || j >= n) continue;
-      if (R == C && i > j) continue;   // diagonal sub-tile: take the upper copy
-      double s = 0.0;
-      for (int k = 0; k < nsplit; ++k) s += (double)part[((size_t)k * np) * 1024 + e];
-      G[(size_t)i * n + j] = s;
-      G[(size_t)j * n + i] = s;
-    } else {
-      const int i = (int)(e - tot);
-      double s = 0.0;
-      for (int k = 0; k < nsplit; ++k) s += part_mass[(size_t)k * n + i];
-      mass[i] = s;
+  const int el = threadIdx.x % RED_ELEMS;
+  const int g = threadIdx.x / RED_ELEMS;
+  const int64_t e = (int64_t)blockIdx.x * RED_ELEMS + el;
+  const bool is_mass = e >= tot;
+  double s = 0.0;
+  if (e < tot + n) {
+    const size_t stride = is_mass ? (size_t)n : (size_t)np * 1024;
+    const size_t base = is_mass ? (size_t)(e - tot) : (size_t)e;
+    int k = g;
+    for (; k + 3 * RED_GROUPS < nsplit; k += 4 * RED_GROUPS) {
+      double v0, v1, v2, v3;
+      if (is_mass) {
+        v0 = part_mass[base + (size_t)k * stride];
+        v1 = part_mass[base + (size_t)(k + RED_GROUPS) * stride];
+        v2 = part_mass[base + (size_t)(k + 2 * RED_GROUPS) * stride];
+        v3 = part_mass[base + (size_t)(k + 3 * RED_GROUPS) * stride];
+      } else {
+        v0 = (double)part[base + (size_t)k * stride];
+        v1 = (double)part[base + (size_t)(k + RED_GROUPS) * stride];
+        v2 = (double)part[base + (size_t)(k + 2 * RED_GROUPS) * stride];
+        v3 = (double)part[base + (size_t)(k + 3 * RED_GROUPS) * stride];
+      }
+      s += v0; s += v1; s += v2; s += v3;
     }
+    for (; k < nsplit; k += RED_GROUPS)
+      s += is_mass ? part_mass[base + (size_t)k * stride] : (double)part[base + (size_t)k * stride];
   }
+  red[g][el] = s;
+  __syncthreads();
+  if (g != 0 || e >= tot + n) return;
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < RED_GROUPS; ++q) t += red[q][el];
+  if (is_mass) {
+    mass[e - tot] = t;
+    return;
+  }
+  const int p = (int)(e >> 10);
+  const int ij = (int)(e & 1023);
+  int C = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while (C * (C + 1) / 2 > p) --C;
+  while ((C + 1) * (C + 2) / 2 <= p) ++C;
+  const int R = p - C * (C + 1) / 2;
+  const int i = R * 32 + (ij >> 5), j = C * 32 + (ij & 31);
+  if (i >= n || j >= n) return;
+  if (R == C && i > j) return;   // diagonal sub-tile: take the upper copy
+  G[(size_t)i * n + j] = t;
+  G[(size_t)j * n + i] = t;
 }
 
 // Inclusion matrix P_ij = G_ij / m_i (0 when m_i = 0); one block per row.
@@ -75,18 +108,33 @@ __global__ __launch_bounds__(256) void pairs_inclusion(const double* __restrict_
 // makes binary results bitwise reproducible):
 //   IN_in(i)  = S_i / (N m_i),  S_i = sum_j G_ij
 //   IN_out(i) = (sum_j G_ji / m_j) / N   (terms with m_j = 0 are 0)
-__global__ __launch_bounds__(256) void pairs_depths(const double* __restrict__ G,
-                                                    const double* __restrict__ mass, int n,
-                                                    double* __restrict__ m_out,
-                                                    double* __restrict__ in_in,
-                                                    double* __restrict__ in_out,
-                                                    double* __restrict__ depth) {
+// Loads are issued eight at a time ahead of the in-order additions.
+__global__ __launch_bounds__(64) void pairs_depths(const double* __restrict__ G,
+                                                   const double* __restrict__ mass, int n,
+                                                   double* __restrict__ m_out,
+                                                   double* __restrict__ in_in,
+                                                   double* __restrict__ in_out,
+                                                   double* __restrict__ depth) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double S = 0.0, O = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const double g = G[(size_t)j * n + i];   // = G_ij (symmetric); coalesced over i
+  int j = 0;
+  for (; j + 8 <= n; j += 8) {
+    double g[8], mj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      g[q] = G[(size_t)(j + q) * n + i];   // = G_ij (symmetric); coalesced over i
+      mj[q] = mass[j + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      S = S + g[q];
+      if (mj[q] > 0.0) O = O + g[q] / mj[q];
+    }
+  }
+  for (; j < n; ++j) {
+    const double g = G[(size_t)j * n + i];
     S = S + g;
     const double mj = mass[j];
     if (mj > 0.0) O = O + g / mj;
@@ -256,7 +304,7 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int64_t work = (int64_t)p.np * 1024 + e.n;
-  const int rgrid = (int)std::min<int64_t>((work + 255) / 256, 4096);
+  const int rgrid = (int)((work + RED_ELEMS - 1) / RED_ELEMS);
   {
   KernelTimer tm("gram_reduce", st);
   if (p.part_elem == 8)
@@ -274,7 +322,7 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
     hipLaunchKernelGGL(pairs_inclusion, (int)e.n, 256, 0, st, G, mass, (int)e.n, out.inclusion);
   }
   KernelTimer tm("pairs_depths", st);
-  hipLaunchKernelGGL(pairs_depths, (int)((e.n + 255) / 256), 256, 0, st, G, mass, (int)e.n,
+  hipLaunchKernelGGL(pairs_depths, (int)((e.n + 63) / 64), 64, 0, st, G, mass, (int)e.n,
                      out.mass, out.in_in, out.in_out, out.depth);
   return hipGetLastError();
 }

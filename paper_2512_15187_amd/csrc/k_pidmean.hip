@@ -11,7 +11,7 @@
 // s(x) for its points and accumulates m_i and A_i for the members it loaded.
 // Per tile the sums are FP32 (FP64 for FP64 input), across tiles FP64; binary
 // input uses exact integers throughout.  Per-workgroup partials are reduced
-// in a fixed order by pidmean_finalize.
+// in a fixed order by pidmean_reduce, and pidmean_ratios forms the depths.
 #include "device_common.h"
 #include "pid_internal.h"
 #include "pid_timing.h"
@@ -33,55 +33,68 @@ __device__ __forceinline__ CT extract_ct(T raw, const Extract& e) {
 // ---------------------------------------------------------------------------
 // Soft path.  SFROM: column sums are read from `sglob` (two-pass mode) and the
 // member range of this workgroup is blockIdx.y * nwaves * MPW + ...
-// part layout: [grid.x][2][n] doubles (m, A).
-template <typename T, int MODE, int MPW, bool WEIGHTED, bool SFROM>
-__global__ __launch_bounds__(1024) void pidmean_soft_kernel(
+// A workgroup handles at most a few tens of tiles, so per-lane FP32 sums stay
+// short; lanes are combined in FP64.  Soft masks (MODE_NONE) keep only the
+// raw 16-byte vectors in registers and widen them again in the second phase;
+// fields keep the extracted probabilities.
+// part layout: [2][n][grid.x] doubles (m, then A).
+template <typename T, int MODE, int MPW, bool WEIGHTED, bool SFROM, int NWMAX>
+__global__ __launch_bounds__(64 * NWMAX) void pidmean_soft_kernel(
     const T* __restrict__ U, int64_t ld, int n, int64_t m, const float* __restrict__ w,
     Extract ex, int64_t ntiles, const void* __restrict__ sglob, double* __restrict__ part, int vec) {
-  const bool VEC = vec != 0;
   using CT = ComputeT<T>;
   constexpr int PPL = Vec16<T>::N;
   constexpr int TP = 64 * PPL;
+  constexpr bool KEEP_RAW = (MODE == MODE_NONE);
+  const bool VEC = vec != 0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   CT* sbuf = reinterpret_cast<CT*>(smem_raw);
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = wave_id();
   const int nw = blockDim.x >> 6;
   const int mbase = (SFROM ? blockIdx.y * nw * MPW : 0) + wave * MPW;
 
-  double accm[MPW], acca[MPW];
+  CT accm[MPW], acca[MPW];
 #pragma unroll
-  for (int r = 0; r < MPW; ++r) { accm[r] = 0.0; acca[r] = 0.0; }
+  for (int r = 0; r < MPW; ++r) { accm[r] = CT(0); acca[r] = CT(0); }
 
   int it = 0;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
     const int64_t x0 = tile * TP + (int64_t)lane * PPL;
     const bool full = (x0 + PPL <= m);
-    CT u[MPW][PPL];
+    Vec16<T> raw[KEEP_RAW ? MPW : 1];
+    CT u[KEEP_RAW ? 1 : MPW][PPL];
     CT sp[PPL];
 #pragma unroll
     for (int p = 0; p < PPL; ++p) sp[p] = CT(0);
 #pragma unroll
     for (int r = 0; r < MPW; ++r) {
       const int i = mbase + r;
+      Vec16<T> v{};
       if (i < n) {
         const T* row = U + (int64_t)i * ld;
-        Vec16<T> v;
         if (VEC && full) v = load16_nt(row + x0);
         else v = load16_guarded(row, x0, m);
+      }
+      if constexpr (KEEP_RAW) {
+        raw[r] = v;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) sp[p] += extract_ct<MODE, T, CT>(v.v[p], ex);
+      } else {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          CT val = extract_ct<MODE, T, CT>(v.v[p], ex);
-          if (MODE != MODE_NONE && !full) val = (x0 + p < m) ? val : CT(0);
+          CT val = (i < n) ? extract_ct<MODE, T, CT>(v.v[p], ex) : CT(0);
+          if (!full) val = (x0 + p < m) ? val : CT(0);
           u[r][p] = val;
           sp[p] += val;
         }
-      } else {
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) u[r][p] = CT(0);
       }
     }
 
+    if constexpr (KEEP_RAW) {
+#pragma unroll
+      for (int r = 0; r < MPW; ++r) opaque(raw[r]);   // widen again in phase 2
+    }
     CT s[PPL];
     if constexpr (SFROM) {
       const CT* sg = reinterpret_cast<const CT*>(sglob);
@@ -113,51 +126,59 @@ __global__ __launch_bounds__(1024) void pidmean_soft_kernel(
 #pragma unroll
         for (int p = 0; p < PPL; ++p) wv[p] = (x0 + p < m) ? CT(w[x0 + p]) : CT(0);
       }
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) s[p] *= wv[p];      // s now holds w * s
     }
 #pragma unroll
     for (int r = 0; r < MPW; ++r) {
       CT tm = CT(0), ta = CT(0);
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
-        CT wu = WEIGHTED ? wv[p] * u[r][p] : u[r][p];
-        tm += wu;
-        ta += wu * s[p];
+        CT uv;
+        if constexpr (KEEP_RAW) uv = extract_ct<MODE, T, CT>(raw[r].v[p], ex);
+        else uv = u[r][p];
+        tm += WEIGHTED ? wv[p] * uv : uv;
+        ta += s[p] * uv;
       }
-      accm[r] += (double)tm;
-      acca[r] += (double)ta;
+      accm[r] += tm;
+      acca[r] += ta;
     }
   }
 
+  const int ng = gridDim.x;
 #pragma unroll
   for (int r = 0; r < MPW; ++r) {
-    const double a = wave_sum(accm[r]);
-    const double b = wave_sum(acca[r]);
+    const double a = wave_sum((double)accm[r]);
+    const double b = wave_sum((double)acca[r]);
     const int i = mbase + r;
     if (lane == 0 && i < n) {
-      part[((size_t)blockIdx.x * 2 + 0) * n + i] = a;
-      part[((size_t)blockIdx.x * 2 + 1) * n + i] = b;
+      part[(size_t)i * ng + blockIdx.x] = a;
+      part[((size_t)n + i) * ng + blockIdx.x] = b;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Binary path (U8 masks, or STEP on fields), exact integers.
-// part layout: [grid.x][2][n] long long (m, S).
-template <typename T, int MODE, int MPW, bool SFROM>
-__global__ __launch_bounds__(1024) void pidmean_bin_kernel(
+// part layout: [2][n][grid.x] long long (m, S).
+template <typename T, int MODE, int MPW, bool SFROM, int NWMAX>
+__global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
     const T* __restrict__ U, int64_t ld, int n, int64_t m, Extract ex, int64_t ntiles,
     const int* __restrict__ sglob, long long* __restrict__ part, int vec) {
-  const bool VEC = vec != 0;
   constexpr int PPL = Vec16<T>::N;
   constexpr int TP = 64 * PPL;
+  constexpr bool PACKED = (sizeof(T) == 1 && MODE == MODE_NONE);
+  const bool VEC = vec != 0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int* sbuf = reinterpret_cast<int*>(smem_raw);
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = wave_id();
   const int nw = blockDim.x >> 6;
   const int mbase = (SFROM ? blockIdx.y * nw * MPW : 0) + wave * MPW;
 
-  long long accm[MPW], acca[MPW];
+  // per-lane integer sums stay below 2^31: at most (tiles per workgroup) *
+  // PPL * N, and the grid keeps the tiles per workgroup small
+  int accm[MPW], acca[MPW];
 #pragma unroll
   for (int r = 0; r < MPW; ++r) { accm[r] = 0; acca[r] = 0; }
 
@@ -165,10 +186,8 @@ __global__ __launch_bounds__(1024) void pidmean_bin_kernel(
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
     const int64_t x0 = tile * TP + (int64_t)lane * PPL;
     const bool full = (x0 + PPL <= m);
-    // u8 masks stay packed (4 dwords per member); other inputs become bits.
-    constexpr bool PACKED = (sizeof(T) == 1 && MODE == MODE_NONE);
-    uint32_t raw[MPW][4];
-    int ub[MPW][PACKED ? 1 : PPL];
+    uint32_t raw[PACKED ? MPW : 1][4];
+    int ub[PACKED ? 1 : MPW][PACKED ? 1 : PPL];
     int sp[PPL];
 #pragma unroll
     for (int p = 0; p < PPL; ++p) sp[p] = 0;
@@ -230,14 +249,15 @@ __global__ __launch_bounds__(1024) void pidmean_bin_kernel(
     }
   }
 
+  const int ng = gridDim.x;
 #pragma unroll
   for (int r = 0; r < MPW; ++r) {
-    const long long a = wave_sum(accm[r]);
-    const long long b = wave_sum(acca[r]);
+    const long long a = wave_sum((long long)accm[r]);
+    const long long b = wave_sum((long long)acca[r]);
     const int i = mbase + r;
     if (lane == 0 && i < n) {
-      part[((size_t)blockIdx.x * 2 + 0) * n + i] = a;
-      part[((size_t)blockIdx.x * 2 + 1) * n + i] = b;
+      part[(size_t)i * ng + blockIdx.x] = a;
+      part[((size_t)n + i) * ng + blockIdx.x] = b;
     }
   }
 }
@@ -263,61 +283,79 @@ __global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ U, in
 }
 
 // ---------------------------------------------------------------------------
-// Fixed-order reduction of the per-workgroup partials and the depth ratios.
-// One workgroup of 256 threads.
+// Fixed-order reduction of the per-workgroup partials: one block per member
+// and quantity (grid.y = 2: m, then A); thread t sums the partials
+// t, t+256, ... in ascending order, then a fixed tree over the 256 threads.
 template <bool BIN>
-__global__ __launch_bounds__(256) void pidmean_finalize(const void* __restrict__ part_v, int nparts,
-                                                        int n, double* __restrict__ m_out,
-                                                        double* __restrict__ in_in,
-                                                        double* __restrict__ in_out,
-                                                        double* __restrict__ depth,
-                                                        void* __restrict__ scratch) {
+__global__ __launch_bounds__(256) void pidmean_reduce(const void* __restrict__ part_v, int nparts,
+                                                      int n, void* __restrict__ out_v) {
+  __shared__ double red_d[256];
+  __shared__ long long red_i[256];
+  const int i = blockIdx.x, q = blockIdx.y, t = threadIdx.x;
+  const size_t base = ((size_t)q * n + i) * nparts;
+  if constexpr (BIN) {
+    const long long* part = reinterpret_cast<const long long*>(part_v);
+    long long s = 0;
+    for (int b = t; b < nparts; b += 256) s += part[base + b];
+    red_i[t] = s;
+  } else {
+    const double* part = reinterpret_cast<const double*>(part_v);
+    double s = 0.0;
+    for (int b = t; b < nparts; b += 256) s += part[base + b];
+    red_d[t] = s;
+  }
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (t < o) {
+      if constexpr (BIN) red_i[t] += red_i[t + o];
+      else red_d[t] += red_d[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if constexpr (BIN) reinterpret_cast<long long*>(out_v)[(size_t)q * n + i] = red_i[0];
+    else reinterpret_cast<double*>(out_v)[(size_t)q * n + i] = red_d[0];
+  }
+}
+
+// Depth ratios: IN_in = A_i / (N m_i), IN_out = A_i / sum_k m_k.  One block;
+// sum_k m_k by a fixed tree.  Binary sums are exact integers, so each ratio is
+// one correctly rounded division.
+template <bool BIN>
+__global__ __launch_bounds__(256) void pidmean_ratios(const void* __restrict__ red_v, int n,
+                                                      double* __restrict__ m_out,
+                                                      double* __restrict__ in_in,
+                                                      double* __restrict__ in_out,
+                                                      double* __restrict__ depth) {
 #pragma clang fp contract(off)
   __shared__ double red_d[256];
   __shared__ long long red_i[256];
   const int t = threadIdx.x;
-  double* Ad = reinterpret_cast<double*>(scratch);            // n
-  long long* Ai = reinterpret_cast<long long*>(scratch);      // n (binary)
-  double* Md = Ad + n;
-  long long* Mi = Ai + n;
-  double md_loc = 0.0;
-  long long mi_loc = 0;
+  double md = 0.0;
+  long long mi = 0;
   for (int i = t; i < n; i += 256) {
-    if constexpr (BIN) {
-      const long long* part = reinterpret_cast<const long long*>(part_v);
-      long long mm = 0, aa = 0;
-      for (int b = 0; b < nparts; ++b) {
-        mm += part[((size_t)b * 2 + 0) * n + i];
-        aa += part[((size_t)b * 2 + 1) * n + i];
-      }
-      Mi[i] = mm; Ai[i] = aa; mi_loc += mm;
-    } else {
-      const double* part = reinterpret_cast<const double*>(part_v);
-      double mm = 0.0, aa = 0.0;
-      for (int b = 0; b < nparts; ++b) {
-        mm += part[((size_t)b * 2 + 0) * n + i];
-        aa += part[((size_t)b * 2 + 1) * n + i];
-      }
-      Md[i] = mm; Ad[i] = aa; md_loc += mm;
-    }
+    if constexpr (BIN) mi += reinterpret_cast<const long long*>(red_v)[i];
+    else md += reinterpret_cast<const double*>(red_v)[i];
   }
-  red_d[t] = md_loc;
-  red_i[t] = mi_loc;
+  red_d[t] = md;
+  red_i[t] = mi;
   __syncthreads();
   for (int o = 128; o >= 1; o >>= 1) {
     if (t < o) { red_d[t] += red_d[t + o]; red_i[t] += red_i[t + o]; }
     __syncthreads();
   }
   for (int i = t; i < n; i += 256) {
-    double mi, a, tot, ii, oo;
+    double mm, a, tot;
     if constexpr (BIN) {
-      mi = (double)Mi[i]; a = (double)Ai[i]; tot = (double)red_i[0];
+      const long long* r = reinterpret_cast<const long long*>(red_v);
+      mm = (double)r[i]; a = (double)r[n + i]; tot = (double)red_i[0];
     } else {
-      mi = Md[i]; a = Ad[i]; tot = red_d[0];
+      const double* r = reinterpret_cast<const double*>(red_v);
+      mm = r[i]; a = r[n + i]; tot = red_d[0];
     }
-    ii = (mi > 0.0) ? a / ((double)n * mi) : 0.0;
-    oo = (tot > 0.0) ? a / tot : 0.0;
-    if (m_out) m_out[i] = mi;
+    const double ii = (mm > 0.0) ? a / ((double)n * mm) : 0.0;
+    const double oo = (tot > 0.0) ? a / tot : 0.0;
+    if (m_out) m_out[i] = mm;
     if (in_in) in_in[i] = ii;
     if (in_out) in_out[i] = oo;
     if (depth) depth[i] = ii < oo ? ii : oo;
@@ -347,14 +385,14 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   const int eb = elem_bytes(dtype);
   const int ppl = 16 / eb;
   const int tp = 64 * ppl;
-  // members per wave: up to 8 waves with the smallest slice that covers N,
-  // then up to 16 waves with 16 members each (N <= 256); beyond: two passes.
+  // members per wave: the smallest slice that covers N with at most 8 waves;
+  // FP32 soft input may use 16 waves of 16 members (N <= 256) within the
+  // 128 registers a 1024-thread workgroup allows; beyond: two passes.
   int mpw = 4;
   if (n > 32) mpw = 8;
   if (n > 64) mpw = 16;
-  if (eb == 1 && mpw > 8) mpw = 8;          // 16 points per lane: keep registers in check
   int nw = (int)((n + mpw - 1) / mpw);
-  const int max_waves = 16;
+  const int max_waves = (eb == 4 && !p.binary) ? 16 : 8;
   p.two_pass = 0;
   p.groups = 1;
   if (nw > max_waves) {
@@ -365,10 +403,12 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   p.mpw = mpw;
   p.nwaves = nw;
   p.ntiles = (m + tp - 1) / tp;
-  // about eight resident workgroups' worth of waves per CU, capped by the tiles
-  int target = device_cu_count() * std::max(1, 32 / nw);
-  if (p.two_pass) target = std::max(1, device_cu_count() * 4 / p.groups);
-  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, target));
+  // at most 16 tiles per workgroup (short FP32 / INT32 lane sums), and at
+  // least two workgroups per CU when there are enough tiles
+  const int64_t cus = device_cu_count();
+  int64_t g = std::max<int64_t>((p.ntiles + 15) / 16, cus * 2);
+  if (p.two_pass) g = std::max<int64_t>((p.ntiles + 15) / 16, std::max<int64_t>(1, cus * 2 / p.groups));
+  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, g));
   const int cb = p.binary ? 4 : (dtype == PID_F64 ? 8 : 4);
   p.lds_bytes = p.two_pass ? 0 : (size_t)2 * nw * tp * cb;
   return p;
@@ -390,9 +430,20 @@ static void launch_soft_t(const MeanPlan& p, const pid_ensemble& e, const Extrac
   const T* U = reinterpret_cast<const T*>(e.data);
   const bool wtd = e.weights != nullptr;
   KernelTimer tm("pidmean", st);
-#define PM_LAUNCH(W, S)                                                                       \
-  hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, W, S>), grid, block, p.lds_bytes, st, U, \
-                     e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles, sglob, part, vec ? 1 : 0)
+#define PM_LAUNCH(W, S)                                                                        \
+  do {                                                                                           \
+    if constexpr (sizeof(T) == 4) {                                                              \
+      if (p.nwaves > 8) {                                                                        \
+        hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, W, S, 16>), grid, block,          \
+                           p.lds_bytes, st, U, e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles,     \
+                           sglob, part, vec ? 1 : 0);                                            \
+        break;                                                                                   \
+      }                                                                                          \
+    }                                                                                            \
+    hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, W, S, 8>), grid, block, p.lds_bytes,   \
+                       st, U, e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles, sglob, part,         \
+                       vec ? 1 : 0);                                                             \
+  } while (0)
   if (p.two_pass) { if (wtd) PM_LAUNCH(true, true); else PM_LAUNCH(false, true); }
   else { if (wtd) PM_LAUNCH(true, false); else PM_LAUNCH(false, false); }
 #undef PM_LAUNCH
@@ -405,8 +456,8 @@ static void launch_bin_t(const MeanPlan& p, const pid_ensemble& e, const Extract
   dim3 block(64 * p.nwaves);
   const T* U = reinterpret_cast<const T*>(e.data);
   KernelTimer tm("pidmean", st);
-#define PB_LAUNCH(S)                                                                  \
-  hipLaunchKernelGGL((pidmean_bin_kernel<T, MODE, MPW, S>), grid, block, p.lds_bytes, st, U, \
+#define PB_LAUNCH(S)                                                                          \
+  hipLaunchKernelGGL((pidmean_bin_kernel<T, MODE, MPW, S, 8>), grid, block, p.lds_bytes, st, U,   \
                      e.ld, (int)e.n, e.m, ex, p.ntiles, sglob, part, vec ? 1 : 0)
   if (p.two_pass) PB_LAUNCH(true); else PB_LAUNCH(false);
 #undef PB_LAUNCH
@@ -492,12 +543,16 @@ hipError_t launch_pid_mean(const MeanPlan& p, const pid_ensemble& e, int iso_kin
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   KernelTimer tm("pidmean_finalize", st);
-  if (p.binary)
-    hipLaunchKernelGGL(pidmean_finalize<true>, 1, 256, 0, st, part, p.grid, (int)e.n, out.mass,
-                       out.in_in, out.in_out, out.depth, red);
-  else
-    hipLaunchKernelGGL(pidmean_finalize<false>, 1, 256, 0, st, part, p.grid, (int)e.n, out.mass,
-                       out.in_in, out.in_out, out.depth, red);
+  dim3 rgrid((unsigned)e.n, 2);
+  if (p.binary) {
+    hipLaunchKernelGGL(pidmean_reduce<true>, rgrid, 256, 0, st, part, p.grid, (int)e.n, red);
+    hipLaunchKernelGGL(pidmean_ratios<true>, 1, 256, 0, st, red, (int)e.n, out.mass, out.in_in,
+                       out.in_out, out.depth);
+  } else {
+    hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, p.grid, (int)e.n, red);
+    hipLaunchKernelGGL(pidmean_ratios<false>, 1, 256, 0, st, red, (int)e.n, out.mass, out.in_in,
+                       out.in_out, out.depth);
+  }
   return hipGetLastError();
 }
 

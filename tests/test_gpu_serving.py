@@ -20,10 +20,21 @@ def pool():
             ("3d", 48): synth.serving_pool("3d", 48, 64, device=DEV)}
 
 
-def test_mixed_equals_alone(pool):
+def _overlap(times):
+    """True if some two requests were on the device at the same time."""
+    for a, (_, sa, da) in enumerate(times):
+        for b, (_, sb, db) in enumerate(times):
+            if a != b and sa < db and sb < da:
+                return True
+    return False
+
+
+def test_mixed_equals_alone(pool, big):
     rng = np.random.Generator(np.random.PCG64(5))
-    srv = pid.PidServer(256 << 20, max_slots=3)
-    jobs = []
+    srv = pid.PidServer(512 << 20, max_slots=3)
+    # a long request first, so that the following ones are admitted while it runs
+    t_big, out_big = srv.pid_submit(big, variant="pairs")
+    jobs = [(big, "pairs", t_big, out_big)]
     for k in range(16):
         key = list(pool)[k % 3]
         n = int(rng.integers(8, pool[key].shape[0] + 1))
@@ -34,14 +45,19 @@ def test_mixed_equals_alone(pool):
     for U, variant, t, out in jobs:
         assert srv.pid_wait(t) == pid.PID_OK
     torch.cuda.synchronize()
-    starts = sorted(srv.pid_request_times(t)[1] for _, _, t, _ in jobs)
-    ends = sorted(srv.pid_request_times(t)[2] for _, _, t, _ in jobs)
-    assert starts[1] < ends[0] or len(jobs) == 1, "no two requests were in flight together"
+    times = [srv.pid_request_times(t) for _, _, t, _ in jobs]
+    assert _overlap(times), "no two requests were in flight together"
     for U, variant, t, out in jobs:
         alone = pid.pid_all_pairs(U) if variant == "pairs" else pid.pid_mean(U)
-        for key in KEYS + (("inclusion",) if variant == "pairs" else ()):
+        for key in KEYS + (("inclusion",) if variant == "pairs" and "inclusion" in out else ()):
             assert torch.equal(out[key], alone[key]), (variant, tuple(U.shape), key)
     srv.pid_server_destroy()
+
+
+@pytest.fixture(scope="module")
+def big():
+    """All-pairs request of 512 members on 1024 x 1024 (several milliseconds)."""
+    return synth.serving_pool("2d", 1024, 512, device=DEV)
 
 
 def test_over_budget_and_cancel(pool):
