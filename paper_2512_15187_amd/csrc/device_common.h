@@ -126,6 +126,14 @@ __device__ __forceinline__ void opaque(Vec16<T>& v) {
   v = __builtin_bit_cast(Vec16<T>, q);
 }
 
+// Workgroup barrier for LDS hand-offs only: waits for this wave's LDS
+// operations, then s_barrier.  Unlike __syncthreads() it carries no memory
+// fence, so global loads issued ahead (register prefetch) stay in flight
+// across it.  Only LDS data may be exchanged through it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // ---- wavefront (64-lane) sums; fixed butterfly order => deterministic ----

@@ -110,6 +110,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   const int rowsI = 32 * na;
   const int rows = diag ? rowsI : rowsI + 32 * nb;
   const int PLANE = rows * ROWB;                 // bytes of one LDS plane
+  const int LBUF = TR::PLANES * PLANE;           // bytes of one LDS slab buffer
 
   // --- this wave's sub-tiles
   const int T = diag ? na * (na + 1) / 2 : na * nb;
@@ -143,48 +144,83 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     return (lrow < rowsI) ? (32 * a.sb * SI + lrow) : (32 * a.sb * SJ + lrow - rowsI);
   };
 
+  // Row of every chunk slot, clamped to a valid row so that the loads of full
+  // slabs need no branches (slots outside the super-tile or past N are masked
+  // when the slab is stored).
+  int rowid[CH];
+  unsigned rvalid_bits = 0;
+#pragma unroll
+  for (int ci = 0; ci < CH; ++ci) {
+    const int lr = crow0 + RSTEP * ci;
+    const int gr = grow(lr);
+    const bool ok = (lr < rows) && (gr < a.n);
+    rowid[ci] = ok ? gr : 0;
+    rvalid_bits |= (ok ? 1u : 0u) << ci;
+  }
   // two register buffers: slab s+1 stays in flight while slab s is stored,
   // and the loads for slab s+2 are issued as soon as slab s left its buffer
   Vec16<Tin> preA[CH], preB[CH];
-  auto load_slab = [&](Vec16<Tin>* pre, int64_t s) {
+  float wA[EPC], wB[EPC];   // weights of the slab's points (prefetched with it)
+  auto load_full = [&](Vec16<Tin>* pre, float* wp, int64_t s) {   // every element in range, rows aligned
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
-    const bool full = (x0 + EPC <= a.m);
 #pragma unroll
-    for (int ci = 0; ci < CH; ++ci) {
-      const int lr = crow0 + RSTEP * ci;
-      const int gr = grow(lr);
-      if (lr < rows && gr < a.n) {
-        const Tin* p = U + (int64_t)gr * a.ld;
-        if (VEC && full) pre[ci] = load16(p + x0);
-        else pre[ci] = load16_guarded(p, x0, a.m);
-      } else {
-        pre[ci] = Vec16<Tin>{};
+    for (int ci = 0; ci < CH; ++ci) pre[ci] = load16(U + (int64_t)rowid[ci] * a.ld + x0);
+    if (WEIGHTED) {
+#pragma unroll
+      for (int e = 0; e < EPC; e += 4) {
+        const float4 t = *reinterpret_cast<const float4*>(a.w + x0 + e);
+        wp[e] = t.x;
+        if (e + 1 < EPC) wp[e + 1] = t.y;
+        if (e + 2 < EPC) wp[e + 2] = t.z;
+        if (e + 3 < EPC) wp[e + 3] = t.w;
       }
     }
   };
-
-  // masses (diagonal super-tiles only): one accumulator per chunk slot
-  double macc[CH];
-#pragma unroll
-  for (int ci = 0; ci < CH; ++ci) macc[ci] = 0.0;
-
-  auto store_slab = [&](const Vec16<Tin>* pre, int64_t s) {
+  auto load_guarded = [&](Vec16<Tin>* pre, float* wp, int64_t s) {
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
-    const bool full = (x0 + EPC <= a.m);
-    float wv[EPC], sw[EPC];
+#pragma unroll
+    for (int ci = 0; ci < CH; ++ci) {
+      if (rvalid_bits & (1u << ci)) pre[ci] = load16_guarded(U + (int64_t)rowid[ci] * a.ld, x0, a.m);
+      else pre[ci] = Vec16<Tin>{};
+    }
     if (WEIGHTED) {
 #pragma unroll
-      for (int e = 0; e < EPC; ++e) {
-        wv[e] = (x0 + e < a.m) ? a.w[x0 + e] : 0.0f;
-        sw[e] = sqrtf(wv[e]);
-      }
+      for (int e = 0; e < EPC; ++e) wp[e] = (x0 + e < a.m) ? a.w[x0 + e] : 0.0f;
+    }
+  };
+
+  // masses (diagonal super-tiles only): per slab, the CPR lanes that share a
+  // row add their chunk sums (fixed butterfly) and the first of them adds the
+  // row sum to the row's FP64 accumulator in LDS, placed after the two slab
+  // buffers.  Each row has one owner lane, which also clears it, so the order
+  // is the slab order and no barrier is needed until the final read.
+  double* lmass = reinterpret_cast<double*>(lds + 2 * LBUF);
+#pragma unroll
+  for (int ci = 0; ci < CH; ++ci) {
+    const int lr = crow0 + RSTEP * ci;
+    if (ccol == 0 && lr < rows) lmass[lr] = 0.0;
+  }
+  auto add_mass = [&](int ci, AccE v) {
+#pragma unroll
+    for (int o = CPR / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lr = crow0 + RSTEP * ci;
+    if (ccol == 0) lmass[lr] += (double)v;
+  };
+
+  auto store_slab = [&](const Vec16<Tin>* pre, const float* wv, int64_t s, unsigned char* lbuf) {
+    const int64_t x0 = s * KS + (int64_t)ccol * EPC;
+    const bool full = (x0 + EPC <= a.m);
+    float sw[EPC];
+    if (WEIGHTED) {
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) sw[e] = sqrtf(wv[e]);
     }
 #pragma unroll
     for (int ci = 0; ci < CH; ++ci) {
       const int lr = crow0 + RSTEP * ci;
       if (lr >= rows) continue;
-      const bool rvalid = grow(lr) < a.n;
-      unsigned char* dst = lds + (size_t)lr * ROWB + (size_t)ccol * EPC * TR::EB;
+      const bool rvalid = (rvalid_bits >> ci) & 1u;
+      unsigned char* dst = lbuf + (size_t)lr * ROWB + (size_t)ccol * EPC * TR::EB;
       if constexpr (BIN) {
         int8_t o[EPC];
         int cnt = 0;
@@ -195,7 +231,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
           o[e] = (int8_t)bit;
           cnt += bit;
         }
-        macc[ci] += (double)cnt;
+        if (diag) add_mass(ci, (AccE)cnt);
         store_lds<EPC>(dst, o);
       } else {
         AccE uv[EPC];
@@ -206,11 +242,11 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
           if constexpr (MT == MT_F64 || sizeof(Tin) == 8) u = (AccE)extract_d<MODE>(pre[ci].v[e], a.ex);
           else u = (AccE)extract_f<MODE>(pre[ci].v[e], a.ex);
           if (!rvalid) u = AccE(0);
-          if (MODE != MODE_NONE && !full) u = (x0 + e < a.m) ? u : AccE(0);
+          if (!full) u = (x0 + e < a.m) ? u : AccE(0);
           if (WEIGHTED) { msum += (AccE)wv[e] * u; uv[e] = (AccE)sw[e] * u; }
           else { msum += u; uv[e] = u; }
         }
-        macc[ci] += (double)msum;
+        if (diag) add_mass(ci, msum);
         if constexpr (MT == MT_F16) {
           f16 o[EPC];
 #pragma unroll
@@ -256,7 +292,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 
   const int jrow_base = diag ? 0 : rowsI;  // LDS row of J-side block 0
 
-  auto compute_slab = [&]() {
+  auto compute_slab = [&](const unsigned char* lbuf) {
     if constexpr (IS_MFMA) {
       constexpr int KSTEPS = KS / TR::KK;
       constexpr int FE = 16 / TR::EB;   // elements per lane per fragment (16 bytes)
@@ -270,12 +306,12 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
             const bool newa = (t == 0) || (ir[t] != ir[t - 1]);
             const bool newb = (t == 0) || (ic[t] != ic[t - 1]);
             if (newa) {
-              const unsigned char* pa = lds + (size_t)(ir[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
+              const unsigned char* pa = lbuf + (size_t)(ir[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
               fa[0] = *reinterpret_cast<const uint4*>(pa);
               if constexpr (TR::PLANES == 2) fa[1] = *reinterpret_cast<const uint4*>(pa + PLANE);
             }
             if (newb) {
-              const unsigned char* pb = lds + (size_t)(jrow_base + ic[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
+              const unsigned char* pb = lbuf + (size_t)(jrow_base + ic[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
               fb[0] = *reinterpret_cast<const uint4*>(pb);
               if constexpr (TR::PLANES == 2) fb[1] = *reinterpret_cast<const uint4*>(pb + PLANE);
             }
@@ -311,8 +347,8 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
             AccE av[4][4], bv[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const AccE* pa = reinterpret_cast<const AccE*>(lds + (size_t)(ir[t] * 32 + rr + i) * ROWB) + k;
-              const AccE* pb = reinterpret_cast<const AccE*>(lds + (size_t)(jrow_base + ic[t] * 32 + cc + i) * ROWB) + k;
+              const AccE* pa = reinterpret_cast<const AccE*>(lbuf + (size_t)(ir[t] * 32 + rr + i) * ROWB) + k;
+              const AccE* pb = reinterpret_cast<const AccE*>(lbuf + (size_t)(jrow_base + ic[t] * 32 + cc + i) * ROWB) + k;
 #pragma unroll
               for (int kk = 0; kk < 4; ++kk) { av[i][kk] = pa[kk]; bv[i][kk] = pb[kk]; }
             }
@@ -328,21 +364,38 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     }
   };
 
-  // --- main loop (unrolled by two over the register buffers)
-  if (s_begin < s_end) load_slab(preA, s_begin);
-  if (s_begin + 1 < s_end) load_slab(preB, s_begin + 1);
-  for (int64_t s = s_begin; s < s_end; s += 2) {
-    store_slab(preA, s);
-    __syncthreads();
-    if (s + 2 < s_end) load_slab(preA, s + 2);
-    compute_slab();
-    __syncthreads();
-    if (s + 1 < s_end) {
-      store_slab(preB, s + 1);
-      __syncthreads();
-      if (s + 3 < s_end) load_slab(preB, s + 3);
-      compute_slab();
-      __syncthreads();
+  // --- main loop over the full slabs of this split, unrolled by two over the
+  // register and LDS buffers.  Slab s goes to LDS buffer s&1; one barrier per
+  // slab suffices because a wave can only overwrite a buffer after every wave
+  // has passed the next barrier, i.e. after all of them finished multiplying
+  // the slab it held (the barrier waits for each wave's LDS reads).
+  unsigned char* lds0 = lds;
+  unsigned char* lds1 = lds + LBUF;
+  const int64_t s_full = a.m / KS;                       // slabs [0, s_full) are full
+  const int64_t f_end = VEC ? max(s_begin, min(s_end, s_full)) : s_begin;
+  if (s_begin < f_end) load_full(preA, wA, s_begin);
+  if (s_begin + 1 < f_end) load_full(preB, wB, s_begin + 1);
+  for (int64_t s = s_begin; s < f_end; s += 2) {
+    store_slab(preA, wA, s, lds0);
+    lds_barrier();
+    if (s + 2 < f_end) load_full(preA, wA, s + 2);
+    compute_slab(lds0);
+    if (s + 1 < f_end) {
+      store_slab(preB, wB, s + 1, lds1);
+      lds_barrier();
+      if (s + 3 < f_end) load_full(preB, wB, s + 3);
+      compute_slab(lds1);
+    }
+  }
+  // ragged last slab, or every slab when rows are not 16-byte aligned
+  if (f_end < s_end) {
+    lds_barrier();
+    for (int64_t s = f_end; s < s_end; ++s) {
+      load_guarded(preA, wA, s);
+      store_slab(preA, wA, s, lds0);
+      lds_barrier();
+      compute_slab(lds0);
+      lds_barrier();
     }
   }
 
@@ -373,14 +426,10 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 
   // --- partial masses (rows of the I side of diagonal super-tiles)
   if (diag) {
-#pragma unroll
-    for (int ci = 0; ci < CH; ++ci) {
-      double v = macc[ci];
-#pragma unroll
-      for (int o = CPR / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-      const int lr = crow0 + RSTEP * ci;
-      const int gr = 32 * a.sb * SI + lr;
-      if (ccol == 0 && lr < rowsI && gr < a.n) a.part_mass[(size_t)split * a.n + gr] = v;
+    lds_barrier();
+    for (int r = tid; r < rowsI; r += 512) {
+      const int gr = 32 * a.sb * SI + r;
+      if (gr < a.n) a.part_mass[(size_t)split * a.n + gr] = lmass[r];
     }
   }
 }
@@ -390,32 +439,36 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 // supported.  maxt: register tiles per wave (5 for one diagonal super-tile of
 // 5..8 row blocks, else 2).
 template <typename Tin, int MT, int MODE>
-void launch_gram_t(const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st) {
+void launch_gram_t(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
   constexpr int EB = sizeof(Tin);
   constexpr int EPC = 16 / EB;
   constexpr int MB = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) ? 2 : (MT == MT_I8 ? 1 : (MT == MT_F32 ? 4 : 8));
   constexpr int CPR = (16 * EPC * MB <= 256) ? 16 : ((8 * EPC * MB <= 256) ? 8 : ((4 * EPC * MB <= 256) ? 4 : 2));
-  constexpr int CH = (256 * CPR / 512) > 0 ? 256 * CPR / 512 : 1;   // up to 256 rows per workgroup
+  constexpr int CH256 = (256 * CPR / 512) > 0 ? 256 * CPR / 512 : 1;   // chunk slots for 256 rows
+  constexpr int CH128 = (128 * CPR / 512) > 0 ? 128 * CPR / 512 : 1;   // ... for 128 rows
+  KernelTimer tm("gram", st);
   if (maxt > 2) {
-    auto k = gram_kernel<Tin, MT, MODE, 5, CPR, CH>;
+    auto k = gram_kernel<Tin, MT, MODE, 5, CPR, CH256>;
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    KernelTimer tm("gram", st);
+    hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
+  } else if (rows > 128) {
+    auto k = gram_kernel<Tin, MT, MODE, 2, CPR, CH256>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
   } else {
-    auto k = gram_kernel<Tin, MT, MODE, 2, CPR, CH>;
+    auto k = gram_kernel<Tin, MT, MODE, 2, CPR, CH128>;
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    KernelTimer tm("gram", st);
     hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
   }
 }
 
 // Per-input-type dispatchers (one translation unit each); return false when
 // the (MFMA type, extraction mode) combination is not provided.
-bool gram_dispatch_f32(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
-bool gram_dispatch_f16(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
-bool gram_dispatch_bf16(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
-bool gram_dispatch_f64(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
-bool gram_dispatch_u8(int mt, int mode, const GramArgs& ga, int maxt, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_f32(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_f16(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_bf16(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_f64(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_u8(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
 bool gram_supported(int dtype, int mt, int mode);
 
 }  // namespace pidk

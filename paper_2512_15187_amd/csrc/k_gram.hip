@@ -104,11 +104,14 @@ __global__ __launch_bounds__(256) void pairs_inclusion(const double* __restrict_
     P[(size_t)i * n + j] = (mi > 0.0) ? G[(size_t)i * n + j] / mi : 0.0;
 }
 
-// Depths, one thread per member, sums in ascending j (the fixed order that
-// makes binary results bitwise reproducible):
+// Depths, one 64-lane block per member i:
 //   IN_in(i)  = S_i / (N m_i),  S_i = sum_j G_ij
 //   IN_out(i) = (sum_j G_ji / m_j) / N   (terms with m_j = 0 are 0)
-// Loads are issued eight at a time ahead of the in-order additions.
+// The lanes form the terms (one correctly rounded division each) for a chunk
+// of j into LDS; lane 0 adds them in ascending j, which is the fixed order
+// that makes binary results bitwise reproducible.
+constexpr int DEP_CHUNK = 1024;
+
 __global__ __launch_bounds__(64) void pairs_depths(const double* __restrict__ G,
                                                    const double* __restrict__ mass, int n,
                                                    double* __restrict__ m_out,
@@ -116,29 +119,29 @@ __global__ __launch_bounds__(64) void pairs_depths(const double* __restrict__ G,
                                                    double* __restrict__ in_out,
                                                    double* __restrict__ depth) {
 #pragma clang fp contract(off)
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  __shared__ double tg[DEP_CHUNK], to[DEP_CHUNK];
+  const int i = blockIdx.x;
+  const int t = threadIdx.x;
+  const double* row = G + (size_t)i * n;   // G_ij = G_ji (symmetric)
   double S = 0.0, O = 0.0;
-  int j = 0;
-  for (; j + 8 <= n; j += 8) {
-    double g[8], mj[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      g[q] = G[(size_t)(j + q) * n + i];   // = G_ij (symmetric); coalesced over i
-      mj[q] = mass[j + q];
+  for (int j0 = 0; j0 < n; j0 += DEP_CHUNK) {
+    const int cnt = min(DEP_CHUNK, n - j0);
+    for (int q = t; q < cnt; q += 64) {
+      const double g = row[j0 + q];
+      const double mj = mass[j0 + q];
+      tg[q] = g;
+      to[q] = (mj > 0.0) ? g / mj : 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      S = S + g[q];
-      if (mj[q] > 0.0) O = O + g[q] / mj[q];
+    __syncthreads();
+    if (t == 0) {
+      for (int q = 0; q < cnt; ++q) {
+        S = S + tg[q];
+        O = O + to[q];
+      }
     }
+    __syncthreads();
   }
-  for (; j < n; ++j) {
-    const double g = G[(size_t)j * n + i];
-    S = S + g;
-    const double mj = mass[j];
-    if (mj > 0.0) O = O + g / mj;
-  }
+  if (t != 0) return;
   const double mi = mass[i];
   const double ii = (mi > 0.0) ? S / ((double)n * mi) : 0.0;
   const double oo = O / (double)n;
@@ -249,7 +252,7 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
   const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;
   const int rowb = p.ks * mt_bytes(mt) + 16;
   const int planes = (mt == MT_BF16X3) ? 2 : 1;
-  p.lds_bytes = (size_t)planes * rows * rowb;
+  p.lds_bytes = (size_t)2 * planes * rows * rowb + (size_t)rows * 8;   // two slab buffers + row masses
   p.part_elem = (mt == MT_F64) ? 8 : 4;
   (void)iso_kind; (void)weighted;
   return p;
@@ -292,13 +295,14 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   const int mt = mtype_of(p.scheme);
   const int mode = iso_kind == PID_ISO_GAUSSIAN ? MODE_GAUSS : (iso_kind == PID_ISO_STEP ? MODE_STEP : MODE_NONE);
   const int grid = p.nsplit * p.ntiles_super;
+  const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;   // most rows a workgroup loads
   bool ok = false;
   switch (e.dtype) {
-    case PID_F64: ok = gram_dispatch_f64(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
-    case PID_F32: ok = gram_dispatch_f32(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
-    case PID_F16: ok = gram_dispatch_f16(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
-    case PID_BF16: ok = gram_dispatch_bf16(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
-    default: ok = gram_dispatch_u8(mt, mode, ga, p.maxt, grid, p.lds_bytes, st); break;
+    case PID_F64: ok = gram_dispatch_f64(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    case PID_F32: ok = gram_dispatch_f32(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    case PID_F16: ok = gram_dispatch_f16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    case PID_BF16: ok = gram_dispatch_bf16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    default: ok = gram_dispatch_u8(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
   }
   if (!ok) return hipErrorNotSupported;
   hipError_t err = hipGetLastError();
@@ -322,7 +326,7 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
     hipLaunchKernelGGL(pairs_inclusion, (int)e.n, 256, 0, st, G, mass, (int)e.n, out.inclusion);
   }
   KernelTimer tm("pairs_depths", st);
-  hipLaunchKernelGGL(pairs_depths, (int)((e.n + 63) / 64), 64, 0, st, G, mass, (int)e.n,
+  hipLaunchKernelGGL(pairs_depths, (int)e.n, 64, 0, st, G, mass, (int)e.n,
                      out.mass, out.in_in, out.in_out, out.depth);
   return hipGetLastError();
 }

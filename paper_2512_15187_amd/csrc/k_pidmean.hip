@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_soft_kernel(
       CT* sb = sbuf + (size_t)(it & 1) * nw * TP;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) sb[wave * TP + lane * PPL + p] = sp[p];
-      __syncthreads();
+      lds_barrier();
 #pragma unroll
       for (int p = 0; p < PPL; ++p) s[p] = CT(0);
       for (int q = 0; q < nw; ++q) {
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
       int* sb = sbuf + (size_t)(it & 1) * nw * TP;
 #pragma unroll
       for (int p = 0; p < PPL; ++p) sb[wave * TP + lane * PPL + p] = sp[p];
-      __syncthreads();
+      lds_barrier();
 #pragma unroll
       for (int p = 0; p < PPL; ++p) s[p] = 0;
       for (int q = 0; q < nw; ++q) {
