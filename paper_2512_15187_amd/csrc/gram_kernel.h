@@ -161,19 +161,39 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   // and the loads for slab s+2 are issued as soon as slab s left its buffer
   Vec16<Tin> preA[CH], preB[CH];
   float wA[EPC], wB[EPC];   // weights of the slab's points (prefetched with it)
+  // loads per buffer issued by load_full (slab chunks, then the weights)
+  constexpr int LB_U = CH;
+  constexpr int LB_W = CH + (EPC + 3) / 4;
   auto load_full = [&](Vec16<Tin>* pre, float* wp, int64_t s) {   // every element in range, rows aligned
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
 #pragma unroll
-    for (int ci = 0; ci < CH; ++ci) pre[ci] = load16(U + (int64_t)rowid[ci] * a.ld + x0);
+    for (int ci = 0; ci < CH; ++ci)
+      pre[ci] = __builtin_bit_cast(Vec16<Tin>, gload16_asm(U + (int64_t)rowid[ci] * a.ld + x0));
     if (WEIGHTED) {
 #pragma unroll
       for (int e = 0; e < EPC; e += 4) {
-        const float4 t = *reinterpret_cast<const float4*>(a.w + x0 + e);
-        wp[e] = t.x;
-        if (e + 1 < EPC) wp[e + 1] = t.y;
-        if (e + 2 < EPC) wp[e + 2] = t.z;
-        if (e + 3 < EPC) wp[e + 3] = t.w;
+        const u32x4 t = gload16_asm(a.w + x0 + e);
+        wp[e] = __uint_as_float(t.x);
+        if (e + 1 < EPC) wp[e + 1] = __uint_as_float(t.y);
+        if (e + 2 < EPC) wp[e + 2] = __uint_as_float(t.z);
+        if (e + 3 < EPC) wp[e + 3] = __uint_as_float(t.w);
       }
+    }
+  };
+  // wait until the buffer filled by load_full has arrived; `behind` = another
+  // buffer's loads were issued after it and may stay in flight
+  auto wait_full = [&](Vec16<Tin>* pre, float* wp, bool behind) {
+    if (behind) {
+      if (WEIGHTED) vm_wait<LB_W>();
+      else vm_wait<LB_U>();
+    } else {
+      vm_wait<0>();
+    }
+#pragma unroll
+    for (int ci = 0; ci < CH; ++ci) opaque(pre[ci]);
+    if (WEIGHTED) {
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) opaque_f(wp[e]);
     }
   };
   auto load_guarded = [&](Vec16<Tin>* pre, float* wp, int64_t s) {
@@ -376,11 +396,13 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   if (s_begin < f_end) load_full(preA, wA, s_begin);
   if (s_begin + 1 < f_end) load_full(preB, wB, s_begin + 1);
   for (int64_t s = s_begin; s < f_end; s += 2) {
+    wait_full(preA, wA, s + 1 < f_end);
     store_slab(preA, wA, s, lds0);
     lds_barrier();
     if (s + 2 < f_end) load_full(preA, wA, s + 2);
     compute_slab(lds0);
     if (s + 1 < f_end) {
+      wait_full(preB, wB, s + 2 < f_end);
       store_slab(preB, wB, s + 1, lds1);
       lds_barrier();
       if (s + 3 < f_end) load_full(preB, wB, s + 3);

@@ -17,6 +17,7 @@
 #include "pid_timing.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 namespace pidk {
@@ -379,7 +380,17 @@ static bool is_binary(int dtype, int iso_kind, bool weighted) {
   return iso_kind == PID_ISO_STEP || (dtype == PID_U8 && iso_kind == PID_ISO_NONE);
 }
 
+// Optional tuning overrides, read once: PID_TUNE_MEAN_MPW (members per wave:
+// 4, 8 or 16) and PID_TUNE_MEAN_TPW (tiles per workgroup, 1..64).  They
+// change the launch geometry only, never what is computed.
+static int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : dflt;
+}
+
 MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted) {
+  static const int tune_mpw = env_int("PID_TUNE_MEAN_MPW", 0);
+  static const int tune_tpw = env_int("PID_TUNE_MEAN_TPW", 16);
   MeanPlan p{};
   p.binary = is_binary(dtype, iso_kind, weighted) ? 1 : 0;
   const int eb = elem_bytes(dtype);
@@ -391,6 +402,7 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   int mpw = 4;
   if (n > 32) mpw = 8;
   if (n > 64) mpw = 16;
+  if (tune_mpw == 4 || tune_mpw == 8 || tune_mpw == 16) mpw = tune_mpw;
   int nw = (int)((n + mpw - 1) / mpw);
   const int max_waves = (eb == 4 && !p.binary) ? 16 : 8;
   p.two_pass = 0;
@@ -406,8 +418,9 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   // at most 16 tiles per workgroup (short FP32 / INT32 lane sums), and at
   // least two workgroups per CU when there are enough tiles
   const int64_t cus = device_cu_count();
-  int64_t g = std::max<int64_t>((p.ntiles + 15) / 16, cus * 2);
-  if (p.two_pass) g = std::max<int64_t>((p.ntiles + 15) / 16, std::max<int64_t>(1, cus * 2 / p.groups));
+  const int64_t tpw = std::min(64, std::max(1, tune_tpw));
+  int64_t g = std::max<int64_t>((p.ntiles + tpw - 1) / tpw, cus * 2);
+  if (p.two_pass) g = std::max<int64_t>((p.ntiles + tpw - 1) / tpw, std::max<int64_t>(1, cus * 2 / p.groups));
   p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, g));
   const int cb = p.binary ? 4 : (dtype == PID_F64 ? 8 : 4);
   p.lds_bytes = p.two_pass ? 0 : (size_t)2 * nw * tp * cb;
