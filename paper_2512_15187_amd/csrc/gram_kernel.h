@@ -80,12 +80,13 @@ __device__ __forceinline__ void super_ij(int t, int& I, int& J) {
 
 template <typename Tin, int MT, int MODE, int MAXT, int CPR, int CH>
 __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
-  const bool WEIGHTED = a.w != nullptr;
+  const bool WEIGHTED = !(MT == MT_I8) && a.w != nullptr;   // INT8 runs are unweighted
   const bool VEC = a.vec != 0;
   using TR = MTraits<MT>;
   using E = typename TR::E;
   constexpr int EPC = 16 / sizeof(Tin);          // elements per 16-byte chunk
   constexpr int KS = CPR * EPC;                  // points per slab
+  constexpr int G4 = EPC < 4 ? EPC : 4;          // elements converted together
   constexpr int ROWB = KS * TR::EB + 16;         // LDS row stride in bytes (padded)
   constexpr bool IS_MFMA = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3 || MT == MT_I8);
   constexpr bool BIN = (MT == MT_I8);
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   };
   auto load_guarded = [&](Vec16<Tin>* pre, float* wp, int64_t s) {
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
-#pragma unroll
+#pragma unroll 2
     for (int ci = 0; ci < CH; ++ci) {
       if (rvalid_bits & (1u << ci)) pre[ci] = load16_guarded(U + (int64_t)rowid[ci] * a.ld, x0, a.m);
       else pre[ci] = Vec16<Tin>{};
@@ -227,69 +228,91 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     if (ccol == 0) lmass[lr] += (double)v;
   };
 
+  // Convert one slab from registers into the LDS tile, four elements at a
+  // time (short live ranges), and add the masses.
   auto store_slab = [&](const Vec16<Tin>* pre, const float* wv, int64_t s, unsigned char* lbuf) {
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
     const bool full = (x0 + EPC <= a.m);
-    float sw[EPC];
-    if (WEIGHTED) {
-#pragma unroll
-      for (int e = 0; e < EPC; ++e) sw[e] = sqrtf(wv[e]);
-    }
 #pragma unroll
     for (int ci = 0; ci < CH; ++ci) {
       const int lr = crow0 + RSTEP * ci;
       if (lr >= rows) continue;
       const bool rvalid = (rvalid_bits >> ci) & 1u;
       unsigned char* dst = lbuf + (size_t)lr * ROWB + (size_t)ccol * EPC * TR::EB;
-      if constexpr (BIN) {
-        int8_t o[EPC];
+      if constexpr (BIN && sizeof(Tin) == 1 && MODE == MODE_NONE) {
+        // 0/1 bytes go to LDS as they are; ones counted four bytes at a time
+        uint4 q = __builtin_bit_cast(uint4, pre[ci]);
+        if (!rvalid) q = make_uint4(0u, 0u, 0u, 0u);
+        if (!full) {
+          uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              if (x0 + 4 * d + b >= a.m) w4[d] &= ~(0xffu << (8 * b));
+          }
+          q = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+        }
+        const int cnt = (int)(((q.x * 0x01010101u) >> 24) + ((q.y * 0x01010101u) >> 24) +
+                              ((q.z * 0x01010101u) >> 24) + ((q.w * 0x01010101u) >> 24));
+        if (diag) add_mass(ci, (AccE)cnt);
+        *reinterpret_cast<uint4*>(dst) = q;
+      } else if constexpr (BIN) {
         int cnt = 0;
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-          int bit = rvalid ? extract_bit<MODE>(pre[ci].v[e], a.ex) : 0;
-          if (!full) bit = (x0 + e < a.m) ? bit : 0;
-          o[e] = (int8_t)bit;
-          cnt += bit;
+        for (int g = 0; g < EPC; g += 4) {
+          int8_t o[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            int bit = rvalid ? extract_bit<MODE>(pre[ci].v[g + e], a.ex) : 0;
+            if (!full) bit = (x0 + g + e < a.m) ? bit : 0;
+            o[e] = (int8_t)bit;
+            cnt += bit;
+          }
+          store_lds<4>(dst + g, o);
         }
         if (diag) add_mass(ci, (AccE)cnt);
-        store_lds<EPC>(dst, o);
       } else {
-        AccE uv[EPC];
         AccE msum = AccE(0);
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-          AccE u;
-          if constexpr (MT == MT_F64 || sizeof(Tin) == 8) u = (AccE)extract_d<MODE>(pre[ci].v[e], a.ex);
-          else u = (AccE)extract_f<MODE>(pre[ci].v[e], a.ex);
-          if (!rvalid) u = AccE(0);
-          if (!full) u = (x0 + e < a.m) ? u : AccE(0);
-          if (WEIGHTED) { msum += (AccE)wv[e] * u; uv[e] = (AccE)sw[e] * u; }
-          else { msum += u; uv[e] = u; }
+        for (int g = 0; g < EPC; g += G4) {
+          AccE uv[G4];
+#pragma unroll
+          for (int e = 0; e < G4; ++e) {
+            AccE u;
+            if constexpr (MT == MT_F64 || sizeof(Tin) == 8) u = (AccE)extract_d<MODE>(pre[ci].v[g + e], a.ex);
+            else u = (AccE)extract_f<MODE>(pre[ci].v[g + e], a.ex);
+            if (!rvalid) u = AccE(0);
+            if (!full) u = (x0 + g + e < a.m) ? u : AccE(0);
+            if (WEIGHTED) { msum += (AccE)wv[g + e] * u; uv[e] = (AccE)sqrtf(wv[g + e]) * u; }
+            else { msum += u; uv[e] = u; }
+          }
+          unsigned char* d4 = dst + (size_t)g * TR::EB;
+          if constexpr (MT == MT_F16) {
+            f16 o[G4];
+#pragma unroll
+            for (int e = 0; e < G4; ++e) o[e] = (f16)uv[e];
+            store_lds<2 * G4>(d4, o);
+          } else if constexpr (MT == MT_BF16) {
+            uint16_t o[G4];
+#pragma unroll
+            for (int e = 0; e < G4; ++e) o[e] = f32_to_bf16_bits((float)uv[e]);
+            store_lds<2 * G4>(d4, o);
+          } else if constexpr (MT == MT_BF16X3) {
+            uint16_t hi[G4], lo[G4];
+#pragma unroll
+            for (int e = 0; e < G4; ++e) {
+              const float v = (float)uv[e];
+              hi[e] = f32_to_bf16_bits(v);
+              lo[e] = f32_to_bf16_bits(v - bf16_bits_to_f32(hi[e]));
+            }
+            store_lds<2 * G4>(d4, hi);
+            store_lds<2 * G4>(d4 + PLANE, lo);
+          } else {
+            store_lds<(int)sizeof(AccE) * G4>(d4, uv);
+          }
         }
         if (diag) add_mass(ci, msum);
-        if constexpr (MT == MT_F16) {
-          f16 o[EPC];
-#pragma unroll
-          for (int e = 0; e < EPC; ++e) o[e] = (f16)uv[e];
-          store_lds<2 * EPC>(dst, o);
-        } else if constexpr (MT == MT_BF16) {
-          uint16_t o[EPC];
-#pragma unroll
-          for (int e = 0; e < EPC; ++e) o[e] = f32_to_bf16_bits((float)uv[e]);
-          store_lds<2 * EPC>(dst, o);
-        } else if constexpr (MT == MT_BF16X3) {
-          uint16_t hi[EPC], lo[EPC];
-#pragma unroll
-          for (int e = 0; e < EPC; ++e) {
-            float v = (float)uv[e];
-            hi[e] = f32_to_bf16_bits(v);
-            lo[e] = f32_to_bf16_bits(v - bf16_bits_to_f32(hi[e]));
-          }
-          store_lds<2 * EPC>(dst, hi);
-          store_lds<2 * EPC>(dst + PLANE, lo);
-        } else {
-          store_lds<(int)sizeof(AccE) * EPC>(dst, uv);
-        }
       }
     }
   };
@@ -316,7 +339,8 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     if constexpr (IS_MFMA) {
       constexpr int KSTEPS = KS / TR::KK;
       constexpr int FE = 16 / TR::EB;   // elements per lane per fragment (16 bytes)
-#pragma unroll
+      constexpr int KUNR = KSTEPS > 4 ? 4 : KSTEPS;   // bounded unroll: fragments stay few
+#pragma unroll KUNR
       for (int kk = 0; kk < KSTEPS; ++kk) {
         const int koff = kk * TR::KK + (lane >> 5) * FE;   // element offset in the row
         uint4 fa[TR::PLANES], fb[TR::PLANES];
@@ -392,7 +416,14 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   unsigned char* lds0 = lds;
   unsigned char* lds1 = lds + LBUF;
   const int64_t s_full = a.m / KS;                       // slabs [0, s_full) are full
-  const int64_t f_end = VEC ? max(s_begin, min(s_end, s_full)) : s_begin;
+  // Hand-issued double-buffered loads only where the register budget holds
+  // both buffers without spilling (a spilled destination of an in-flight
+  // load would be saved before the data arrives); the other variants use the
+  // compiler-scheduled single-buffer loop below for every slab.
+  constexpr bool DB = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3 || MT == MT_I8 || MT == MT_F32) &&
+                     (sizeof(Tin) > 1 || (MT == MT_I8 && MODE == MODE_NONE));
+  const int64_t f_end = (DB && VEC) ? max(s_begin, min(s_end, s_full)) : s_begin;
+  if constexpr (DB) {
   if (s_begin < f_end) load_full(preA, wA, s_begin);
   if (s_begin + 1 < f_end) load_full(preB, wB, s_begin + 1);
   for (int64_t s = s_begin; s < f_end; s += 2) {
@@ -409,7 +440,9 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
       compute_slab(lds1);
     }
   }
-  // ragged last slab, or every slab when rows are not 16-byte aligned
+  }
+  // ragged last slab, every slab when rows are not 16-byte aligned, and every
+  // slab of the single-buffer variants
   if (f_end < s_end) {
     lds_barrier();
     for (int64_t s = f_end; s < s_end; ++s) {

@@ -57,26 +57,26 @@ hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost
 }
 
 // rank[i] = #{ j : d_j > d_i  or  (d_j == d_i and j < i) };  order[rank[i]] = i.
-__global__ __launch_bounds__(64) void rank_kernel(const double* __restrict__ d, int n,
-                                                  int32_t* __restrict__ rank,
-                                                  int32_t* __restrict__ order) {
-  __shared__ double tile[64];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const double di = (i < n) ? d[i] : 0.0;
+// One wave per member: lanes compare strided j, popcounts of the ballots
+// give the count (an exact integer, so the result is order-independent).
+__global__ __launch_bounds__(256) void rank_kernel(const double* __restrict__ d, int n,
+                                                   int32_t* __restrict__ rank,
+                                                   int32_t* __restrict__ order) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;                       // whole wave leaves together
+  const double di = d[i];
   int r = 0;
   for (int j0 = 0; j0 < n; j0 += 64) {
-    const int j = j0 + threadIdx.x;
-    tile[threadIdx.x] = (j < n) ? d[j] : 0.0;
-    __syncthreads();
-    const int lim = min(64, n - j0);
-    for (int k = 0; k < lim; ++k) {
-      const double dj = tile[k];
-      const int jj = j0 + k;
-      r += (dj > di) || (dj == di && jj < i);
+    const int j = j0 + lane;
+    bool before = false;
+    if (j < n) {
+      const double dj = d[j];
+      before = (dj > di) || (dj == di && j < i);
     }
-    __syncthreads();
+    r += __popcll(__ballot(before));
   }
-  if (i < n) {
+  if (lane == 0) {
     if (rank) rank[i] = r;
     if (order) order[r] = i;
   }
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(64) void rank_kernel(const double* __restrict__ d, 
 
 hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st) {
   KernelTimer tm("rank", st);
-  hipLaunchKernelGGL(rank_kernel, (int)((n + 63) / 64), 64, 0, st, depth, (int)n, rank, order);
+  hipLaunchKernelGGL(rank_kernel, (int)((n + 3) / 4), 256, 0, st, depth, (int)n, rank, order);
   return hipGetLastError();
 }
 
