@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -24,24 +25,71 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+REPORT = os.path.join(OUT_DIR, "resource_usage.txt")
 SOURCES = ["k_gram_f32.hip", "k_gram_f16.hip", "k_gram_f64u8.hip", "k_pidmean.hip", "k_gram.hip", "k_misc.hip", "api.cpp", "server.cpp", "timing.cpp"]
 
 
-def _compile(src: str) -> str:
+def _compile(src: str):
     obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    remarks = ["-Rpass-analysis=kernel-resource-usage"] if src.endswith(".hip") else []
+    cmd = [HIPCC, *COMMON, *remarks, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    return obj
+    return obj, r.stderr
+
+
+# Gram-kernel template arguments: <Tin, MT, MODE, MAXT, CPR, CH>.  MT: 0 F16,
+# 1 BF16, 2 BF16x3, 3 I8, 4 F32, 5 F64; MODE: 0 none, 1 Gaussian, 2 step.
+_TIN_BYTES = {"f": 4, "DF16_": 2, "NS_6bf16_tE": 2, "d": 8, "h": 1}
+
+
+def _hand_loads(tin_bytes: int, mt: int, mode: int, maxt: int) -> bool:
+    """Variants that issue their slab loads by hand (the DB condition of
+    gram_kernel.h)."""
+    return mt in (0, 1, 2, 3, 4) and (tin_bytes == 4 or (tin_bytes == 2 and maxt == 2 and mt != 4) or
+                                      (tin_bytes == 1 and mt == 3 and mode == 0))
+
+
+def resource_report(remarks: str):
+    """(kernel, vgprs, scratch bytes per lane) from -Rpass-analysis remarks."""
+    out = []
+    for block in re.split(r"remark: Function Name: ", remarks)[1:]:
+        name = block.split()[0]
+        v = re.search(r"VGPRs: (\d+)", block)
+        sc = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", block)
+        out.append((name, int(v.group(1)) if v else -1, int(sc.group(1)) if sc else 0))
+    return out
+
+
+def check_hand_loads(report):
+    """Fail when a kernel with hand-issued loads uses scratch memory (spills
+    or stack objects): a destination register of an in-flight load that got
+    saved to scratch would be saved before the data arrives."""
+    bad = []
+    for name, _, scratch in report:
+        m = re.search(r"gram_kernelI(\w+?)Li(\d)ELi(\d)ELi(\d)ELi(\d+)ELi(\d+)E", name)
+        if not m:
+            continue
+        tin = _TIN_BYTES.get(m.group(1), 0)
+        if _hand_loads(tin, int(m.group(2)), int(m.group(3)), int(m.group(4))) and scratch > 0:
+            bad.append(name)
+    if bad:
+        raise RuntimeError("kernels with hand-issued loads spill to scratch: " + ", ".join(bad))
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = max(1, min(len(SOURCES), os.cpu_count() or 1))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(_compile, SOURCES))
+    objs = [o for o, _ in results]
+    report = [r for _, rem in results for r in resource_report(rem)]
+    with open(REPORT, "w") as fh:
+        for name, vgpr, scratch in report:
+            fh.write(f"{name}\tvgpr={vgpr}\tscratch={scratch}\n")
+    check_hand_loads(report)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pidk {
 
 typedef _Float16 f16;
@@ -107,13 +109,22 @@ __device__ __forceinline__ Vec16<T> load16_nt(const T* p) {
 }
 
 // Element-wise guarded load of up to Vec16<T>::N values starting at index x0
-// of a row with m valid entries; missing entries read as zero bits.
+// of a row with m >= 1 valid entries; missing entries read as zero.  Every
+// load reads an in-bounds element (index clamped to m - 1) and the value is
+// then selected, so no branch and no stack copy is needed.
 template <typename T>
 __device__ __forceinline__ Vec16<T> load16_guarded(const T* row, int64_t x0, int64_t m) {
-  Vec16<T> out{};
+  using B = typename std::conditional<sizeof(T) == 8, uint64_t,
+            typename std::conditional<sizeof(T) == 4, uint32_t,
+            typename std::conditional<sizeof(T) == 2, uint16_t, uint8_t>::type>::type>::type;
+  const B* rb = reinterpret_cast<const B*>(row);
+  Vec16<T> out;
 #pragma unroll
-  for (int p = 0; p < Vec16<T>::N; ++p)
-    if (x0 + p < m) out.v[p] = row[x0 + p];
+  for (int p = 0; p < Vec16<T>::N; ++p) {
+    const int64_t x = x0 + p;
+    const B v = rb[x < m ? x : m - 1];
+    out.v[p] = __builtin_bit_cast(T, (B)(x < m ? v : (B)0));
+  }
   return out;
 }
 

@@ -197,19 +197,6 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
       for (int e = 0; e < EPC; ++e) opaque_f(wp[e]);
     }
   };
-  auto load_guarded = [&](Vec16<Tin>* pre, float* wp, int64_t s) {
-    const int64_t x0 = s * KS + (int64_t)ccol * EPC;
-#pragma unroll 2
-    for (int ci = 0; ci < CH; ++ci) {
-      if (rvalid_bits & (1u << ci)) pre[ci] = load16_guarded(U + (int64_t)rowid[ci] * a.ld, x0, a.m);
-      else pre[ci] = Vec16<Tin>{};
-    }
-    if (WEIGHTED) {
-#pragma unroll
-      for (int e = 0; e < EPC; ++e) wp[e] = (x0 + e < a.m) ? a.w[x0 + e] : 0.0f;
-    }
-  };
-
   // masses (diagonal super-tiles only): per slab, the CPR lanes that share a
   // row add their chunk sums (fixed butterfly) and the first of them adds the
   // row sum to the row's FP64 accumulator in LDS, placed after the two slab
@@ -230,18 +217,17 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 
   // Convert one slab from registers into the LDS tile, four elements at a
   // time (short live ranges), and add the masses.
-  auto store_slab = [&](const Vec16<Tin>* pre, const float* wv, int64_t s, unsigned char* lbuf) {
+  auto store_chunk = [&](int ci, const Vec16<Tin>& pv, const float* wv, int64_t s, unsigned char* lbuf) {
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
     const bool full = (x0 + EPC <= a.m);
-#pragma unroll
-    for (int ci = 0; ci < CH; ++ci) {
+    {
       const int lr = crow0 + RSTEP * ci;
-      if (lr >= rows) continue;
+      if (lr >= rows) return;
       const bool rvalid = (rvalid_bits >> ci) & 1u;
       unsigned char* dst = lbuf + (size_t)lr * ROWB + (size_t)ccol * EPC * TR::EB;
       if constexpr (BIN && sizeof(Tin) == 1 && MODE == MODE_NONE) {
         // 0/1 bytes go to LDS as they are; ones counted four bytes at a time
-        uint4 q = __builtin_bit_cast(uint4, pre[ci]);
+        uint4 q = __builtin_bit_cast(uint4, pv);
         if (!rvalid) q = make_uint4(0u, 0u, 0u, 0u);
         if (!full) {
           uint32_t w4[4] = {q.x, q.y, q.z, q.w};
@@ -264,7 +250,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
           int8_t o[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            int bit = rvalid ? extract_bit<MODE>(pre[ci].v[g + e], a.ex) : 0;
+            int bit = rvalid ? extract_bit<MODE>(pv.v[g + e], a.ex) : 0;
             if (!full) bit = (x0 + g + e < a.m) ? bit : 0;
             o[e] = (int8_t)bit;
             cnt += bit;
@@ -280,8 +266,8 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 #pragma unroll
           for (int e = 0; e < G4; ++e) {
             AccE u;
-            if constexpr (MT == MT_F64 || sizeof(Tin) == 8) u = (AccE)extract_d<MODE>(pre[ci].v[g + e], a.ex);
-            else u = (AccE)extract_f<MODE>(pre[ci].v[g + e], a.ex);
+            if constexpr (MT == MT_F64 || sizeof(Tin) == 8) u = (AccE)extract_d<MODE>(pv.v[g + e], a.ex);
+            else u = (AccE)extract_f<MODE>(pv.v[g + e], a.ex);
             if (!rvalid) u = AccE(0);
             if (!full) u = (x0 + g + e < a.m) ? u : AccE(0);
             if (WEIGHTED) { msum += (AccE)wv[g + e] * u; uv[e] = (AccE)sqrtf(wv[g + e]) * u; }
@@ -314,6 +300,26 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
         }
         if (diag) add_mass(ci, msum);
       }
+    }
+  };
+  auto store_slab = [&](const Vec16<Tin>* pre, const float* wv, int64_t s, unsigned char* lbuf) {
+#pragma unroll
+    for (int ci = 0; ci < CH; ++ci) store_chunk(ci, pre[ci], wv, s, lbuf);
+  };
+  // Guarded path (ragged last slab, unaligned rows, single-buffer variants):
+  // one chunk at a time, loaded by the compiler, straight into LDS.
+  auto load_store_guarded = [&](int64_t s, unsigned char* lbuf) {
+    const int64_t x0 = s * KS + (int64_t)ccol * EPC;
+    float wt[EPC];
+    if (WEIGHTED) {
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) wt[e] = a.w[(x0 + e < a.m) ? x0 + e : a.m - 1] * ((x0 + e < a.m) ? 1.0f : 0.0f);
+    }
+#pragma unroll 1
+    for (int ci = 0; ci < CH; ++ci) {
+      Vec16<Tin> v{};
+      if ((rvalid_bits >> ci) & 1u) v = load16_guarded(U + (int64_t)rowid[ci] * a.ld, x0, a.m);
+      store_chunk(ci, v, wt, s, lbuf);
     }
   };
 
@@ -421,7 +427,8 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   // load would be saved before the data arrives); the other variants use the
   // compiler-scheduled single-buffer loop below for every slab.
   constexpr bool DB = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3 || MT == MT_I8 || MT == MT_F32) &&
-                     (sizeof(Tin) > 1 || (MT == MT_I8 && MODE == MODE_NONE));
+                     (sizeof(Tin) == 4 || (sizeof(Tin) == 2 && MAXT == 2 && MT != MT_F32) ||
+                      (sizeof(Tin) == 1 && MT == MT_I8 && MODE == MODE_NONE));
   const int64_t f_end = (DB && VEC) ? max(s_begin, min(s_end, s_full)) : s_begin;
   if constexpr (DB) {
   if (s_begin < f_end) load_full(preA, wA, s_begin);
@@ -446,8 +453,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   if (f_end < s_end) {
     lds_barrier();
     for (int64_t s = f_end; s < s_end; ++s) {
-      load_guarded(preA, wA, s);
-      store_slab(preA, wA, s, lds0);
+      load_store_guarded(s, lds0);
       lds_barrier();
       compute_slab(lds0);
       lds_barrier();
