@@ -145,23 +145,6 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Streaming loads issued by hand.  The compiler's wait-count insertion does
-// not see them, so the caller waits with vm_wait<N>() (at most N vector
-// memory operations still outstanding; they retire in order) and then ties
-// the destination registers with opaque() so no use is scheduled earlier.
-// Waits the compiler inserts for its own loads stay correct: an extra
-// outstanding load can only make such a wait longer.
-__device__ __forceinline__ u32x4 gload16_asm(const void* p) {
-  u32x4 r;
-  asm volatile("global_load_dwordx4 %0, %1, off" : "=v"(r) : "v"(p) : "memory");
-  return r;
-}
-template <int N>
-__device__ __forceinline__ void vm_wait() {
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
-__device__ __forceinline__ void opaque_f(float& x) { asm volatile("" : "+v"(x)); }
-
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // ---- wavefront (64-lane) sums; fixed butterfly order => deterministic ----

@@ -78,9 +78,8 @@ __device__ __forceinline__ void super_ij(int t, int& I, int& J) {
   I = t - j * (j + 1) / 2;
 }
 
-template <typename Tin, int MT, int MODE, int MAXT, int CPR, int CH>
+template <typename Tin, int MT, int MODE, int MAXT, int CPR, int CH, bool WEIGHTED>
 __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
-  const bool WEIGHTED = !(MT == MT_I8) && a.w != nullptr;   // INT8 runs are unweighted
   const bool VEC = a.vec != 0;
   using TR = MTraits<MT>;
   using E = typename TR::E;
@@ -162,41 +161,22 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   // and the loads for slab s+2 are issued as soon as slab s left its buffer
   Vec16<Tin> preA[CH], preB[CH];
   float wA[EPC], wB[EPC];   // weights of the slab's points (prefetched with it)
-  // loads per buffer issued by load_full (slab chunks, then the weights)
-  constexpr int LB_U = CH;
-  constexpr int LB_W = CH + (EPC + 3) / 4;
   auto load_full = [&](Vec16<Tin>* pre, float* wp, int64_t s) {   // every element in range, rows aligned
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
 #pragma unroll
-    for (int ci = 0; ci < CH; ++ci)
-      pre[ci] = __builtin_bit_cast(Vec16<Tin>, gload16_asm(U + (int64_t)rowid[ci] * a.ld + x0));
-    if (WEIGHTED) {
+    for (int ci = 0; ci < CH; ++ci) pre[ci] = load16(U + (int64_t)rowid[ci] * a.ld + x0);
+    if constexpr (WEIGHTED) {
 #pragma unroll
       for (int e = 0; e < EPC; e += 4) {
-        const u32x4 t = gload16_asm(a.w + x0 + e);
-        wp[e] = __uint_as_float(t.x);
-        if (e + 1 < EPC) wp[e + 1] = __uint_as_float(t.y);
-        if (e + 2 < EPC) wp[e + 2] = __uint_as_float(t.z);
-        if (e + 3 < EPC) wp[e + 3] = __uint_as_float(t.w);
+        const float4 t = *reinterpret_cast<const float4*>(a.w + x0 + e);
+        wp[e] = t.x;
+        if (e + 1 < EPC) wp[e + 1] = t.y;
+        if (e + 2 < EPC) wp[e + 2] = t.z;
+        if (e + 3 < EPC) wp[e + 3] = t.w;
       }
     }
   };
-  // wait until the buffer filled by load_full has arrived; `behind` = another
-  // buffer's loads were issued after it and may stay in flight
-  auto wait_full = [&](Vec16<Tin>* pre, float* wp, bool behind) {
-    if (behind) {
-      if (WEIGHTED) vm_wait<LB_W>();
-      else vm_wait<LB_U>();
-    } else {
-      vm_wait<0>();
-    }
-#pragma unroll
-    for (int ci = 0; ci < CH; ++ci) opaque(pre[ci]);
-    if (WEIGHTED) {
-#pragma unroll
-      for (int e = 0; e < EPC; ++e) opaque_f(wp[e]);
-    }
-  };
+
   // masses (diagonal super-tiles only): per slab, the CPR lanes that share a
   // row add their chunk sums (fixed butterfly) and the first of them adds the
   // row sum to the row's FP64 accumulator in LDS, placed after the two slab
@@ -270,7 +250,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
             else u = (AccE)extract_f<MODE>(pv.v[g + e], a.ex);
             if (!rvalid) u = AccE(0);
             if (!full) u = (x0 + g + e < a.m) ? u : AccE(0);
-            if (WEIGHTED) { msum += (AccE)wv[g + e] * u; uv[e] = (AccE)sqrtf(wv[g + e]) * u; }
+            if constexpr (WEIGHTED) { msum += (AccE)wv[g + e] * u; uv[e] = (AccE)sqrtf(wv[g + e]) * u; }
             else { msum += u; uv[e] = u; }
           }
           unsigned char* d4 = dst + (size_t)g * TR::EB;
@@ -311,7 +291,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   auto load_store_guarded = [&](int64_t s, unsigned char* lbuf) {
     const int64_t x0 = s * KS + (int64_t)ccol * EPC;
     float wt[EPC];
-    if (WEIGHTED) {
+    if constexpr (WEIGHTED) {
 #pragma unroll
       for (int e = 0; e < EPC; ++e) wt[e] = a.w[(x0 + e < a.m) ? x0 + e : a.m - 1] * ((x0 + e < a.m) ? 1.0f : 0.0f);
     }
@@ -414,39 +394,37 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     }
   };
 
-  // --- main loop over the full slabs of this split, unrolled by two over the
-  // register and LDS buffers.  Slab s goes to LDS buffer s&1; one barrier per
-  // slab suffices because a wave can only overwrite a buffer after every wave
-  // has passed the next barrier, i.e. after all of them finished multiplying
-  // the slab it held (the barrier waits for each wave's LDS reads).
+  // --- main loop over pairs of full slabs of this split, over two register
+  // and two LDS buffers.  Slab s goes to LDS buffer s&1; one barrier per slab
+  // suffices because a wave can only overwrite a buffer after every wave has
+  // passed the next barrier, i.e. after all of them finished multiplying the
+  // slab it held (the barrier waits for each wave's LDS reads).  The loop body
+  // has no branch around a memory load (the prefetch index is clamped, the
+  // last prefetches re-read a slab and are not used), so the compiler's wait
+  // counts stay exact: storing one buffer waits only for that buffer while
+  // the other stays in flight.
   unsigned char* lds0 = lds;
   unsigned char* lds1 = lds + LBUF;
   const int64_t s_full = a.m / KS;                       // slabs [0, s_full) are full
-  // Hand-issued double-buffered loads only where the register budget holds
-  // both buffers without spilling (a spilled destination of an in-flight
-  // load would be saved before the data arrives); the other variants use the
-  // compiler-scheduled single-buffer loop below for every slab.
-  constexpr bool DB = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3 || MT == MT_I8 || MT == MT_F32) &&
-                     (sizeof(Tin) == 4 || (sizeof(Tin) == 2 && MAXT == 2 && MT != MT_F32) ||
-                      (sizeof(Tin) == 1 && MT == MT_I8 && MODE == MODE_NONE));
-  const int64_t f_end = (DB && VEC) ? max(s_begin, min(s_end, s_full)) : s_begin;
-  if constexpr (DB) {
-  if (s_begin < f_end) load_full(preA, wA, s_begin);
-  if (s_begin + 1 < f_end) load_full(preB, wB, s_begin + 1);
-  for (int64_t s = s_begin; s < f_end; s += 2) {
-    wait_full(preA, wA, s + 1 < f_end);
-    store_slab(preA, wA, s, lds0);
-    lds_barrier();
-    if (s + 2 < f_end) load_full(preA, wA, s + 2);
-    compute_slab(lds0);
-    if (s + 1 < f_end) {
-      wait_full(preB, wB, s + 2 < f_end);
+  constexpr bool DB = IS_MFMA || MT == MT_F32;
+  const int64_t nfull = (DB && VEC) ? max((int64_t)0, min(s_end, s_full) - s_begin) : 0;
+  const int64_t f_end = s_begin + (nfull & ~(int64_t)1);  // even number of slabs
+  if (f_end > s_begin) {
+    load_full(preA, wA, s_begin);
+    // keep the two prologue slabs in issue order (A before B), as in the loop,
+    // so that one wait count per chunk serves the first and later iterations
+    __builtin_amdgcn_sched_barrier(0);
+    load_full(preB, wB, s_begin + 1);
+    for (int64_t s = s_begin; s < f_end; s += 2) {
+      store_slab(preA, wA, s, lds0);
+      lds_barrier();
+      load_full(preA, wA, min(s + 2, f_end - 1));
+      compute_slab(lds0);
       store_slab(preB, wB, s + 1, lds1);
       lds_barrier();
-      if (s + 3 < f_end) load_full(preB, wB, s + 3);
+      load_full(preB, wB, min(s + 3, f_end - 1));
       compute_slab(lds1);
     }
-  }
   }
   // ragged last slab, every slab when rows are not 16-byte aligned, and every
   // slab of the single-buffer variants
@@ -499,28 +477,32 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 // Launch one instantiation; the caller has checked that the combination is
 // supported.  maxt: register tiles per wave (5 for one diagonal super-tile of
 // 5..8 row blocks, else 2).
-template <typename Tin, int MT, int MODE>
-void launch_gram_t(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
+template <typename Tin, int MT, int MODE, bool W>
+void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
   constexpr int EB = sizeof(Tin);
   constexpr int EPC = 16 / EB;
   constexpr int MB = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) ? 2 : (MT == MT_I8 ? 1 : (MT == MT_F32 ? 4 : 8));
   constexpr int CPR = (16 * EPC * MB <= 256) ? 16 : ((8 * EPC * MB <= 256) ? 8 : ((4 * EPC * MB <= 256) ? 4 : 2));
   constexpr int CH256 = (256 * CPR / 512) > 0 ? 256 * CPR / 512 : 1;   // chunk slots for 256 rows
   constexpr int CH128 = (128 * CPR / 512) > 0 ? 128 * CPR / 512 : 1;   // ... for 128 rows
+  auto go = [&](auto k) {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
+  };
+  if (maxt > 2) go(gram_kernel<Tin, MT, MODE, 5, CPR, CH256, W>);
+  else if (rows > 128) go(gram_kernel<Tin, MT, MODE, 2, CPR, CH256, W>);
+  else go(gram_kernel<Tin, MT, MODE, 2, CPR, CH128, W>);
+}
+
+// Launch one instantiation; the caller has checked that the combination is
+// supported.  maxt: register tiles per wave (5 for one diagonal super-tile of
+// 5..8 row blocks, else 2).  INT8 runs are unweighted.
+template <typename Tin, int MT, int MODE>
+void launch_gram_t(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
   KernelTimer tm("gram", st);
-  if (maxt > 2) {
-    auto k = gram_kernel<Tin, MT, MODE, 5, CPR, CH256>;
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
-  } else if (rows > 128) {
-    auto k = gram_kernel<Tin, MT, MODE, 2, CPR, CH256>;
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
-  } else {
-    auto k = gram_kernel<Tin, MT, MODE, 2, CPR, CH128>;
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
-  }
+  if constexpr (MT == MT_I8) launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st);
+  else if (ga.w != nullptr) launch_gram_w<Tin, MT, MODE, true>(ga, maxt, rows, grid, lds, st);
+  else launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st);
 }
 
 // Per-input-type dispatchers (one translation unit each); return false when
