@@ -205,6 +205,10 @@ pid_status pid_server_destroy(pid_server* server);
  * "rank", "extract".  Unknown names report 0. */
 pid_status pid_timing_enable(int on);
 pid_status pid_timing_get(const char* kernel, double* total_ms, int64_t* launches);
+/* Restrict timing to a comma-separated list of the kernel names above (so
+ * that a benchmark brackets only the kernel it reports); NULL or "" times
+ * every kernel again.  Takes effect for launches after the call. */
+pid_status pid_timing_select(const char* names);
 
 /* Diagnostics. */
 const char* pid_status_string(pid_status s);

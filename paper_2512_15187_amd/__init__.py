@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "pid_server_destroy": ([V], I32),
         "pid_timing_enable": ([I32], I32),
         "pid_timing_get": ([ctypes.c_char_p, P(ctypes.c_double), P(I64)], I32),
+        "pid_timing_select": ([ctypes.c_char_p], I32),
         "pid_status_string": ([I32], ctypes.c_char_p),
         "pid_last_error": ([], ctypes.c_char_p),
         "pid_abi_version": ([], I32),
@@ -280,6 +281,14 @@ class PreparedCall:
 def pid_timing_enable(on: bool = True):
     """Turn per-kernel event timing on/off (clears the totals)."""
     _check(load_library().pid_timing_enable(1 if on else 0))
+
+
+def pid_timing_select(names=None):
+    """Time only the listed kernels (a comma-separated string or a list);
+    None times all of them."""
+    if names is not None and not isinstance(names, str):
+        names = ",".join(names)
+    _check(load_library().pid_timing_select(None if names is None else names.encode()))
 
 
 def pid_timing_get(kernel: str):

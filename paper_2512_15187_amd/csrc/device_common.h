@@ -108,6 +108,100 @@ __device__ __forceinline__ Vec16<T> load16_nt(const T* p) {
   return __builtin_bit_cast(Vec16<T>, r);
 }
 
+// Vector of B (4, 8 or 16) bytes of stored elements, loaded non-temporally.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename T, int B>
+struct VecB {
+  static constexpr int N = B / sizeof(T);
+  T v[N];
+};
+
+template <typename T, int B>
+__device__ __forceinline__ VecB<T, B> loadB_nt(const T* p) {
+  if constexpr (B == 16) {
+    u32x4 r = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    return __builtin_bit_cast(VecB<T, B>, r);
+  } else {
+    static_assert(B == 8, "8- or 16-byte vectors");
+    u32x2 r = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    return __builtin_bit_cast(VecB<T, B>, r);
+  }
+}
+
+// Raw buffer loads: one 128-bit resource per wave (base, byte extent) in
+// scalar registers, a 32-bit per-lane byte offset and a wave-uniform scalar
+// offset; cache policy "non-temporal".  Rows of a tile then share one offset
+// register instead of holding a 64-bit address each.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T, int B>
+__device__ __forceinline__ VecB<T, B> bufload_nt(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  if constexpr (B == 16) {
+    intx4 r = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 2);
+    return __builtin_bit_cast(VecB<T, B>, r);
+  } else if constexpr (B == 4) {
+    int r = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 2);
+    return __builtin_bit_cast(VecB<T, B>, r);
+  } else {
+    typedef int intx2 __attribute__((ext_vector_type(2)));
+    intx2 r = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 2);
+    return __builtin_bit_cast(VecB<T, B>, r);
+  }
+}
+
+// Direct load into LDS: every lane reads B (4 or 16) bytes at byte offset
+// voff + soff of the resource, and the wave's 64 results land in LDS
+// contiguously from dst (lane l at dst + l * B), without passing through
+// registers.  An offset at or past the resource's extent writes zeros and
+// reads no memory.  The compiler does not order LDS reads after these loads:
+// the caller waits with vm_wait<N>() (loads retire in order) before reading.
+// The offset is passed through an empty asm so that the compiler cannot
+// turn a select of it into branches: each call is exactly one instruction
+// for the whole wave, which the callers' wait counts rely on.
+template <int B>
+__device__ __forceinline__ void dma_to_lds(__amdgpu_buffer_rsrc_t rs, const void* dst, uint32_t voff, uint32_t soff) {
+  asm volatile("" : "+v"(voff));
+  auto* l = (__attribute__((address_space(3))) void*)(uintptr_t)dst;
+  if constexpr (B == 16) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 16, (int)voff, (int)soff, 0, 0);
+  else __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 4, (int)voff, (int)soff, 0, 0);
+}
+
+// Wait until at most N vector memory operations of this wave are outstanding.
+template <int N>
+__device__ __forceinline__ void vm_wait() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Hide a register vector from common-subexpression elimination.
+template <typename T, int B>
+__device__ __forceinline__ void opaque(VecB<T, B>& v) {
+  uint32_t q[B / 4];
+  __builtin_memcpy(q, &v, B);
+#pragma unroll
+  for (int i = 0; i < B / 4; ++i) asm volatile("" : "+v"(q[i]));
+  __builtin_memcpy(&v, q, B);
+}
+
+// Guarded form of loadB_nt for a ragged tile: entries at or past m read as
+// zero; every access is in bounds (index clamped to m - 1).
+template <typename T, int B>
+__device__ __forceinline__ VecB<T, B> loadB_guarded(const T* row, int64_t x0, int64_t m) {
+  using E = typename std::conditional<sizeof(T) == 8, uint64_t,
+            typename std::conditional<sizeof(T) == 4, uint32_t,
+            typename std::conditional<sizeof(T) == 2, uint16_t, uint8_t>::type>::type>::type;
+  const E* rb = reinterpret_cast<const E*>(row);
+  VecB<T, B> out;
+#pragma unroll
+  for (int p = 0; p < VecB<T, B>::N; ++p) {
+    const int64_t x = x0 + p;
+    const E v = rb[x < m ? x : m - 1];
+    out.v[p] = __builtin_bit_cast(T, (E)(x < m ? v : (E)0));
+  }
+  return out;
+}
+
 // Element-wise guarded load of up to Vec16<T>::N values starting at index x0
 // of a row with m >= 1 valid entries; missing entries read as zero.  Every
 // load reads an in-bounds element (index clamped to m - 1) and the value is

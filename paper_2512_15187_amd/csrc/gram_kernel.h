@@ -64,7 +64,6 @@ struct GramArgs {
   int np;              // packed upper sub-tiles
   int nsplit;
   int64_t slabs;       // total slabs
-  int64_t slabs_per_split;
   int vec;             // rows are 16-byte aligned
   void* part;          // [nsplit][np][1024] (float / int / double)
   double* part_mass;   // [nsplit][n]
@@ -131,9 +130,11 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     }
   }
 
-  // --- K range of this split
-  const int64_t s_begin = min((int64_t)split * a.slabs_per_split, a.slabs);
-  const int64_t s_end = min(s_begin + a.slabs_per_split, a.slabs);
+  // --- slabs of this split: split, split + nsplit, split + 2 nsplit, ...
+  // (interleaved, so that at any time the workgroups read neighbouring slabs
+  // of every row)
+  const int64_t cnt = (a.slabs > split) ? (a.slabs - 1 - split) / a.nsplit + 1 : 0;
+  auto slab = [&](int64_t j) -> int64_t { return split + j * a.nsplit; };
 
   // --- loader geometry: chunk q = tid + 512*ci -> row tid/CPR + (512/CPR)*ci, column tid%CPR
   const int ccol = tid % CPR;
@@ -407,31 +408,32 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
   unsigned char* lds1 = lds + LBUF;
   const int64_t s_full = a.m / KS;                       // slabs [0, s_full) are full
   constexpr bool DB = IS_MFMA || MT == MT_F32;
-  const int64_t nfull = (DB && VEC) ? max((int64_t)0, min(s_end, s_full) - s_begin) : 0;
-  const int64_t f_end = s_begin + (nfull & ~(int64_t)1);  // even number of slabs
-  if (f_end > s_begin) {
-    load_full(preA, wA, s_begin);
+  const int64_t nf_all = (s_full > split) ? (s_full - 1 - split) / a.nsplit + 1 : 0;
+  const int64_t nfull = (DB && VEC) ? min(nf_all, cnt) : 0;   // full slabs come first
+  const int64_t j_end = nfull & ~(int64_t)1;                   // an even number of them
+  if (j_end > 0) {
+    load_full(preA, wA, slab(0));
     // keep the two prologue slabs in issue order (A before B), as in the loop,
     // so that one wait count per chunk serves the first and later iterations
     __builtin_amdgcn_sched_barrier(0);
-    load_full(preB, wB, s_begin + 1);
-    for (int64_t s = s_begin; s < f_end; s += 2) {
-      store_slab(preA, wA, s, lds0);
+    load_full(preB, wB, slab(1));
+    for (int64_t j = 0; j < j_end; j += 2) {
+      store_slab(preA, wA, slab(j), lds0);
       lds_barrier();
-      load_full(preA, wA, min(s + 2, f_end - 1));
+      load_full(preA, wA, slab(min(j + 2, j_end - 1)));
       compute_slab(lds0);
-      store_slab(preB, wB, s + 1, lds1);
+      store_slab(preB, wB, slab(j + 1), lds1);
       lds_barrier();
-      load_full(preB, wB, min(s + 3, f_end - 1));
+      load_full(preB, wB, slab(min(j + 3, j_end - 1)));
       compute_slab(lds1);
     }
   }
   // ragged last slab, every slab when rows are not 16-byte aligned, and every
   // slab of the single-buffer variants
-  if (f_end < s_end) {
+  if (j_end < cnt) {
     lds_barrier();
-    for (int64_t s = f_end; s < s_end; ++s) {
-      load_store_guarded(s, lds0);
+    for (int64_t j = j_end; j < cnt; ++j) {
+      load_store_guarded(slab(j), lds0);
       lds_barrier();
       compute_slab(lds0);
       lds_barrier();
@@ -486,7 +488,10 @@ void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
   constexpr int CH256 = (256 * CPR / 512) > 0 ? 256 * CPR / 512 : 1;   // chunk slots for 256 rows
   constexpr int CH128 = (128 * CPR / 512) > 0 ? 128 * CPR / 512 : 1;   // ... for 128 rows
   auto go = [&](auto k) {
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // allow up to 160 KB of LDS, once per kernel
+    static const bool attr = (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  163840) == hipSuccess);
+    (void)attr;
     hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
   };
   if (maxt > 2) go(gram_kernel<Tin, MT, MODE, 5, CPR, CH256, W>);

@@ -284,7 +284,6 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   ga.np = p.np;
   ga.nsplit = p.nsplit;
   ga.slabs = p.slabs;
-  ga.slabs_per_split = p.slabs_per_split;
   ga.part = c.take<char>((size_t)p.nsplit * p.np * 1024 * p.part_elem);
   ga.part_mass = c.take<double>((size_t)p.nsplit * e.n);
   double* G = c.take<double>((size_t)e.n * e.n);

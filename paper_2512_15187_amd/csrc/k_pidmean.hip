@@ -25,6 +25,12 @@ namespace pidk {
 template <typename T>
 using ComputeT = typename std::conditional<sizeof(T) == 8, double, float>::type;
 
+template <typename CT, typename T>
+__device__ __forceinline__ CT to_ct(T raw) {
+  if constexpr (std::is_same<CT, double>::value) return to_double(raw);
+  else return to_float(raw);
+}
+
 template <int MODE, typename T, typename CT>
 __device__ __forceinline__ CT extract_ct(T raw, const Extract& e) {
   if constexpr (std::is_same<CT, double>::value) return extract_d<MODE>(raw, e);
@@ -155,6 +161,350 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_soft_kernel(
     if (lane == 0 && i < n) {
       part[(size_t)i * ng + blockIdx.x] = a;
       part[((size_t)n + i) * ng + blockIdx.x] = b;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined soft path (rows aligned to LB bytes, N <= NWMAX * MPW): the same sums
+// as pidmean_soft_kernel, with a register double buffer.  Workgroup b takes
+// the full tiles b, b + G, b + 2G, ... (G = grid); while one tile's column
+// sums go through LDS and its members' sums are accumulated, the loads of
+// the next tile are in flight.  The loop runs over pairs of tiles with no
+// branch around a load, so the compiler's wait counts keep the other buffer
+// outstanding: a tile past the workgroup's last one is read with an offset
+// beyond the buffer's range, which the hardware answers with zeros and no
+// memory access, and it adds nothing.  Rows past n re-read the wave's last
+// row, and their copies are taken off the column sum.  The ragged last tile
+// is taken afterwards, with guarded loads, by the workgroup it falls to.
+// Soft masks keep the raw vectors and widen them twice; fields keep the
+// extracted probabilities.
+// part layout: [2][n][grid] doubles (m, then A).
+template <typename T, int MODE, int MPW, int LB, bool WEIGHTED, int NWMAX>
+__global__ __launch_bounds__(64 * NWMAX) void pidmean_pipe_kernel(
+    const T* __restrict__ U, int64_t ld, int n, int64_t m, const float* __restrict__ w,
+    Extract ex, double* __restrict__ part) {
+  using CT = ComputeT<T>;
+  using V = VecB<T, LB>;
+  constexpr int PPL = V::N;
+  constexpr int TP = 64 * PPL;
+  constexpr bool KEEP_RAW = (MODE == MODE_NONE);
+  constexpr uint32_t OOB = 0x80000000u;   // beyond every buffer range used here
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  CT* sbuf = reinterpret_cast<CT*>(smem_raw);
+  const int lane = threadIdx.x & 63;
+  const int wave = wave_id();
+  const int nw = blockDim.x >> 6;
+  const int mbase = wave * MPW;
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int64_t nfull = m / TP;
+  const int64_t K = (nfull > b) ? (nfull - 1 - b) / G + 1 : 0;   // full tiles of this workgroup
+
+  // One buffer resource per wave, based at its first row; row r sits at
+  // scalar offset min(r, rl) * ld, the points at a 32-bit per-lane offset.
+  // The host has checked that every offset fits in 31 bits.
+  const int rl = min(n - 1, mbase + MPW - 1) - mbase;            // last valid row of the wave
+  const CT dup = (CT)(MPW - 1 - rl);                               // copies of row rl beyond it
+  const __amdgpu_buffer_rsrc_t rsU = buffer_rsrc(
+      U + (int64_t)mbase * ld, (uint32_t)(((int64_t)rl * ld + m) * (int64_t)sizeof(T)));
+  const __amdgpu_buffer_rsrc_t rsW = buffer_rsrc(w, (uint32_t)(m * (int64_t)sizeof(float)));
+  const uint32_t ldb0 = (uint32_t)(ld * (int64_t)sizeof(T));     // row stride in bytes
+  const uint32_t xb = (uint32_t)b * TP + (uint32_t)(lane * PPL);
+  const uint32_t xg = (uint32_t)G * TP;
+
+  V bufA[MPW], bufB[MPW];
+  float wA[WEIGHTED ? PPL : 1], wB[WEIGHTED ? PPL : 1];
+  auto load_tile = [&](V* buf, float* wb, int64_t k) {
+    const bool ok = k < K;
+    const uint32_t x = xb + (uint32_t)k * xg;
+    const uint32_t vo = ok ? x * (uint32_t)sizeof(T) : OOB;
+    // row offsets recomputed per tile (a scalar multiply each) rather than
+    // kept in scalar registers across the loop
+    uint32_t ldb = ldb0;
+    asm volatile("" : "+s"(ldb));
+#pragma unroll
+    for (int r = 0; r < MPW; ++r) buf[r] = bufload_nt<T, LB>(rsU, vo, (uint32_t)min(r, rl) * ldb);
+    if constexpr (WEIGHTED) {
+      constexpr int WB = PPL * 4 < 16 ? PPL * 4 : 16;   // bytes per weight load
+      const uint32_t wo = ok ? x * 4u : OOB;
+#pragma unroll
+      for (int o = 0; o < PPL; o += WB / 4) {
+        const VecB<float, WB> t = bufload_nt<float, WB>(rsW, wo + 4u * o, 0u);
+#pragma unroll
+        for (int p = 0; p < WB / 4; ++p) wb[o + p] = t.v[p];
+      }
+    }
+  };
+
+  // Per-lane sums run over at most 16 tiles; then each wave folds them
+  // (fixed butterfly) into FP64 accumulators of its members in LDS, placed
+  // after the two column-sum halves.  Lane 0 owns the wave's accumulators.
+  CT accm[MPW], acca[MPW];
+#pragma unroll
+  for (int r = 0; r < MPW; ++r) { accm[r] = CT(0); acca[r] = CT(0); }
+  double* lacc = reinterpret_cast<double*>(sbuf + (size_t)2 * nw * TP) + (size_t)wave * MPW * 2;
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < 2 * MPW; ++r) lacc[r] = 0.0;
+  }
+  auto fold = [&]() {
+#pragma unroll
+    for (int r = 0; r < MPW; ++r) {
+      const CT a = wave_sum(accm[r]);
+      const CT c = wave_sum(acca[r]);
+      if (lane == 0) { lacc[2 * r] += (double)a; lacc[2 * r + 1] += (double)c; }
+      accm[r] = CT(0);
+      acca[r] = CT(0);
+    }
+  };
+
+  // One tile: column sums of the wave's members -> LDS half `parity`; after
+  // the barrier every lane adds the NW partials for its points (fixed order)
+  // and accumulates m_i and A_i of its members.  tv[p] = 0 marks a point past
+  // the end (its raw value reads as zero; fields would turn it into
+  // Phi(-c/sigma)); soft masks need no factor.
+  auto process = [&](V* buf, const float* wb, int parity, const CT* tv) {
+    CT u[KEEP_RAW ? 1 : MPW][PPL];
+    CT sp[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) sp[p] = CT(0);
+#pragma unroll
+    for (int r = 0; r < MPW; ++r) {
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        CT val = extract_ct<MODE, T, CT>(buf[r].v[p], ex);
+        if constexpr (!KEEP_RAW) { val *= tv[p]; u[r][p] = val; }
+        sp[p] += val;
+      }
+    }
+    // take off the copies of row rl read for rows past n
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      CT last;
+      if constexpr (KEEP_RAW) last = extract_ct<MODE, T, CT>(buf[MPW - 1].v[p], ex);
+      else last = u[MPW - 1][p];
+      sp[p] -= dup * last;
+    }
+    if constexpr (KEEP_RAW) {
+#pragma unroll
+      for (int r = 0; r < MPW; ++r) opaque(buf[r]);   // widen again below
+    }
+    CT* sb = sbuf + (size_t)parity * nw * TP;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) sb[wave * TP + lane * PPL + p] = sp[p];
+    lds_barrier();
+    CT s[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) s[p] = CT(0);
+    for (int q = 0; q < nw; ++q) {
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) s[p] += sb[q * TP + lane * PPL + p];
+    }
+    if constexpr (WEIGHTED) {
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) s[p] *= (CT)wb[p];   // s now holds w * s
+    }
+#pragma unroll
+    for (int r = 0; r < MPW; ++r) {
+      CT tm = CT(0), ta = CT(0);
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        CT uv;
+        if constexpr (KEEP_RAW) uv = extract_ct<MODE, T, CT>(buf[r].v[p], ex);
+        else uv = u[r][p];
+        if constexpr (WEIGHTED) tm += (CT)wb[p] * uv;
+        else tm += uv;
+        ta += s[p] * uv;
+      }
+      accm[r] += tm;
+      acca[r] += ta;
+    }
+  };
+
+  // pairs of tiles; when K is odd the second tile of the last pair is past
+  // the end and adds zeros
+  load_tile(bufA, wA, 0);
+  __builtin_amdgcn_sched_barrier(0);   // prologue loads in the loop's order (A, then B)
+  load_tile(bufB, wB, 1);
+  for (int64_t k = 0; k < K; k += 2) {
+    CT one[PPL], second[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) { one[p] = CT(1); second[p] = (k + 1 < K) ? CT(1) : CT(0); }
+    process(bufA, wA, 0, one);
+    load_tile(bufA, wA, k + 2);
+    process(bufB, wB, 1, second);
+    load_tile(bufB, wB, k + 3);
+    if ((k & 15) == 14 && k + 2 < K) fold();   // every 16 tiles, if more follow
+  }
+  // ragged last tile (LDS half 0 follows the loop's last tile, which used 1)
+  if ((m % TP) != 0 && b == (int)(nfull % G)) {
+    const int64_t x0 = nfull * TP + (int64_t)lane * PPL;
+#pragma unroll
+    for (int r = 0; r < MPW; ++r)
+      bufA[r] = loadB_guarded<T, LB>(U + (int64_t)(mbase + min(r, rl)) * ld, x0, m);
+    if constexpr (WEIGHTED) {
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) wA[p] = w[(x0 + p < m) ? x0 + p : m - 1] * ((x0 + p < m) ? 1.0f : 0.0f);
+    }
+    CT pf[PPL];   // entries past m add nothing (fields would map 0 to Phi(-c/sigma))
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) pf[p] = (x0 + p < m) ? CT(1) : CT(0);
+    process(bufA, wA, 0, pf);
+  }
+
+  fold();
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < MPW; ++r) {
+      const int i = mbase + r;
+      if (i < n) {
+        part[(size_t)i * G + b] = lacc[2 * r];
+        part[((size_t)n + i) * G + b] = lacc[2 * r + 1];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// DMA-staged soft path (soft masks; rows 16-byte aligned, M * sizeof(T) a
+// multiple of 16, N <= 8 * RPW).  Tiles hold TPP = 128 / sizeof(T) points of
+// every row.  Each wave owns RPW rows and streams its 128-byte row segments of
+// each tile straight into a ring of NBUF LDS slots (16 bytes per lane, eight
+// rows per instruction), so NBUF - 1 tiles are in flight without holding
+// registers, and no other wave reads them.  Per tile, a lane reads its point
+// of the wave's rows from LDS for the wave's column sums, which go through
+// LDS (one barrier), and again for m_i and A_i.  Loads of tiles past the
+// workgroup's share, of rows past N and of points past M use an offset
+// beyond the buffer's range: they write zeros and read no memory, so the
+// loop has no branch around a load and the wait counts are constants.
+// Lane sums run over at most 16 tiles and are then folded (fixed butterfly)
+// into FP64 accumulators in LDS.  part layout: [2][n][grid] doubles.
+template <typename T, bool WEIGHTED, int RPW, int NBUF>
+__global__ __launch_bounds__(512) void pidmean_dma_kernel(
+    const T* __restrict__ U, int64_t ld, int n, int64_t m, const float* __restrict__ w,
+    double* __restrict__ part) {
+  using CT = ComputeT<T>;
+  constexpr int SEG = 128;                  // bytes of a row per tile
+  constexpr int TPP = SEG / (int)sizeof(T); // points per tile
+  constexpr int LPP = 64 / TPP;             // lanes per point
+  constexpr int RPL = RPW / LPP;            // rows per lane
+  constexpr int RPI = 64 * 16 / SEG;        // rows per load instruction (8)
+  constexpr int DPT = RPW / RPI + (WEIGHTED ? 1 : 0);   // load instructions per tile and wave
+  constexpr uint32_t OOB = 0x80000000u;
+  static_assert(RPW % RPI == 0 && RPW % LPP == 0, "row split");
+  static_assert((NBUF - 2) * DPT <= 63, "wait count");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wave = wave_id();
+  const int nw = blockDim.x >> 6;
+  const int mbase = wave * RPW;
+  const int nrows = min(RPW, n - mbase);    // valid rows of this wave (>= 1)
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int64_t ntiles = (m + TPP - 1) / TPP;
+  const int64_t K = (ntiles > b) ? (ntiles - 1 - b) / G + 1 : 0;
+
+  // LDS: raw ring [NBUF][nw][RPW][SEG], weights [NBUF][nw][64] floats,
+  // column-sum partials [2][nw][TPP], FP64 accumulators [nw][RPW][2]
+  unsigned char* raw = smem_raw;
+  float* wts = reinterpret_cast<float*>(raw + (size_t)NBUF * nw * RPW * SEG);
+  CT* psum = reinterpret_cast<CT*>(wts + (WEIGHTED ? (size_t)NBUF * nw * 64 : 0));
+  double* lacc = reinterpret_cast<double*>(psum + (size_t)2 * nw * TPP) + (size_t)wave * RPW * 2;
+  auto slot_raw = [&](int64_t k) -> unsigned char* {
+    return raw + ((size_t)(k % NBUF) * nw + wave) * RPW * SEG;
+  };
+  auto slot_w = [&](int64_t k) -> float* { return wts + ((size_t)(k % NBUF) * nw + wave) * 64; };
+
+  // resources based at the wave's first row; the host has checked that all
+  // offsets stay below 2^31
+  const __amdgpu_buffer_rsrc_t rsU = buffer_rsrc(
+      U + (int64_t)mbase * ld, (uint32_t)(((int64_t)(nrows - 1) * ld + m) * (int64_t)sizeof(T)));
+  const __amdgpu_buffer_rsrc_t rsW = buffer_rsrc(w, (uint32_t)(m * (int64_t)sizeof(float)));
+  const uint32_t ldb = (uint32_t)(ld * (int64_t)sizeof(T));
+  const int lrow = lane >> 3;               // row within a load instruction
+  const uint32_t lbyte = (uint32_t)(lane & 7) * 16u;
+
+  auto issue = [&](int64_t k) {
+    const int64_t t = b + k * G;
+    const bool tok = k < K;
+    const uint32_t xb = (uint32_t)(t * SEG) + lbyte;                  // byte of the point in a row
+    const bool pok = tok && (int64_t)(t * TPP) + (lane & 7) * (16 / (int)sizeof(T)) < m;
+    unsigned char* dst = slot_raw(k);
+#pragma unroll
+    for (int j = 0; j < RPW / RPI; ++j) {
+      const int r = j * RPI + lrow;
+      const uint32_t vo = (pok && r < nrows) ? (uint32_t)r * ldb + xb : OOB;
+      dma_to_lds<16>(rsU, dst + (size_t)j * RPI * SEG, vo, 0u);
+    }
+    if constexpr (WEIGHTED) {
+      const int64_t x = t * TPP + lane;
+      const uint32_t vo = (tok && lane < TPP && x < m) ? (uint32_t)(x * 4) : OOB;
+      dma_to_lds<4>(rsW, slot_w(k), vo, 0u);
+    }
+  };
+
+  CT accm[RPL], acca[RPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) { accm[i] = CT(0); acca[i] = CT(0); }
+  if (lane == 0) {
+    for (int r = 0; r < 2 * RPW; ++r) lacc[r] = 0.0;
+  }
+  const int pt = lane % TPP;                // this lane's point in a tile
+  const int hr = lane / TPP;                // and its first row
+  // members of a lane: rows hr + LPP * i; fold the TPP lanes of each row
+  auto fold = [&]() {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      CT a = accm[i], c = acca[i];
+#pragma unroll
+      for (int o = TPP / 2; o >= 1; o >>= 1) { a += __shfl_xor(a, o, 64); c += __shfl_xor(c, o, 64); }
+      if (pt == 0) {
+        const int r = hr + LPP * i;
+        lacc[2 * r] += (double)a;
+        lacc[2 * r + 1] += (double)c;
+      }
+      accm[i] = CT(0);
+      acca[i] = CT(0);
+    }
+  };
+
+#pragma unroll
+  for (int k = 0; k < NBUF - 1; ++k) issue(k);
+  for (int64_t k = 0; k < K; ++k) {
+    vm_wait<(NBUF - 2) * DPT>();            // this wave's loads of tile k have landed
+    const unsigned char* rt = slot_raw(k);
+    const int64_t x = (b + k * G) * TPP + pt;
+    const bool pv = x < m;
+    CT sp = CT(0);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+      sp += to_ct<CT>(*reinterpret_cast<const T*>(rt + (size_t)(hr + LPP * i) * SEG + (size_t)pt * sizeof(T)));
+#pragma unroll
+    for (int o = TPP; o < 64; o <<= 1) sp += __shfl_xor(sp, o, 64);   // the wave's rows
+    CT* ps = psum + (size_t)(k & 1) * nw * TPP;
+    if (hr == 0) ps[wave * TPP + pt] = pv ? sp : CT(0);
+    lds_barrier();
+    issue(k + NBUF - 1);                    // into the slot this wave finished with
+    CT s = CT(0);
+    for (int q = 0; q < nw; ++q) s += ps[q * TPP + pt];
+    CT wv = CT(1);
+    if constexpr (WEIGHTED) { wv = pv ? (CT)slot_w(k)[pt] : CT(0); s *= wv; }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      CT u = to_ct<CT>(*reinterpret_cast<const T*>(rt + (size_t)(hr + LPP * i) * SEG + (size_t)pt * sizeof(T)));
+      u = pv ? u : CT(0);
+      accm[i] += WEIGHTED ? wv * u : u;
+      acca[i] += s * u;
+    }
+    if ((k & 15) == 15 && k + 1 < K) fold();
+  }
+  fold();
+  vm_wait<0>();                             // no load into LDS outlives the workgroup
+  if (lane == 0) {
+    for (int r = 0; r < nrows; ++r) {
+      part[(size_t)(mbase + r) * G + b] = lacc[2 * r];
+      part[((size_t)n + mbase + r) * G + b] = lacc[2 * r + 1];
     }
   }
 }
@@ -391,11 +741,76 @@ static int env_int(const char* name, int dflt) {
 MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted) {
   static const int tune_mpw = env_int("PID_TUNE_MEAN_MPW", 0);
   static const int tune_tpw = env_int("PID_TUNE_MEAN_TPW", 16);
+  static const int tune_pipe = env_int("PID_TUNE_MEAN_PIPE", 1);
   MeanPlan p{};
   p.binary = is_binary(dtype, iso_kind, weighted) ? 1 : 0;
   const int eb = elem_bytes(dtype);
   const int ppl = 16 / eb;
   const int tp = 64 * ppl;
+  const int64_t cus = device_cu_count();
+  const int64_t tpw = std::min(64, std::max(1, tune_tpw));
+  p.ntiles = (m + tp - 1) / tp;
+
+  // LDS-staged single pass (soft masks, 128 < N <= 256, no straddling
+  // 16-byte chunk at the end of a row): waves of 32 rows, a ring of four
+  // tile slots.
+  static const int tune_dma = env_int("PID_TUNE_MEAN_DMA", 1);
+  // (For N <= 128 the tiles of eight-row waves are too small per barrier;
+  // the register pipeline below is faster there.)
+  if (tune_dma && !p.binary && iso_kind == PID_ISO_NONE && dtype != PID_U8 && n > 128 && n <= 256 &&
+      (m * eb) % 16 == 0) {
+    const int rpw = 32;
+    const int nw = (int)((n + rpw - 1) / rpw);
+    const int tpp = 128 / eb;
+    const int cb = (dtype == PID_F64) ? 8 : 4;
+    const size_t lds = (size_t)4 * nw * rpw * 128 + (weighted ? (size_t)4 * nw * 256 : 0) +
+                       (size_t)2 * nw * tpp * cb + (size_t)nw * rpw * 16;
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(163840 / (int64_t)lds, 32 / nw));
+    const int64_t tiles = (m + tpp - 1) / tpp;
+    p.dma_rpw = rpw;
+    p.dma_nwaves = nw;
+    p.dma_lds = lds;
+    p.dma_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cus * per_cu));
+  }
+
+  // Pipelined single pass (soft input, N <= 256; FP64 N <= 128).  Each tile
+  // buffer holds MPW members x LB bytes per lane: 4 members x 16 B and
+  // 8 members x 8 B (up to 16 waves, 128 registers per lane), 32 members x
+  // 4 B (8 waves, 256 registers per lane), so that two buffers, the sums
+  // and the addressing fit without spills.  It needs one full tile; rows
+  // that are not aligned take the kernel below.
+  const bool soft = !p.binary && dtype != PID_U8 &&
+                    (iso_kind == PID_ISO_NONE || (iso_kind == PID_ISO_GAUSSIAN && eb != 2));
+  if (soft && tune_pipe) {
+    int mpw = 0;
+    if (n <= 32) mpw = 4;
+    else if (n <= 128) mpw = 8;
+    else if (n <= 256 && eb <= 4) mpw = 32;
+    const int lb = (mpw == 4) ? 16 : (mpw == 8 ? 8 : 4);
+    const int ptp = (mpw && lb >= eb) ? 64 * (lb / eb) : 0;
+    if (ptp == 0) mpw = 0;
+    if (mpw && m >= ptp) {
+      p.mpw = mpw;
+      p.nwaves = (int)((n + mpw - 1) / mpw);
+      p.two_pass = 0;
+      p.groups = 1;
+      p.pipe_lb = lb;
+      const int64_t pt = (m + ptp - 1) / ptp;
+      // the workgroups that fit at once (16 waves per CU, 8 with 32 members
+      // per wave), each streaming its share of the tiles
+      const int64_t resident = cus * std::max(1, (mpw == 32 ? 8 : 16) / p.nwaves);
+      p.pipe_grid = (int)std::max<int64_t>(1, std::min<int64_t>(pt, resident));
+      const int cb = (dtype == PID_F64) ? 8 : 4;
+      p.lds_bytes = (size_t)2 * p.nwaves * ptp * cb + (size_t)2 * p.nwaves * mpw * 8;
+      // the unpipelined kernel for rows that are not aligned: at most 16
+      // members per wave, at most tpw tiles per workgroup
+      p.fb_mpw = (n <= 32) ? 4 : (n <= 64 ? 8 : 16);
+      p.fb_nwaves = (int)((n + p.fb_mpw - 1) / p.fb_mpw);
+      p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, std::max<int64_t>((p.ntiles + tpw - 1) / tpw, cus * 2)));
+      return p;
+    }
+  }
+
   // members per wave: the smallest slice that covers N with at most 8 waves;
   // FP32 soft input may use 16 waves of 16 members (N <= 256) within the
   // 128 registers a 1024-thread workgroup allows; beyond: two passes.
@@ -414,11 +829,8 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   }
   p.mpw = mpw;
   p.nwaves = nw;
-  p.ntiles = (m + tp - 1) / tp;
-  // at most 16 tiles per workgroup (short FP32 / INT32 lane sums), and at
+  // at most tpw tiles per workgroup (short FP32 / INT32 lane sums), and at
   // least two workgroups per CU when there are enough tiles
-  const int64_t cus = device_cu_count();
-  const int64_t tpw = std::min(64, std::max(1, tune_tpw));
   int64_t g = std::max<int64_t>((p.ntiles + tpw - 1) / tpw, cus * 2);
   if (p.two_pass) g = std::max<int64_t>((p.ntiles + tpw - 1) / tpw, std::max<int64_t>(1, cus * 2 / p.groups));
   p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, g));
@@ -429,37 +841,59 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
 
 size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m) {
   Carve c(nullptr);
-  c.take<double>((size_t)p.grid * 2 * n);   // partials (double or long long)
+  c.take<double>((size_t)std::max(std::max(p.grid, p.pipe_grid), p.dma_grid) * 2 * n);   // partials
   c.take<double>((size_t)2 * n);            // reduced A and m
   if (p.two_pass) c.take<double>((size_t)m);  // column sums
   return c.off + 256;
 }
 
+template <typename T, int MODE, int MPW, bool W, int NWMAX>
+static void launch_soft_one(const MeanPlan& p, const pid_ensemble& e, const Extract& ex, bool vec,
+                            int nwaves, const void* sglob, double* part, hipStream_t st) {
+  const size_t lds = (size_t)2 * nwaves * (64 * Vec16<T>::N) * sizeof(ComputeT<T>);
+  hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, W, false, NWMAX>), dim3(p.grid), dim3(64 * nwaves),
+                     lds, st, reinterpret_cast<const T*>(e.data), e.ld, (int)e.n, e.m, e.weights, ex,
+                     p.ntiles, sglob, part, vec ? 1 : 0);
+}
+
 template <typename T, int MODE, int MPW>
 static void launch_soft_t(const MeanPlan& p, const pid_ensemble& e, const Extract& ex, bool vec,
                           const void* sglob, double* part, hipStream_t st) {
-  dim3 grid(p.grid, p.two_pass ? p.groups : 1);
-  dim3 block(64 * p.nwaves);
   const T* U = reinterpret_cast<const T*>(e.data);
   const bool wtd = e.weights != nullptr;
   KernelTimer tm("pidmean", st);
-#define PM_LAUNCH(W, S)                                                                        \
-  do {                                                                                           \
-    if constexpr (sizeof(T) == 4) {                                                              \
-      if (p.nwaves > 8) {                                                                        \
-        hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, W, S, 16>), grid, block,          \
-                           p.lds_bytes, st, U, e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles,     \
-                           sglob, part, vec ? 1 : 0);                                            \
-        break;                                                                                   \
-      }                                                                                          \
-    }                                                                                            \
-    hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, W, S, 8>), grid, block, p.lds_bytes,   \
-                       st, U, e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles, sglob, part,         \
-                       vec ? 1 : 0);                                                             \
-  } while (0)
-  if (p.two_pass) { if (wtd) PM_LAUNCH(true, true); else PM_LAUNCH(false, true); }
-  else { if (wtd) PM_LAUNCH(true, false); else PM_LAUNCH(false, false); }
-#undef PM_LAUNCH
+  if (p.pipe_lb) {   // the plan picks the pipelined kernel only where it is instantiated
+    if constexpr (MODE != MODE_STEP && !std::is_same<T, uint8_t>::value && !(sizeof(T) == 8 && MPW == 32) &&
+                  !(sizeof(T) == 2 && MODE == MODE_GAUSS) && MPW != 16) {
+      constexpr int LB = (MPW == 4) ? 16 : (MPW == 8 ? 8 : 4);
+      constexpr int NWM = (MPW == 32) ? 8 : 16;
+      if (wtd)
+        hipLaunchKernelGGL((pidmean_pipe_kernel<T, MODE, MPW, LB, true, NWM>), dim3(p.pipe_grid),
+                           dim3(64 * p.nwaves), p.lds_bytes, st, U, e.ld, (int)e.n, e.m, e.weights, ex, part);
+      else
+        hipLaunchKernelGGL((pidmean_pipe_kernel<T, MODE, MPW, LB, false, NWM>), dim3(p.pipe_grid),
+                           dim3(64 * p.nwaves), p.lds_bytes, st, U, e.ld, (int)e.n, e.m, e.weights, ex, part);
+    }
+    return;
+  }
+  if constexpr (MPW != 32) {
+    dim3 grid(p.grid, p.two_pass ? p.groups : 1);
+    dim3 block(64 * p.nwaves);
+    if (p.two_pass) {
+      if (wtd)
+        hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, true, true, 8>), grid, block, 0, st, U,
+                           e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles, sglob, part, vec ? 1 : 0);
+      else
+        hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, false, true, 8>), grid, block, 0, st, U,
+                           e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles, sglob, part, vec ? 1 : 0);
+      return;
+    }
+    // single pass; 16 waves only where N needs them
+    if (p.nwaves > 8) { if (wtd) launch_soft_one<T, MODE, MPW, true, 16>(p, e, ex, vec, p.nwaves, sglob, part, st);
+                        else launch_soft_one<T, MODE, MPW, false, 16>(p, e, ex, vec, p.nwaves, sglob, part, st); }
+    else { if (wtd) launch_soft_one<T, MODE, MPW, true, 8>(p, e, ex, vec, p.nwaves, sglob, part, st);
+           else launch_soft_one<T, MODE, MPW, false, 8>(p, e, ex, vec, p.nwaves, sglob, part, st); }
+  }
 }
 
 template <typename T, int MODE, int MPW>
@@ -491,6 +925,7 @@ static void dispatch_mpw(const MeanPlan& p, const pid_ensemble& e, const Extract
     switch (p.mpw) {
       case 4: launch_soft_t<T, MODE, 4>(p, e, ex, vec, sglob, (double*)part, st); break;
       case 8: launch_soft_t<T, MODE, 8>(p, e, ex, vec, sglob, (double*)part, st); break;
+      case 32: launch_soft_t<T, MODE, 32>(p, e, ex, vec, sglob, (double*)part, st); break;
       default: launch_soft_t<T, MODE, 16>(p, e, ex, vec, sglob, (double*)part, st); break;
     }
   }
@@ -526,16 +961,73 @@ static void launch_colsum(const MeanPlan& p, const pid_ensemble& e, int iso_kind
   }
 }
 
-hipError_t launch_pid_mean(const MeanPlan& p, const pid_ensemble& e, int iso_kind,
+static hipError_t launch_mean_finalize(const MeanPlan& p, const pid_ensemble& e, void* part, void* red,
+                                       int nparts, const pid_out& out, hipStream_t st) {
+  KernelTimer tm("pidmean_finalize", st);
+  dim3 rgrid((unsigned)e.n, 2);
+  if (p.binary) {
+    hipLaunchKernelGGL(pidmean_reduce<true>, rgrid, 256, 0, st, part, nparts, (int)e.n, red);
+    hipLaunchKernelGGL(pidmean_ratios<true>, 1, 256, 0, st, red, (int)e.n, out.mass, out.in_in,
+                       out.in_out, out.depth);
+  } else {
+    hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, nparts, (int)e.n, red);
+    hipLaunchKernelGGL(pidmean_ratios<false>, 1, 256, 0, st, red, (int)e.n, out.mass, out.in_in,
+                       out.in_out, out.depth);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static void launch_dma(const MeanPlan& p, const pid_ensemble& e, double* part, hipStream_t st) {
+  const T* U = reinterpret_cast<const T*>(e.data);
+  KernelTimer tm("pidmean", st);
+  auto go = [&](auto kern) {
+    // allow up to 160 KB of LDS, once per kernel
+    static const bool attr = (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  163840) == hipSuccess);
+    (void)attr;
+    hipLaunchKernelGGL(kern, dim3(p.dma_grid), dim3(64 * p.dma_nwaves), p.dma_lds, st, U, e.ld, (int)e.n, e.m,
+                       e.weights, part);
+  };
+  const bool wtd = e.weights != nullptr;
+  if (wtd) go(pidmean_dma_kernel<T, true, 32, 4>);
+  else go(pidmean_dma_kernel<T, false, 32, 4>);
+}
+
+hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_kind,
                            const ExtractHost& exh, const pid_out& out, void* ws, hipStream_t st) {
   Extract ex = __builtin_bit_cast(Extract, exh);
   Carve c(ws);
-  void* part = c.take<double>((size_t)p.grid * 2 * e.n);
+  void* part = c.take<double>((size_t)std::max(std::max(plan.grid, plan.pipe_grid), plan.dma_grid) * 2 * e.n);
   void* red = c.take<double>((size_t)2 * e.n);
-  void* sbuf = p.two_pass ? (void*)c.take<double>((size_t)e.m) : nullptr;
+  void* sbuf = plan.two_pass ? (void*)c.take<double>((size_t)e.m) : nullptr;
   const int eb = elem_bytes(e.dtype);
   const bool vec = ((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
                    (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0);
+  // the pipelined kernel needs aligned rows and buffer offsets (one wave's
+  // rows, the weights) below 2^31; otherwise the unpipelined kernel runs
+  MeanPlan p = plan;
+  if (p.dma_rpw) {
+    const bool fits = ((int64_t)(p.dma_rpw - 1) * e.ld + e.m) * eb < (INT64_C(1) << 31) &&
+                      e.m * (int64_t)sizeof(float) < (INT64_C(1) << 31);
+    if (vec && fits) {
+      switch (e.dtype) {
+        case PID_F64: launch_dma<double>(p, e, (double*)part, st); break;
+        case PID_F32: launch_dma<float>(p, e, (double*)part, st); break;
+        case PID_F16: launch_dma<f16>(p, e, (double*)part, st); break;
+        default: launch_dma<bf16_t>(p, e, (double*)part, st); break;
+      }
+      hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+      return launch_mean_finalize(p, e, part, red, p.dma_grid, out, st);
+    }
+  }
+  if (p.pipe_lb) {
+    const bool fits = ((int64_t)(p.mpw - 1) * e.ld + e.m) * eb < (INT64_C(1) << 31) &&
+                      e.m * (int64_t)sizeof(float) < (INT64_C(1) << 31);
+    if (!(vec && fits)) { p.pipe_lb = 0; p.mpw = p.fb_mpw; p.nwaves = p.fb_nwaves; }
+  }
+  const int nparts = p.pipe_lb ? p.pipe_grid : p.grid;
   switch (e.dtype) {
     case PID_F64:
       if (p.two_pass) launch_colsum<double>(p, e, iso_kind, ex, sbuf, st);
@@ -555,18 +1047,7 @@ hipError_t launch_pid_mean(const MeanPlan& p, const pid_ensemble& e, int iso_kin
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  KernelTimer tm("pidmean_finalize", st);
-  dim3 rgrid((unsigned)e.n, 2);
-  if (p.binary) {
-    hipLaunchKernelGGL(pidmean_reduce<true>, rgrid, 256, 0, st, part, p.grid, (int)e.n, red);
-    hipLaunchKernelGGL(pidmean_ratios<true>, 1, 256, 0, st, red, (int)e.n, out.mass, out.in_in,
-                       out.in_out, out.depth);
-  } else {
-    hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, p.grid, (int)e.n, red);
-    hipLaunchKernelGGL(pidmean_ratios<false>, 1, 256, 0, st, red, (int)e.n, out.mass, out.in_in,
-                       out.in_out, out.depth);
-  }
-  return hipGetLastError();
+  return launch_mean_finalize(p, e, part, red, nparts, out, st);
 }
 
 }  // namespace pidk

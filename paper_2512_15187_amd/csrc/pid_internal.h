@@ -43,6 +43,12 @@ struct MeanPlan {
   int grid;         // workgroups along the points
   int binary;       // exact integer arithmetic
   size_t lds_bytes;
+  int pipe_lb;      // >0: pipelined single pass with LB-byte loads (aligned rows)
+  int pipe_grid;    // its grid
+  int fb_mpw, fb_nwaves;   // the unpipelined kernel's slices when rows are not aligned
+  int dma_rpw;      // >0: LDS-staged single pass, rows per wave (soft masks)
+  int dma_nwaves, dma_grid;
+  size_t dma_lds;
 };
 MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted);
 size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m);

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,7 @@ std::mutex g_mu;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, std::pair<double, int64_t>> g_tot;
+std::set<std::string> g_sel;   // kernels to time; empty = all
 
 hipEvent_t take_event() {
   if (!g_pool.empty()) {
@@ -58,6 +60,7 @@ namespace pidk {
 KernelTimer::KernelTimer(const char* name, hipStream_t st) : name_(name), st_(st) {
   if (!g_on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_sel.empty() && g_sel.find(name) == g_sel.end()) return;
   a_ = take_event();
   b_ = take_event();
   if (a_ && b_) hipEventRecord(a_, st_);
@@ -79,6 +82,23 @@ pid_status pid_timing_enable(int on) {
   resolve_locked();
   g_tot.clear();
   g_on.store(on != 0);
+  return PID_OK;
+}
+
+pid_status pid_timing_select(const char* names) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_sel.clear();
+  if (!names) return PID_OK;
+  std::string cur;
+  for (const char* c = names;; ++c) {
+    if (*c == ',' || *c == '\0') {
+      if (!cur.empty()) g_sel.insert(cur);
+      cur.clear();
+      if (*c == '\0') break;
+    } else if (*c != ' ') {
+      cur.push_back(*c);
+    }
+  }
   return PID_OK;
 }
 

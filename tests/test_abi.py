@@ -21,7 +21,7 @@ def test_exports_every_declared_symbol():
     expected = {"pid_workspace_size", "pid_all_pairs", "pid_mean", "pid_extract", "pid_rank",
                 "pid_server_create", "pid_submit", "pid_poll", "pid_wait", "pid_request_times",
                 "pid_server_destroy", "pid_status_string", "pid_last_error", "pid_abi_version",
-                "pid_timing_enable", "pid_timing_get"}
+                "pid_timing_enable", "pid_timing_get", "pid_timing_select"}
     assert expected <= set(names), set(names)
     for n in names:
         assert hasattr(lib, n), n

@@ -48,6 +48,15 @@ def test_config1_all_pairs(c1, scheme, tol):
     assert_ranks(res["rank"], ref["depth"], tol, label=f"C1 {scheme}")
 
 
+def test_config1_pid_mean(c1):
+    """PID-mean of the same ensemble (FP32 sums per tile, FP64 across tiles)."""
+    U, _ = c1
+    ref = oracle.pid_mean_large(_host(U).numpy())
+    res = pid.pid_mean(U)
+    assert_close(res, ref, TOL_F32, label="C1 mean")
+    assert_ranks(res["rank"], ref["depth"], TOL_F32, label="C1 mean")
+
+
 def test_config1_bf16_single_pass_error_is_reported(c1):
     """One BF16 pass on FP32 masks is less accurate than 1e-4 can promise; the
     split scheme exists for that.  Record its error, bounded loosely."""

@@ -77,6 +77,19 @@ MEAN_CASES = [
     ("f16_n200", 200, 4000, torch.float16, True, TOL_MIXED),
     ("f16_twopass", 300, 4001, torch.float16, False, TOL_MIXED),
     ("f32_twopass_w", 280, 2100, torch.float32, True, TOL_MIXED),
+    # several tiles per workgroup in the pipelined kernel: an odd count (the
+    # last pair reads past the end), a ragged tile, rows past N in the last wave
+    ("f32_pipe_oddK", 200, 64 * 256 * 3 + 37, torch.float32, False, TOL_F32),
+    ("f32_pipe_oddK_w", 200, 64 * 256 * 3 + 37, torch.float32, True, TOL_F32),
+    ("f16_pipe_w", 100, 256 * 256 * 6 + 100, torch.float16, True, TOL_MIXED),
+    ("f64_pipe", 70, 128 * 256 * 5 + 3, torch.float64, True, TOL_F64),
+    # LDS-staged kernel (rows end on 16-byte boundaries): ragged last tile,
+    # rows past N in the last wave, weights, every element type
+    ("f32_lds", 150, 32 * 1000 + 12, torch.float32, False, TOL_F32),
+    ("f32_lds_w", 256, 32 * 777 + 20, torch.float32, True, TOL_F32),
+    ("f16_lds_w", 64, 64 * 513 + 8, torch.float16, True, TOL_MIXED),
+    ("bf16_lds", 100, 64 * 300 + 24, torch.bfloat16, False, TOL_MIXED),
+    ("f64_lds_w", 40, 16 * 777 + 2, torch.float64, True, TOL_F64),
 ]
 
 
