@@ -32,12 +32,37 @@ SOURCES = ["k_gram_f32.hip", "k_gram_f16.hip", "k_gram_f64u8.hip", "k_pidmean.hi
 def _compile(src: str):
     obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    remarks = ["-Rpass-analysis=kernel-resource-usage"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *COMMON, *remarks, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    # kernel sources keep their device assembly (checked below) and report
+    # register use
+    extra = ["-Rpass-analysis=kernel-resource-usage", "-save-temps"] if src.endswith(".hip") else []
+    tmp = os.path.join(OUT_DIR, "tmp_" + os.path.basename(src))
+    os.makedirs(tmp, exist_ok=True)
+    cmd = [HIPCC, *COMMON, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd=tmp)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if src.endswith(".hip"):
+        for f in os.listdir(tmp):
+            if f.endswith(f"-{ARCH}.s"):
+                check_m0(os.path.join(tmp, f))
+    shutil.rmtree(tmp, ignore_errors=True)
     return obj, r.stderr
+
+
+def check_m0(asm_path: str):
+    """The loads into LDS are written as inline assembly that sets M0 itself.
+    Fail if the compiled device code uses M0 anywhere else: the compiler
+    could then hold a value in M0 across such a load."""
+    lines = [l.strip() for l in open(asm_path) if l.strip() and not l.strip().startswith(";")]
+    bad = []
+    for i, l in enumerate(lines):
+        if re.search(r"\bm0\b", l):
+            ok = (l.startswith("s_mov_b32 m0, ") and i + 1 < len(lines)
+                  and re.match(r"buffer_load_dword\w* v\d+, s\[\d+:\d+\], 0 offen lds$", lines[i + 1]))
+            if not ok:
+                bad.append(l)
+    if bad:
+        raise RuntimeError(f"{os.path.basename(asm_path)}: M0 used outside the LDS loads: {bad[:5]}")
 
 
 def resource_report(remarks: str):

@@ -152,20 +152,40 @@ __device__ __forceinline__ VecB<T, B> bufload_nt(__amdgpu_buffer_rsrc_t rs, uint
 }
 
 // Direct load into LDS: every lane reads B (4 or 16) bytes at byte offset
-// voff + soff of the resource, and the wave's 64 results land in LDS
-// contiguously from dst (lane l at dst + l * B), without passing through
-// registers.  An offset at or past the resource's extent writes zeros and
-// reads no memory.  The compiler does not order LDS reads after these loads:
-// the caller waits with vm_wait<N>() (loads retire in order) before reading.
-// The offset is passed through an empty asm so that the compiler cannot
-// turn a select of it into branches: each call is exactly one instruction
-// for the whole wave, which the callers' wait counts rely on.
+// voff of the resource, and the wave's 64 results land in LDS contiguously
+// from dst (lane l at dst + l * B), without passing through registers.  An
+// offset at or past the resource's extent writes zeros and reads no memory.
+// The instruction is written out (M0 = LDS address) rather than left to the
+// compiler, which would otherwise wait for every such load before any LDS
+// read it cannot prove disjoint; callers order LDS reads themselves with
+// vm_wait<N>() (loads retire in order) and barriers.  It has no register
+// results, and one call is exactly one instruction for the whole wave.
+// The resource words must be wave-uniform.
+typedef int intx4_t __attribute__((ext_vector_type(4)));
+struct BufRes {
+  intx4_t w;
+};
+__device__ __forceinline__ BufRes make_bufres(const void* base, uint32_t bytes) {
+  const uint64_t a = (uint64_t)(uintptr_t)base;
+  BufRes r;
+  r.w[0] = (int)__builtin_amdgcn_readfirstlane((uint32_t)a);
+  r.w[1] = (int)(__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) & 0xffffu);   // stride 0
+  r.w[2] = (int)__builtin_amdgcn_readfirstlane(bytes);
+  r.w[3] = 0x00020000;
+  return r;
+}
 template <int B>
-__device__ __forceinline__ void dma_to_lds(__amdgpu_buffer_rsrc_t rs, const void* dst, uint32_t voff, uint32_t soff) {
-  asm volatile("" : "+v"(voff));
-  auto* l = (__attribute__((address_space(3))) void*)(uintptr_t)dst;
-  if constexpr (B == 16) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 16, (int)voff, (int)soff, 0, 0);
-  else __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 4, (int)voff, (int)soff, 0, 0);
+__device__ __forceinline__ void dma_to_lds(const BufRes& rs, const void* dst, uint32_t voff) {
+  const uint32_t l = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)dst);
+  asm volatile("" : "+v"(voff));   // keep a select of the offset a select
+  if constexpr (B == 16) {
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                 :: "s"(l), "v"(voff), "s"(rs.w) : "memory", "m0");
+  } else {
+    static_assert(B == 4, "4- or 16-byte lanes");
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, 0 offen lds"
+                 :: "s"(l), "v"(voff), "s"(rs.w) : "memory", "m0");
+  }
 }
 
 // Wait until at most N vector memory operations of this wave are outstanding.

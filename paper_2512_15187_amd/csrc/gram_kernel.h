@@ -6,6 +6,7 @@
 #include "pid_timing.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 namespace pidk {
@@ -75,6 +76,113 @@ __device__ __forceinline__ void super_ij(int t, int& I, int& J) {
   while ((j + 1) * (j + 2) / 2 <= t) ++j;
   J = j;
   I = t - j * (j + 1) / 2;
+}
+
+// Accumulator vector of one 32x32 sub-tile (int for INT8, float otherwise).
+template <int MT>
+using AccVec = typename std::conditional<MT == MT_I8, intx16, floatx16>::type;
+
+// Multiply one LDS slab into the wave's sub-tiles: rows of block ir[t] times
+// rows of block ic[t] (offset by jrow_base), KS points, row stride ROWB bytes,
+// hi/lo planes PLANE bytes apart.  Per k-step the fragments of every
+// sub-tile are read first (no data-dependent branch, so the reads are issued
+// back to back and their latency is paid once), then the MFMAs follow.
+template <int MT, int MAXT, int KS, int ROWB>
+__device__ __forceinline__ void mfma_slab(const unsigned char* lbuf, int PLANE, int lane, int nt,
+                                          const int* ir, const int* ic, int jrow_base, AccVec<MT>* acc) {
+  using TR = MTraits<MT>;
+  constexpr int KSTEPS = KS / TR::KK;
+  constexpr int FE = 16 / TR::EB;   // elements per lane per fragment (16 bytes)
+  constexpr int KUNR = KSTEPS > 2 ? 2 : KSTEPS;
+#pragma unroll KUNR
+  for (int kk = 0; kk < KSTEPS; ++kk) {
+    const int koff = kk * TR::KK + (lane >> 5) * FE;   // element offset in the row
+    uint4 fa[MAXT][TR::PLANES], fb[MAXT][TR::PLANES];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      const unsigned char* pa = lbuf + (size_t)(ir[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
+      const unsigned char* pb = lbuf + (size_t)(jrow_base + ic[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
+      fa[t][0] = *reinterpret_cast<const uint4*>(pa);
+      fb[t][0] = *reinterpret_cast<const uint4*>(pb);
+      if constexpr (TR::PLANES == 2) {
+        fa[t][1] = *reinterpret_cast<const uint4*>(pa + PLANE);
+        fb[t][1] = *reinterpret_cast<const uint4*>(pb + PLANE);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      if (t < nt) {
+        if constexpr (MT == MT_F16) {
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, fa[t][0]),
+                                                           __builtin_bit_cast(half8, fb[t][0]), acc[t], 0, 0, 0);
+        } else if constexpr (MT == MT_BF16) {
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[t][0]),
+                                                            __builtin_bit_cast(bf16x8, fb[t][0]), acc[t], 0, 0, 0);
+        } else if constexpr (MT == MT_BF16X3) {
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[t][0]),
+                                                            __builtin_bit_cast(bf16x8, fb[t][0]), acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[t][0]),
+                                                            __builtin_bit_cast(bf16x8, fb[t][1]), acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[t][1]),
+                                                            __builtin_bit_cast(bf16x8, fb[t][0]), acc[t], 0, 0, 0);
+        } else {
+          acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(intx4, fa[t][0]),
+                                                          __builtin_bit_cast(intx4, fb[t][0]), acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+// The same with fragment reuse: a fragment is read once while consecutive
+// sub-tiles share it (fewer registers; used where registers also hold the
+// prefetched slab).
+template <int MT, int MAXT, int KS, int ROWB>
+__device__ __forceinline__ void mfma_slab_reuse(const unsigned char* lbuf, int PLANE, int lane, int nt,
+                                                const int* ir, const int* ic, int jrow_base, AccVec<MT>* acc) {
+  using TR = MTraits<MT>;
+  constexpr int KSTEPS = KS / TR::KK;
+  constexpr int FE = 16 / TR::EB;
+  constexpr int KUNR = KSTEPS > 4 ? 4 : KSTEPS;
+#pragma unroll KUNR
+  for (int kk = 0; kk < KSTEPS; ++kk) {
+    const int koff = kk * TR::KK + (lane >> 5) * FE;
+    uint4 fa[TR::PLANES], fb[TR::PLANES];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      if (t < nt) {
+        const bool newa = (t == 0) || (ir[t] != ir[t - 1]);
+        const bool newb = (t == 0) || (ic[t] != ic[t - 1]);
+        if (newa) {
+          const unsigned char* pa = lbuf + (size_t)(ir[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
+          fa[0] = *reinterpret_cast<const uint4*>(pa);
+          if constexpr (TR::PLANES == 2) fa[1] = *reinterpret_cast<const uint4*>(pa + PLANE);
+        }
+        if (newb) {
+          const unsigned char* pb = lbuf + (size_t)(jrow_base + ic[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
+          fb[0] = *reinterpret_cast<const uint4*>(pb);
+          if constexpr (TR::PLANES == 2) fb[1] = *reinterpret_cast<const uint4*>(pb + PLANE);
+        }
+        if constexpr (MT == MT_F16) {
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, fa[0]),
+                                                           __builtin_bit_cast(half8, fb[0]), acc[t], 0, 0, 0);
+        } else if constexpr (MT == MT_BF16) {
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
+                                                            __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
+        } else if constexpr (MT == MT_BF16X3) {
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
+                                                            __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
+                                                            __builtin_bit_cast(bf16x8, fb[1]), acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[1]),
+                                                            __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
+        } else {
+          acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(intx4, fa[0]),
+                                                          __builtin_bit_cast(intx4, fb[0]), acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
 }
 
 template <typename Tin, int MT, int MODE, int MAXT, int CPR, int CH, bool WEIGHTED>
@@ -306,8 +414,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 
   // --- accumulators
   constexpr int ACCN = IS_MFMA ? 16 : 16;
-  using AccV = typename std::conditional<BIN, intx16, floatx16>::type;
-  AccV acc[MAXT];
+  AccVec<MT> acc[MAXT];
   AccE vacc[IS_MFMA ? 1 : MAXT][IS_MFMA ? 1 : ACCN];
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) {
@@ -324,48 +431,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 
   auto compute_slab = [&](const unsigned char* lbuf) {
     if constexpr (IS_MFMA) {
-      constexpr int KSTEPS = KS / TR::KK;
-      constexpr int FE = 16 / TR::EB;   // elements per lane per fragment (16 bytes)
-      constexpr int KUNR = KSTEPS > 4 ? 4 : KSTEPS;   // bounded unroll: fragments stay few
-#pragma unroll KUNR
-      for (int kk = 0; kk < KSTEPS; ++kk) {
-        const int koff = kk * TR::KK + (lane >> 5) * FE;   // element offset in the row
-        uint4 fa[TR::PLANES], fb[TR::PLANES];
-#pragma unroll
-        for (int t = 0; t < MAXT; ++t) {
-          if (t < nt) {
-            const bool newa = (t == 0) || (ir[t] != ir[t - 1]);
-            const bool newb = (t == 0) || (ic[t] != ic[t - 1]);
-            if (newa) {
-              const unsigned char* pa = lbuf + (size_t)(ir[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
-              fa[0] = *reinterpret_cast<const uint4*>(pa);
-              if constexpr (TR::PLANES == 2) fa[1] = *reinterpret_cast<const uint4*>(pa + PLANE);
-            }
-            if (newb) {
-              const unsigned char* pb = lbuf + (size_t)(jrow_base + ic[t] * 32 + (lane & 31)) * ROWB + koff * TR::EB;
-              fb[0] = *reinterpret_cast<const uint4*>(pb);
-              if constexpr (TR::PLANES == 2) fb[1] = *reinterpret_cast<const uint4*>(pb + PLANE);
-            }
-            if constexpr (MT == MT_F16) {
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, fa[0]),
-                                                               __builtin_bit_cast(half8, fb[0]), acc[t], 0, 0, 0);
-            } else if constexpr (MT == MT_BF16) {
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
-                                                                __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
-            } else if constexpr (MT == MT_BF16X3) {
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
-                                                                __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]),
-                                                                __builtin_bit_cast(bf16x8, fb[1]), acc[t], 0, 0, 0);
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[1]),
-                                                                __builtin_bit_cast(bf16x8, fb[0]), acc[t], 0, 0, 0);
-            } else {
-              acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(intx4, fa[0]),
-                                                              __builtin_bit_cast(intx4, fb[0]), acc[t], 0, 0, 0);
-            }
-          }
-        }
-      }
+      mfma_slab_reuse<MT, MAXT, KS, ROWB>(lbuf, PLANE, lane, nt, ir, ic, jrow_base, acc);
     } else {
       // Vector FMA: lane owns a 4x4 block of each 32x32 sub-tile
       // (rows 4*(lane/8) .. +3, cols 4*(lane%8) .. +3).
@@ -479,6 +545,320 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 // Launch one instantiation; the caller has checked that the combination is
 // supported.  maxt: register tiles per wave (5 for one diagonal super-tile of
 // 5..8 row blocks, else 2).
+// LDS-staged Gram kernel (soft input, 16-bit MFMA types; rows 16-byte aligned
+// and ending on a 16-byte boundary).  Super-tiles, splits, sub-tile runs, the
+// MFMA loop and the outputs are those of gram_kernel; the loader differs.
+// Each wave streams 32 rows of every slab (128 bytes per row) straight into a
+// ring of NB LDS slots with loads to LDS, so NB - 1 slabs are in flight
+// without holding registers.  Per slab, one pass converts the slot into the
+// MFMA tile (isovalue model, sqrt(w), rounding) and adds the masses; the
+// tile is then multiplied.  Rows past N, points past M and slabs past the
+// split's share are read with an offset beyond the buffer's range: they land
+// as zeros without a memory access, so no load sits under a branch that
+// depends on the data and the wait counts are constants.
+template <typename Tin, int MT, int MODE, int MAXT, bool WEIGHTED, int NB, int NT, int NW>
+__global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
+  using TR = MTraits<MT>;
+  constexpr int SEG = 128;                    // bytes of a row per slab
+  constexpr int EPC = 16 / (int)sizeof(Tin);  // elements per 16-byte chunk
+  constexpr int KS = SEG / (int)sizeof(Tin);  // points per slab
+  constexpr int ROWB = KS * TR::EB + 16;      // LDS tile row stride (padded)
+  constexpr uint32_t OOB = 0x80000000u;
+  constexpr int RW = 256 / NW;                // staged rows per wave (32 or 16)
+  constexpr int LW = RW / 8;                  // row loads per slab and wave
+  constexpr int NTH = 64 * NW;                // threads
+  constexpr int DW = LW + (WEIGHTED ? 1 : 0); // loads per slab of wave 0 (rows, weights)
+  static_assert(MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3, "16-bit MFMA types");
+  static_assert((NB - 2) * DW <= 63, "wait count");
+  extern __shared__ __align__(16) unsigned char lds[];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = wave_id();
+
+  // --- XCD-aware decode of the block index (as in gram_kernel)
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int q = b >> 3;
+  const int st = q % a.ntiles_super;
+  const int split = (q / a.ntiles_super) * 8 + xcd;
+  int SI, SJ;
+  super_ij(st, SI, SJ);
+  const bool diag = (SI == SJ);
+  const int na = min(a.sb, a.nbt - a.sb * SI);
+  const int nb = min(a.sb, a.nbt - a.sb * SJ);
+  const int rowsI = 32 * na;
+  const int rows = diag ? rowsI : rowsI + 32 * nb;
+  const int PLANE = rows * ROWB;
+
+  const int T = diag ? na * (na + 1) / 2 : na * nb;
+  const int t0 = (wave * T) / NW, t1 = ((wave + 1) * T) / NW;
+  const int nt = t1 - t0;
+  int ir[MAXT], ic[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    int k = min(t0 + t, T - 1);
+    if (diag) {
+      int c = 0;
+      while ((c + 1) * (c + 2) / 2 <= k) ++c;
+      ic[t] = c;
+      ir[t] = k - c * (c + 1) / 2;
+    } else {
+      ir[t] = k / nb;
+      ic[t] = k % nb;
+    }
+  }
+  const int64_t cnt = (a.slabs > split) ? (a.slabs - 1 - split) / a.nsplit + 1 : 0;
+  auto grow = [&](int lrow) -> int {
+    return (lrow < rowsI) ? (32 * a.sb * SI + lrow) : (32 * a.sb * SJ + lrow - rowsI);
+  };
+
+  // --- LDS: ring [NB][rows][SEG], NT tiles [PLANES][rows][ROWB], masses
+  // [rows], weights [NB][64]
+  unsigned char* stage = lds;
+  unsigned char* tiles = stage + (size_t)NB * rows * SEG;
+  auto tile_of = [&](int64_t j) -> unsigned char* { return tiles + (size_t)(j % NT) * TR::PLANES * PLANE; };
+  double* lmass = reinterpret_cast<double*>(tiles + (size_t)NT * TR::PLANES * PLANE);
+  float* wsl = reinterpret_cast<float*>(lmass + rows);
+
+  // --- loads: wave w streams staging rows [RW w, RW w + RW) (inside one
+  // 32-row block, so all in the I or the J range), eight rows per instruction
+  const bool loader = RW * wave < rows;
+  const int g0 = loader ? grow(RW * wave) : 0;            // first global row of the wave
+  const int nvalid = loader ? max(0, min(RW, a.n - g0)) : 0;
+  const Tin* Ub = reinterpret_cast<const Tin*>(a.U) + (int64_t)(nvalid > 0 ? g0 : 0) * a.ld;
+  const BufRes rsU = make_bufres(Ub, (uint32_t)(((int64_t)max(nvalid - 1, 0) * a.ld + a.m) * (int64_t)sizeof(Tin)));
+  const BufRes rsW = make_bufres(a.w, (uint32_t)(a.m * (int64_t)sizeof(float)));
+  const uint32_t ldb = (uint32_t)(a.ld * (int64_t)sizeof(Tin));
+  const int lr8 = lane >> 3;                 // row within an instruction
+  const int lc = lane & 7;                   // 16-byte chunk within the row segment
+  auto issue = [&](int64_t j) {
+    const int64_t s = split + j * a.nsplit;
+    const bool ok = j < cnt;
+    if (loader) {
+      const bool pok = ok && s * KS + lc * EPC < a.m;
+#pragma unroll
+      for (int i = 0; i < LW; ++i) {
+        const int r = 8 * i + lr8;
+        const uint32_t vo = (pok && r < nvalid) ? (uint32_t)r * ldb + (uint32_t)(s * SEG) + (uint32_t)lc * 16u : OOB;
+        dma_to_lds<16>(rsU, stage + ((size_t)(j % NB) * rows + RW * wave + 8 * i) * SEG, vo);
+      }
+    }
+    if constexpr (WEIGHTED) {
+      if (wave == 0) {
+        const int64_t x = s * KS + lane;
+        const uint32_t vo = (ok && lane < KS && x < a.m) ? (uint32_t)(x * 4) : OOB;
+        dma_to_lds<4>(rsW, wsl + (size_t)(j % NB) * 64, vo);
+      }
+    }
+  };
+  // at most K slabs of this wave's loads still in flight
+  auto wait_slab_n = [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    if (WEIGHTED && wave == 0) vm_wait<K * DW>();
+    else if (loader) vm_wait<K * LW>();
+  };
+  // the slab about to be used has landed (NB - 2 later ones may be in flight)
+  auto wait_slab = [&]() { wait_slab_n(std::integral_constant<int, NB - 2>()); };
+
+  // masses (diagonal super-tiles): the 8 lanes of a row add their chunk
+  // sums (fixed butterfly); the first adds the row sum in FP64, slab by slab
+  for (int r = tid; r < rows; r += NTH) lmass[r] = 0.0;
+
+  // Convert slot j (slab s) into its tile.
+  auto convert = [&](int64_t j) {
+    const int64_t s = split + j * a.nsplit;
+    const unsigned char* src = stage + (size_t)(j % NB) * rows * SEG;
+    unsigned char* tile = tile_of(j);
+    for (int qq = tid; qq < rows * 8; qq += NTH) {
+      const int row = qq >> 3, c = qq & 7;
+      const Vec16<Tin> raw = *reinterpret_cast<const Vec16<Tin>*>(src + (size_t)row * SEG + c * 16);
+      const int64_t x0 = s * KS + c * EPC;
+      const bool rv = grow(row) < a.n;
+      float msum = 0.f;
+      float uv[EPC];
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) {
+        float u = extract_f<MODE>(raw.v[e], a.ex);
+        if constexpr (MODE != MODE_NONE) u = (rv && x0 + e < a.m) ? u : 0.f;   // zeros read past the ends
+        if constexpr (WEIGHTED) {
+          const float wv = wsl[(size_t)(j % NB) * 64 + c * EPC + e];
+          msum += wv * u;
+          uv[e] = sqrtf(wv) * u;
+        } else {
+          msum += u;
+          uv[e] = u;
+        }
+      }
+      unsigned char* d = tile + (size_t)row * ROWB + (size_t)c * EPC * TR::EB;
+      if constexpr (MT == MT_F16) {
+        f16 o[EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) o[e] = (f16)uv[e];
+        store_lds<2 * EPC>(d, o);
+      } else if constexpr (MT == MT_BF16) {
+        uint16_t o[EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) o[e] = f32_to_bf16_bits(uv[e]);
+        store_lds<2 * EPC>(d, o);
+      } else {
+        uint16_t hi[EPC], lo[EPC];
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+          hi[e] = f32_to_bf16_bits(uv[e]);
+          lo[e] = f32_to_bf16_bits(uv[e] - bf16_bits_to_f32(hi[e]));
+        }
+        store_lds<2 * EPC>(d, hi);
+        store_lds<2 * EPC>(d + PLANE, lo);
+      }
+      if (diag) {
+#pragma unroll
+        for (int o = 4; o >= 1; o >>= 1) msum += __shfl_xor(msum, o, 64);
+        if (c == 0) lmass[row] += (double)msum;
+      }
+    }
+  };
+
+  AccVec<MT> acc[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0;
+  const int jrow_base = diag ? 0 : rowsI;
+
+  if constexpr (NT == 1) {
+    // one tile: convert, barrier, multiply
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j) issue(j);
+    for (int64_t j = 0; j < cnt; ++j) {
+      wait_slab();
+      lds_barrier();            // every wave's rows of slab j are in LDS; the tile is free
+      issue(j + NB - 1);        // into the slot converted in the previous step
+      convert(j);
+      lds_barrier();            // the tile is complete
+      mfma_slab<MT, MAXT, KS, ROWB>(tile_of(j), PLANE, lane, nt, ir, ic, jrow_base, acc);
+    }
+  } else {
+    // two tiles: slab j + 1 is converted while slab j is multiplied, one
+    // barrier per slab (it also separates the multiply of slab j - 1 from
+    // the conversion that overwrites its tile)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) issue(j);
+    if (cnt > 0) {
+      wait_slab_n(std::integral_constant<int, NB - 1>());
+      lds_barrier();
+      convert(0);
+    }
+    for (int64_t j = 0; j < cnt; ++j) {
+      wait_slab();              // slab j + 1
+      lds_barrier();            // slab j + 1 is in LDS, tile j is complete, tile j + 1 is free
+      issue(j + NB);            // into the slot of slab j, converted in the previous step
+      if (j + 1 < cnt) convert(j + 1);
+      mfma_slab<MT, MAXT, KS, ROWB>(tile_of(j), PLANE, lane, nt, ir, ic, jrow_base, acc);
+    }
+  }
+  vm_wait<0>();               // no load into LDS outlives the workgroup
+
+  // --- partial sub-tiles
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    if (t < nt) {
+      const int R = a.sb * SI + ir[t], C = a.sb * SJ + ic[t];
+      const size_t pidx = ((size_t)split * a.np + (size_t)(C * (C + 1) / 2 + R)) * 1024;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int jj = lane & 31;
+        reinterpret_cast<float*>(a.part)[pidx + i * 32 + jj] = acc[t][r];
+      }
+    }
+  }
+  // --- partial masses (rows of the I side of diagonal super-tiles)
+  if (diag) {
+    lds_barrier();
+    for (int r = tid; r < rowsI; r += NTH) {
+      const int gr = 32 * a.sb * SI + r;
+      if (gr < a.n) a.part_mass[(size_t)split * a.n + gr] = lmass[r];
+    }
+  }
+}
+
+// LDS bytes of gram_dma_kernel for a workgroup of `rows` staged rows.
+template <typename Tin, int MT, int NT>
+constexpr int gram_dma_nb() {
+  constexpr int KS = 128 / (int)sizeof(Tin);
+  constexpr int ROWB = KS * MTraits<MT>::EB + 16;
+  constexpr int fixed = NT * MTraits<MT>::PLANES * 256 * ROWB + 256 * 8 + 4 * 256;
+  constexpr int nb = (163840 - fixed) / (256 * 128 + 256);
+  return nb > 4 ? 4 : nb;
+}
+template <typename Tin, int MT, int NT>
+size_t gram_dma_lds(int rows, bool weighted) {
+  constexpr int KS = 128 / (int)sizeof(Tin);
+  constexpr int ROWB = KS * MTraits<MT>::EB + 16;
+  constexpr int NB = gram_dma_nb<Tin, MT, NT>();
+  return (size_t)NB * rows * 128 + (size_t)NT * MTraits<MT>::PLANES * rows * ROWB + (size_t)rows * 8 +
+         (weighted ? (size_t)NB * 256 : 0);
+}
+
+// Launch the LDS-staged kernel when it applies (soft input in FP32, FP16 or
+// BF16 with a 16-bit MFMA type, aligned rows ending on a 16-byte boundary,
+// offsets within 2^31); returns false otherwise.
+template <typename Tin, int MT, int MODE>
+bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStream_t st) {
+  if constexpr (!((MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) && sizeof(Tin) <= 4 && sizeof(Tin) >= 2)) {
+    return false;
+  } else {
+    static const bool enabled = [] {
+      const char* v = getenv("PID_TUNE_GRAM_DMA");
+      return v == nullptr || atoi(v) != 0;
+    }();
+    constexpr int eb = sizeof(Tin);
+    if (!enabled || !ga0.vec || (ga0.m * eb) % 16 != 0) return false;
+    if (((int64_t)31 * ga0.ld + ga0.m) * eb >= (INT64_C(1) << 31) || ga0.m * 4 >= (INT64_C(1) << 31)) return false;
+    static const int ntiles = [] {
+      const char* v = getenv("PID_TUNE_GRAM_TILES");
+      return (v != nullptr && atoi(v) == 2) ? 2 : 1;
+    }();
+    GramArgs ga = ga0;
+    ga.slabs = (ga0.m * eb + 127) / 128;   // 128-byte slabs of every row
+    const bool w = ga.w != nullptr;
+    static const int nwaves = [] {
+      const char* v = getenv("PID_TUNE_GRAM_WAVES");
+      return (v != nullptr && atoi(v) == 8) ? 8 : 16;
+    }();
+    auto go = [&](auto k, size_t lds, int threads) {
+      static const bool attr = (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    163840) == hipSuccess);
+      (void)attr;
+      hipLaunchKernelGGL(k, grid, threads, lds, st, ga);
+    };
+    // sub-tiles per wave: at most 36 over 8 waves (5) or over 16 waves (3)
+    auto pick = [&](auto ntc) {
+      constexpr int NT = decltype(ntc)::value;
+      constexpr int NB = gram_dma_nb<Tin, MT, NT>();
+      static_assert(NB >= 2, "LDS ring");
+      const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w);
+      if (nwaves == 16) {
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16>, lds, 1024);
+        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16>, lds, 1024);
+      } else if (maxt > 2) {
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 5, true, NB, NT, 8>, lds, 512);
+        else go(gram_dma_kernel<Tin, MT, MODE, 5, false, NB, NT, 8>, lds, 512);
+      } else {
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 2, true, NB, NT, 8>, lds, 512);
+        else go(gram_dma_kernel<Tin, MT, MODE, 2, false, NB, NT, 8>, lds, 512);
+      }
+    };
+    // one tile by default (faster with 16 waves); two where asked for and the
+    // ring still holds three slots
+    constexpr bool two_ok = gram_dma_nb<Tin, MT, 2>() >= 3;
+    if (ntiles == 1 || !two_ok) pick(std::integral_constant<int, 1>());
+    else if constexpr (two_ok) pick(std::integral_constant<int, 2>());
+    return true;
+  }
+}
+
 template <typename Tin, int MT, int MODE, bool W>
 void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
   constexpr int EB = sizeof(Tin);
@@ -505,6 +885,7 @@ void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
 template <typename Tin, int MT, int MODE>
 void launch_gram_t(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
   KernelTimer tm("gram", st);
+  if (launch_gram_dma<Tin, MT, MODE>(ga, maxt, rows, grid, st)) return;
   if constexpr (MT == MT_I8) launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st);
   else if (ga.w != nullptr) launch_gram_w<Tin, MT, MODE, true>(ga, maxt, rows, grid, lds, st);
   else launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st);

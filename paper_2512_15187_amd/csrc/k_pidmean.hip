@@ -418,9 +418,8 @@ __global__ __launch_bounds__(512) void pidmean_dma_kernel(
 
   // resources based at the wave's first row; the host has checked that all
   // offsets stay below 2^31
-  const __amdgpu_buffer_rsrc_t rsU = buffer_rsrc(
-      U + (int64_t)mbase * ld, (uint32_t)(((int64_t)(nrows - 1) * ld + m) * (int64_t)sizeof(T)));
-  const __amdgpu_buffer_rsrc_t rsW = buffer_rsrc(w, (uint32_t)(m * (int64_t)sizeof(float)));
+  const BufRes rsU = make_bufres(U + (int64_t)mbase * ld, (uint32_t)(((int64_t)(nrows - 1) * ld + m) * (int64_t)sizeof(T)));
+  const BufRes rsW = make_bufres(w, (uint32_t)(m * (int64_t)sizeof(float)));
   const uint32_t ldb = (uint32_t)(ld * (int64_t)sizeof(T));
   const int lrow = lane >> 3;               // row within a load instruction
   const uint32_t lbyte = (uint32_t)(lane & 7) * 16u;
@@ -435,12 +434,12 @@ __global__ __launch_bounds__(512) void pidmean_dma_kernel(
     for (int j = 0; j < RPW / RPI; ++j) {
       const int r = j * RPI + lrow;
       const uint32_t vo = (pok && r < nrows) ? (uint32_t)r * ldb + xb : OOB;
-      dma_to_lds<16>(rsU, dst + (size_t)j * RPI * SEG, vo, 0u);
+      dma_to_lds<16>(rsU, dst + (size_t)j * RPI * SEG, vo);
     }
     if constexpr (WEIGHTED) {
       const int64_t x = t * TPP + lane;
       const uint32_t vo = (tok && lane < TPP && x < m) ? (uint32_t)(x * 4) : OOB;
-      dma_to_lds<4>(rsW, slot_w(k), vo, 0u);
+      dma_to_lds<4>(rsW, slot_w(k), vo);
     }
   };
 
