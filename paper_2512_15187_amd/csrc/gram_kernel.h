@@ -2,6 +2,7 @@
 // the algorithm); included by the per-input-type translation units.
 #pragma once
 #include "device_common.h"
+#include <hip/hip_ext.h>
 #include "pid_internal.h"
 #include "pid_timing.h"
 
@@ -805,7 +806,7 @@ size_t gram_dma_lds(int rows, bool weighted) {
 // BF16 with a 16-bit MFMA type, aligned rows ending on a 16-byte boundary,
 // offsets within 2^31); returns false otherwise.
 template <typename Tin, int MT, int MODE>
-bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStream_t st) {
+bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStream_t st, const KernelTimer& tm) {
   if constexpr (!((MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) && sizeof(Tin) <= 4 && sizeof(Tin) >= 2)) {
     return false;
   } else {
@@ -831,7 +832,7 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
       static const bool attr = (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                     163840) == hipSuccess);
       (void)attr;
-      hipLaunchKernelGGL(k, grid, threads, lds, st, ga);
+      hipExtLaunchKernelGGL(k, dim3(grid), dim3(threads), (uint32_t)lds, st, tm.start(), tm.stop(), 0u, ga);
     };
     // sub-tiles per wave: at most 36 over 8 waves (5) or over 16 waves (3)
     auto pick = [&](auto ntc) {
@@ -860,7 +861,8 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
 }
 
 template <typename Tin, int MT, int MODE, bool W>
-void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
+void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st,
+                   const KernelTimer& tm) {
   constexpr int EB = sizeof(Tin);
   constexpr int EPC = 16 / EB;
   constexpr int MB = (MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) ? 2 : (MT == MT_I8 ? 1 : (MT == MT_F32 ? 4 : 8));
@@ -872,7 +874,7 @@ void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
     static const bool attr = (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                   163840) == hipSuccess);
     (void)attr;
-    hipLaunchKernelGGL(k, grid, 512, lds, st, ga);
+    hipExtLaunchKernelGGL(k, dim3(grid), dim3(512), (uint32_t)lds, st, tm.start(), tm.stop(), 0u, ga);
   };
   if (maxt > 2) go(gram_kernel<Tin, MT, MODE, 5, CPR, CH256, W>);
   else if (rows > 128) go(gram_kernel<Tin, MT, MODE, 2, CPR, CH256, W>);
@@ -884,11 +886,11 @@ void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
 // 5..8 row blocks, else 2).  INT8 runs are unweighted.
 template <typename Tin, int MT, int MODE>
 void launch_gram_t(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
-  KernelTimer tm("gram", st);
-  if (launch_gram_dma<Tin, MT, MODE>(ga, maxt, rows, grid, st)) return;
-  if constexpr (MT == MT_I8) launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st);
-  else if (ga.w != nullptr) launch_gram_w<Tin, MT, MODE, true>(ga, maxt, rows, grid, lds, st);
-  else launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st);
+  KernelTimer tm("gram", st, /*by_launch=*/true);
+  if (launch_gram_dma<Tin, MT, MODE>(ga, maxt, rows, grid, st, tm)) return;
+  if constexpr (MT == MT_I8) launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st, tm);
+  else if (ga.w != nullptr) launch_gram_w<Tin, MT, MODE, true>(ga, maxt, rows, grid, lds, st, tm);
+  else launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st, tm);
 }
 
 // Per-input-type dispatchers (one translation unit each); return false when

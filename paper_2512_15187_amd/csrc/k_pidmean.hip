@@ -13,6 +13,7 @@
 // input uses exact integers throughout.  Per-workgroup partials are reduced
 // in a fixed order by pidmean_reduce, and pidmean_ratios forms the depths.
 #include "device_common.h"
+#include <hip/hip_ext.h>
 #include "pid_internal.h"
 #include "pid_timing.h"
 
@@ -848,10 +849,10 @@ size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m) {
 
 template <typename T, int MODE, int MPW, bool W, int NWMAX>
 static void launch_soft_one(const MeanPlan& p, const pid_ensemble& e, const Extract& ex, bool vec,
-                            int nwaves, const void* sglob, double* part, hipStream_t st) {
+                            int nwaves, const void* sglob, double* part, hipStream_t st, const KernelTimer& tm) {
   const size_t lds = (size_t)2 * nwaves * (64 * Vec16<T>::N) * sizeof(ComputeT<T>);
-  hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, W, false, NWMAX>), dim3(p.grid), dim3(64 * nwaves),
-                     lds, st, reinterpret_cast<const T*>(e.data), e.ld, (int)e.n, e.m, e.weights, ex,
+  hipExtLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, W, false, NWMAX>), dim3(p.grid), dim3(64 * nwaves),
+                        (uint32_t)lds, st, tm.start(), tm.stop(), 0u, reinterpret_cast<const T*>(e.data), e.ld, (int)e.n, e.m, e.weights, ex,
                      p.ntiles, sglob, part, vec ? 1 : 0);
 }
 
@@ -860,18 +861,18 @@ static void launch_soft_t(const MeanPlan& p, const pid_ensemble& e, const Extrac
                           const void* sglob, double* part, hipStream_t st) {
   const T* U = reinterpret_cast<const T*>(e.data);
   const bool wtd = e.weights != nullptr;
-  KernelTimer tm("pidmean", st);
+  KernelTimer tm("pidmean", st, /*by_launch=*/true);   // one kernel per call
   if (p.pipe_lb) {   // the plan picks the pipelined kernel only where it is instantiated
     if constexpr (MODE != MODE_STEP && !std::is_same<T, uint8_t>::value && !(sizeof(T) == 8 && MPW == 32) &&
                   !(sizeof(T) == 2 && MODE == MODE_GAUSS) && MPW != 16) {
       constexpr int LB = (MPW == 4) ? 16 : (MPW == 8 ? 8 : 4);
       constexpr int NWM = (MPW == 32) ? 8 : 16;
       if (wtd)
-        hipLaunchKernelGGL((pidmean_pipe_kernel<T, MODE, MPW, LB, true, NWM>), dim3(p.pipe_grid),
-                           dim3(64 * p.nwaves), p.lds_bytes, st, U, e.ld, (int)e.n, e.m, e.weights, ex, part);
+        hipExtLaunchKernelGGL((pidmean_pipe_kernel<T, MODE, MPW, LB, true, NWM>), dim3(p.pipe_grid),
+                              dim3(64 * p.nwaves), (uint32_t)p.lds_bytes, st, tm.start(), tm.stop(), 0u, U, e.ld, (int)e.n, e.m, e.weights, ex, part);
       else
-        hipLaunchKernelGGL((pidmean_pipe_kernel<T, MODE, MPW, LB, false, NWM>), dim3(p.pipe_grid),
-                           dim3(64 * p.nwaves), p.lds_bytes, st, U, e.ld, (int)e.n, e.m, e.weights, ex, part);
+        hipExtLaunchKernelGGL((pidmean_pipe_kernel<T, MODE, MPW, LB, false, NWM>), dim3(p.pipe_grid),
+                              dim3(64 * p.nwaves), (uint32_t)p.lds_bytes, st, tm.start(), tm.stop(), 0u, U, e.ld, (int)e.n, e.m, e.weights, ex, part);
     }
     return;
   }
@@ -880,18 +881,18 @@ static void launch_soft_t(const MeanPlan& p, const pid_ensemble& e, const Extrac
     dim3 block(64 * p.nwaves);
     if (p.two_pass) {
       if (wtd)
-        hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, true, true, 8>), grid, block, 0, st, U,
+        hipExtLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, true, true, 8>), grid, block, 0u, st, tm.start(), tm.stop(), 0u, U,
                            e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles, sglob, part, vec ? 1 : 0);
       else
-        hipLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, false, true, 8>), grid, block, 0, st, U,
+        hipExtLaunchKernelGGL((pidmean_soft_kernel<T, MODE, MPW, false, true, 8>), grid, block, 0u, st, tm.start(), tm.stop(), 0u, U,
                            e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles, sglob, part, vec ? 1 : 0);
       return;
     }
     // single pass; 16 waves only where N needs them
-    if (p.nwaves > 8) { if (wtd) launch_soft_one<T, MODE, MPW, true, 16>(p, e, ex, vec, p.nwaves, sglob, part, st);
-                        else launch_soft_one<T, MODE, MPW, false, 16>(p, e, ex, vec, p.nwaves, sglob, part, st); }
-    else { if (wtd) launch_soft_one<T, MODE, MPW, true, 8>(p, e, ex, vec, p.nwaves, sglob, part, st);
-           else launch_soft_one<T, MODE, MPW, false, 8>(p, e, ex, vec, p.nwaves, sglob, part, st); }
+    if (p.nwaves > 8) { if (wtd) launch_soft_one<T, MODE, MPW, true, 16>(p, e, ex, vec, p.nwaves, sglob, part, st, tm);
+                        else launch_soft_one<T, MODE, MPW, false, 16>(p, e, ex, vec, p.nwaves, sglob, part, st, tm); }
+    else { if (wtd) launch_soft_one<T, MODE, MPW, true, 8>(p, e, ex, vec, p.nwaves, sglob, part, st, tm);
+           else launch_soft_one<T, MODE, MPW, false, 8>(p, e, ex, vec, p.nwaves, sglob, part, st, tm); }
   }
 }
 
@@ -901,9 +902,10 @@ static void launch_bin_t(const MeanPlan& p, const pid_ensemble& e, const Extract
   dim3 grid(p.grid, p.two_pass ? p.groups : 1);
   dim3 block(64 * p.nwaves);
   const T* U = reinterpret_cast<const T*>(e.data);
-  KernelTimer tm("pidmean", st);
+  KernelTimer tm("pidmean", st, /*by_launch=*/true);   // one kernel per call
 #define PB_LAUNCH(S)                                                                          \
-  hipLaunchKernelGGL((pidmean_bin_kernel<T, MODE, MPW, S, 8>), grid, block, p.lds_bytes, st, U,   \
+  hipExtLaunchKernelGGL((pidmean_bin_kernel<T, MODE, MPW, S, 8>), grid, block, (uint32_t)p.lds_bytes, st,    \
+                        tm.start(), tm.stop(), 0u, U,                                              \
                      e.ld, (int)e.n, e.m, ex, p.ntiles, sglob, part, vec ? 1 : 0)
   if (p.two_pass) PB_LAUNCH(true); else PB_LAUNCH(false);
 #undef PB_LAUNCH
@@ -979,13 +981,14 @@ static hipError_t launch_mean_finalize(const MeanPlan& p, const pid_ensemble& e,
 template <typename T>
 static void launch_dma(const MeanPlan& p, const pid_ensemble& e, double* part, hipStream_t st) {
   const T* U = reinterpret_cast<const T*>(e.data);
-  KernelTimer tm("pidmean", st);
+  KernelTimer tm("pidmean", st, /*by_launch=*/true);
   auto go = [&](auto kern) {
     // allow up to 160 KB of LDS, once per kernel
     static const bool attr = (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                   163840) == hipSuccess);
     (void)attr;
-    hipLaunchKernelGGL(kern, dim3(p.dma_grid), dim3(64 * p.dma_nwaves), p.dma_lds, st, U, e.ld, (int)e.n, e.m,
+    hipExtLaunchKernelGGL(kern, dim3(p.dma_grid), dim3(64 * p.dma_nwaves), (uint32_t)p.dma_lds, st, tm.start(),
+                          tm.stop(), 0u, U, e.ld, (int)e.n, e.m,
                        e.weights, part);
   };
   const bool wtd = e.weights != nullptr;

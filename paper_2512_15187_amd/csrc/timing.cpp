@@ -57,19 +57,26 @@ void resolve_locked() {
 
 namespace pidk {
 
-KernelTimer::KernelTimer(const char* name, hipStream_t st) : name_(name), st_(st) {
+KernelTimer::KernelTimer(const char* name, hipStream_t st, bool by_launch)
+    : name_(name), st_(st), by_launch_(by_launch) {
   if (!g_on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_sel.empty() && g_sel.find(name) == g_sel.end()) return;
   a_ = take_event();
   b_ = take_event();
-  if (a_ && b_) hipEventRecord(a_, st_);
+  if (!a_ || !b_) {
+    if (a_) g_pool.push_back(a_);
+    if (b_) g_pool.push_back(b_);
+    a_ = b_ = nullptr;
+    return;
+  }
+  if (!by_launch_) hipEventRecord(a_, st_);
 }
 
 KernelTimer::~KernelTimer() {
   if (!a_ || !b_) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  hipEventRecord(b_, st_);
+  if (!by_launch_) hipEventRecord(b_, st_);
   g_pending.push_back({name_, a_, b_});
 }
 
