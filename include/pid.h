@@ -124,10 +124,10 @@ typedef struct {
   int32_t* order;
 } pid_out;
 
-/* Bytes of device workspace needed by pid_all_pairs (variant 0) or pid_mean
- * (variant 1) for this ensemble, isovalue model and scheme.  The size depends
- * on n, m, dtype, iso kind, weights (NULL or not) and scheme only.
- * iso may be NULL (= PID_ISO_NONE). */
+/* Bytes of device workspace needed by pid_all_pairs (variant 0), pid_mean
+ * (variant 1) or pid_both (variant 2) for this ensemble, isovalue model and
+ * scheme.  The size depends on n, m, dtype, iso kind, weights (NULL or not)
+ * and scheme only.  iso may be NULL (= PID_ISO_NONE). */
 pid_status pid_workspace_size(const pid_ensemble* ens, const pid_iso* iso, int variant,
                               int gemm, size_t* bytes);
 
@@ -148,6 +148,21 @@ pid_status pid_all_pairs(const pid_ensemble* ens, const pid_iso* iso, int gemm,
  * out->inclusion is ignored. */
 pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out,
                     void* workspace, size_t ws_bytes, void* stream);
+
+/* All-pairs PID and PID-mean of one ensemble (Sec. 3.2 with the weighted
+ * sums of Sec. 3.4, and Sec. 4.1) in one call: pairs_out as pid_all_pairs
+ * with `gemm`, mean_out as pid_mean.  Where the Gram kernel holds every member
+ * of a slab of points at once (N <= 256, soft masks with PID_ISO_NONE, a
+ * 16-bit MFMA scheme, rows 16-byte aligned and ending on a 16-byte boundary),
+ * it also forms the PID-mean numerators A_i = sum_x w u_i s (s = column sums,
+ * Sec. 4.1) from the FP32/FP16 values it streams, so the ensemble is read
+ * once; otherwise the PID-mean kernels run after it.  pairs_out results are
+ * bitwise those of pid_all_pairs; mean_out agrees with pid_mean within the
+ * FP32 tolerance of its sums (the masses are shared with the all-pairs
+ * result).  Workspace: pid_workspace_size(variant 2).  Errors as
+ * pid_all_pairs; both output structs are required (their fields may be NULL). */
+pid_status pid_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* pairs_out,
+                    const pid_out* mean_out, void* workspace, size_t ws_bytes, void* stream);
 
 /* Fuzzy-contour extraction alone (Sec. 3.5): writes u = model(value) for the
  * N x M ensemble into `u_out` (dense N x M, row stride M) as float (out_dtype

@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "pid_workspace_size": ([P(pid_ensemble), P(pid_iso), I32, I32, P(ctypes.c_size_t)], I32),
         "pid_all_pairs": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_mean": ([P(pid_ensemble), P(pid_iso), P(pid_out), V, ctypes.c_size_t, V], I32),
+        "pid_both": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_extract": ([P(pid_ensemble), P(pid_iso), V, I32, V], I32),
         "pid_rank": ([V, I64, V, V, V], I32),
         "pid_server_create": ([I32, V, ctypes.c_size_t, I32, P(V)], I32),
@@ -221,6 +222,23 @@ def pid_mean(U, weights=None, iso=None, workspace=None, stream=None, validate=Fa
     return d
 
 
+def pid_both(U, weights=None, iso=None, gemm="auto", inclusion=True, workspace=None, stream=None,
+             validate=False):
+    """All-pairs PID and PID-mean in one call (one pass over the ensemble
+    where the Gram kernel can form both).  Returns (pairs dict, mean dict)."""
+    lib = load_library()
+    e, i = make_ensemble(U, weights, validate), make_iso(iso)
+    ws_n = ctypes.c_size_t(0)
+    _check(lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 2, GEMM[gemm], ctypes.byref(ws_n)))
+    ws = _workspace(ws_n.value, U.device, workspace)
+    dp, op = _outputs(U.shape[0], U.device, inclusion)
+    dm, om = _outputs(U.shape[0], U.device, False)
+    _check(lib.pid_both(ctypes.byref(e), ctypes.byref(i), GEMM[gemm], ctypes.byref(op), ctypes.byref(om),
+                        ctypes.c_void_p(ws.data_ptr()), ws_n.value, _stream_ptr(stream)))
+    dp["_workspace"] = ws
+    return dp, dm
+
+
 def pid_extract(U, iso, out_dtype=torch.float32, stream=None):
     """Membership probabilities (N x M dense) from stored values."""
     lib = load_library()
@@ -250,11 +268,12 @@ def pid_rank(depth, stream=None):
 class PreparedCall:
     """One depth call with its structs, outputs and workspace allocated once,
     so that repeated ``run()`` calls allocate nothing (benchmark loops,
-    serving drivers).  variant: "pairs" or "mean"."""
+    serving drivers).  variant: "pairs", "mean" or "both" (then ``out`` holds
+    the all-pairs results and ``out_mean`` the PID-mean ones)."""
 
     def __init__(self, variant, U, weights=None, iso=None, gemm="auto", inclusion=False):
         lib = load_library()
-        self.variant = 0 if variant == "pairs" else 1
+        self.variant = {"pairs": 0, "mean": 1, "both": 2}[variant]
         self.gemm = GEMM[gemm]
         self.e, self.i = make_ensemble(U, weights), make_iso(iso)
         n = ctypes.c_size_t(0)
@@ -262,7 +281,9 @@ class PreparedCall:
                                       ctypes.byref(n)))
         self.ws_bytes = n.value
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=U.device)
-        self.out, self.o = _outputs(U.shape[0], U.device, inclusion and self.variant == 0)
+        self.out, self.o = _outputs(U.shape[0], U.device, inclusion and self.variant != 1)
+        if self.variant == 2:
+            self.out_mean, self.om = _outputs(U.shape[0], U.device, False)
         self._keep = (U, weights)
 
     def run(self, stream=None):
@@ -272,9 +293,12 @@ class PreparedCall:
         if self.variant == 0:
             _check(lib.pid_all_pairs(ctypes.byref(self.e), ctypes.byref(self.i), self.gemm, ctypes.byref(self.o),
                                      ws, self.ws_bytes, st))
-        else:
+        elif self.variant == 1:
             _check(lib.pid_mean(ctypes.byref(self.e), ctypes.byref(self.i), ctypes.byref(self.o), ws,
                                 self.ws_bytes, st))
+        else:
+            _check(lib.pid_both(ctypes.byref(self.e), ctypes.byref(self.i), self.gemm, ctypes.byref(self.o),
+                                ctypes.byref(self.om), ws, self.ws_bytes, st))
         return self.out
 
 

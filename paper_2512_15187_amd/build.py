@@ -68,7 +68,9 @@ def check_m0(asm_path: str):
 def resource_report(remarks: str):
     """(kernel, vgprs, scratch bytes per lane) from -Rpass-analysis remarks."""
     out = []
-    for block in re.split(r"remark: Function Name: ", remarks)[1:]:
+    # (the remark prefix differs with -save-temps: "file:l:c: remark: Function
+    # Name:" or "remark: file:l:c: Function Name:")
+    for block in re.split(r"Function Name: ", remarks)[1:]:
         name = block.split()[0]
         v = re.search(r"VGPRs: (\d+)", block)
         sc = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", block)
@@ -83,6 +85,8 @@ def build(verbose: bool = False) -> str:
         results = list(ex.map(_compile, SOURCES))
     objs = [o for o, _ in results]
     report = [r for _, rem in results for r in resource_report(rem)]
+    if not report:
+        raise RuntimeError("no kernel resource remarks were parsed")
     with open(REPORT, "w") as fh:
         for name, vgpr, scratch in report:
             fh.write(f"{name}\tvgpr={vgpr}\tscratch={scratch}\n")

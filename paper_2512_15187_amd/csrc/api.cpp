@@ -112,20 +112,22 @@ pid_status resolve_scheme(const pid_ensemble* e, int kind, int gemm, int* scheme
   }
 }
 
-// Extra workspace after the kernels' own: depth scratch (for ranks) and the
-// validation flag.
-size_t extra_bytes(int64_t n) { return ((size_t)n * 8 + 255) / 256 * 256 + 256 + 256; }
+// Extra workspace after the kernels' own: depth scratch (for ranks; two
+// arrays for the combined call) and the validation flag.
+size_t extra_bytes(int64_t n, int ndepth = 1) {
+  return ((size_t)n * 8 * ndepth + 255) / 256 * 256 + 256 + 256;
+}
 
 struct Extras {
   double* depth;
   unsigned int* flag;
 };
 
-Extras carve_extras(void* ws, size_t kernel_bytes, int64_t n) {
+Extras carve_extras(void* ws, size_t kernel_bytes, int64_t n, int ndepth = 1) {
   char* base = static_cast<char*>(ws) + ((kernel_bytes + 255) / 256) * 256;
   Extras x;
   x.depth = reinterpret_cast<double*>(base);
-  x.flag = reinterpret_cast<unsigned int*>(base + ((size_t)n * 8 + 255) / 256 * 256);
+  x.flag = reinterpret_cast<unsigned int*>(base + ((size_t)n * 8 * ndepth + 255) / 256 * 256);
   return x;
 }
 
@@ -180,15 +182,71 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
   } else if (variant == 1) {
     pidk::MeanPlan p = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
     kb = pidk::mean_workspace(p, ens->n, ens->m);
+  } else if (variant == 2) {
+    size_t kp = 0, km = 0;
+    s = workspace_size(ens, iso, 0, gemm, &kp);
+    if (s != PID_OK) return s;
+    s = workspace_size(ens, iso, 1, gemm, &km);
+    if (s != PID_OK) return s;
+    kb = kp + km;   // all-pairs workspace, then the PID-mean one (used when the pass cannot be shared)
   } else {
-    return fail(PID_ERR_INVALID_ARG, "variant must be 0 (all-pairs) or 1 (PID-mean)");
+    return fail(PID_ERR_INVALID_ARG, "variant must be 0 (all-pairs), 1 (PID-mean) or 2 (both)");
   }
-  *bytes = ((kb + 255) / 256) * 256 + extra_bytes(ens->n);
+  *bytes = ((kb + 255) / 256) * 256 + extra_bytes(ens->n, variant == 2 ? 2 : 1);
+  return PID_OK;
+}
+
+// All-pairs and PID-mean outputs of one ensemble; one pass over it where the
+// Gram kernel can also form the PID-mean numerators.
+pid_status run_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* pairs_out,
+                    const pid_out* mean_out, void* ws, size_t ws_bytes, void* stream) {
+  int kind = 0;
+  pid_status s = check_ensemble(ens, iso, &kind);
+  if (s != PID_OK) return s;
+  if (!pairs_out || !mean_out) return fail(PID_ERR_INVALID_ARG, "pairs_out or mean_out is NULL");
+  if (!ws) return fail(PID_ERR_INVALID_ARG, "workspace is NULL");
+  size_t need = 0, kp = 0;
+  s = workspace_size(ens, iso, 2, gemm, &need);
+  if (s != PID_OK) return s;
+  if (ws_bytes < need)
+    return fail(PID_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  workspace_size(ens, iso, 0, gemm, &kp);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Extras x = carve_extras(ws, need - extra_bytes(ens->n, 2), ens->n, 2);
+  if (ens->flags & PID_FLAG_VALIDATE) {
+    s = run_validate(ens, kind, x.flag, st);
+    if (s != PID_OK) return s;
+  }
+  pid_out po = *pairs_out, mo = *mean_out;
+  const bool rank_p = po.rank || po.order, rank_m = mo.rank || mo.order;
+  if (rank_p && !po.depth) po.depth = x.depth;
+  if (rank_m && !mo.depth) mo.depth = x.depth + ens->n;
+  pidk::ExtractHost ex = make_extract(iso);
+  int scheme = 0;
+  resolve_scheme(ens, kind, gemm, &scheme);
+  pidk::PairsPlan p = pidk::pairs_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr, scheme);
+  bool fused = false;
+  hipError_t err = pidk::launch_pid_pairs(p, *ens, kind, ex, po, ws, st, &mo, &fused);
+  if (err != hipSuccess) return hip_fail(err, "pid_both all-pairs launch");
+  if (!fused) {
+    pidk::MeanPlan mp = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
+    err = pidk::launch_pid_mean(mp, *ens, kind, ex, mo, static_cast<char*>(ws) + kp, st);
+    if (err != hipSuccess) return hip_fail(err, "pid_both PID-mean launch");
+  }
+  if (rank_p) {
+    err = pidk::launch_rank(po.depth, ens->n, po.rank, po.order, st);
+    if (err != hipSuccess) return hip_fail(err, "rank launch");
+  }
+  if (rank_m) {
+    err = pidk::launch_rank(mo.depth, ens->n, mo.rank, mo.order, st);
+    if (err != hipSuccess) return hip_fail(err, "rank launch");
+  }
   return PID_OK;
 }
 
 pid_status run(int variant, const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* out,
                void* ws, size_t ws_bytes, void* stream) {
+  if (variant != 0 && variant != 1) return fail(PID_ERR_INVALID_ARG, "variant must be 0 or 1 here");
   int kind = 0;
   pid_status s = check_ensemble(ens, iso, &kind);
   if (s != PID_OK) return s;
@@ -245,6 +303,11 @@ pid_status pid_all_pairs(const pid_ensemble* ens, const pid_iso* iso, int gemm, 
 pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out, void* workspace,
                     size_t ws_bytes, void* stream) {
   return pidapi::run(1, ens, iso, PID_GEMM_AUTO, out, workspace, ws_bytes, stream);
+}
+
+pid_status pid_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* pairs_out,
+                    const pid_out* mean_out, void* workspace, size_t ws_bytes, void* stream) {
+  return pidapi::run_both(ens, iso, gemm, pairs_out, mean_out, workspace, ws_bytes, stream);
 }
 
 pid_status pid_extract(const pid_ensemble* ens, const pid_iso* iso, void* u_out, int out_dtype,

@@ -259,6 +259,15 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Round an FP32 value to FP16 as a separate step.  The value passes through
+// an empty asm first, so the compiler cannot fuse the product that produced
+// it with the conversion (a mixed-precision FMA rounds once, the two steps
+// twice), and every kernel variant rounds the same way.
+__device__ __forceinline__ _Float16 to_f16_rounded(float v) {
+  asm volatile("" : "+v"(v));
+  return (_Float16)v;
+}
+
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // ---- wavefront (64-lane) sums; fixed butterfly order => deterministic ----

@@ -39,18 +39,22 @@ constexpr int RED_GROUPS = 8;
 
 template <typename PT>
 __global__ __launch_bounds__(256) void gram_reduce(const PT* __restrict__ part,
-                                                   const double* __restrict__ part_mass, int nsplit,
-                                                   int np, int n, double* __restrict__ G,
-                                                   double* __restrict__ mass) {
+                                                   const double* __restrict__ part_mass, int64_t mass_stride,
+                                                   int nsplit, int np, int n, double* __restrict__ G,
+                                                   double* __restrict__ mass, int nrows_extra) {
   __shared__ double red[RED_GROUPS][RED_ELEMS];
   const int64_t tot = (int64_t)np * 1024;
   const int el = threadIdx.x % RED_ELEMS;
   const int g = threadIdx.x / RED_ELEMS;
   const int64_t e = (int64_t)blockIdx.x * RED_ELEMS + el;
   const bool is_mass = e >= tot;
+  // elements: the packed sub-tiles, then n masses, then (fused PID-mean) n
+  // numerators, which follow the masses of each split in part_mass and the
+  // masses in mass
+  const int64_t nx = (int64_t)n * nrows_extra;
   double s = 0.0;
-  if (e < tot + n) {
-    const size_t stride = is_mass ? (size_t)n : (size_t)np * 1024;
+  if (e < tot + nx) {
+    const size_t stride = is_mass ? (size_t)mass_stride : (size_t)np * 1024;
     const size_t base = is_mass ? (size_t)(e - tot) : (size_t)e;
     int k = g;
     for (; k + 3 * RED_GROUPS < nsplit; k += 4 * RED_GROUPS) {
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(256) void gram_reduce(const PT* __restrict__ part,
   }
   red[g][el] = s;
   __syncthreads();
-  if (g != 0 || e >= tot + n) return;
+  if (g != 0 || e >= tot + nx) return;
   double t = 0.0;
 #pragma unroll
   for (int q = 0; q < RED_GROUPS; ++q) t += red[q][el];
@@ -261,14 +265,15 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
 size_t pairs_workspace(const PairsPlan& p, int64_t n) {
   Carve c(nullptr);
   c.take<char>((size_t)p.nsplit * p.np * 1024 * p.part_elem);
-  c.take<double>((size_t)p.nsplit * n);   // partial masses
-  c.take<double>((size_t)n * n);          // G
-  c.take<double>((size_t)n);              // masses
+  c.take<double>((size_t)p.nsplit * n * 2);   // partial masses, then partial PID-mean numerators
+  c.take<double>((size_t)n * n);              // G
+  c.take<double>((size_t)n * 2);              // masses, then PID-mean numerators
   return c.off + 256;
 }
 
 hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,
-                            const ExtractHost& exh, const pid_out& out, void* ws, hipStream_t st) {
+                            const ExtractHost& exh, const pid_out& out, void* ws, hipStream_t st,
+                            const pid_out* mean_out, bool* mean_done) {
   Carve c(ws);
   GramArgs ga{};
   ga.U = e.data;
@@ -285,9 +290,14 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   ga.nsplit = p.nsplit;
   ga.slabs = p.slabs;
   ga.part = c.take<char>((size_t)p.nsplit * p.np * 1024 * p.part_elem);
-  ga.part_mass = c.take<double>((size_t)p.nsplit * e.n);
+  // [nsplit][n] masses, then [nsplit][n] PID-mean numerators: the reduction
+  // treats them as one [nsplit][2n] array when the fused pass ran
+  double* pm = c.take<double>((size_t)p.nsplit * e.n * 2);
   double* G = c.take<double>((size_t)e.n * e.n);
-  double* mass = c.take<double>((size_t)e.n);
+  double* mass = c.take<double>((size_t)e.n * 2);
+  ga.part_mass = pm;
+  ga.mass_stride = mean_out ? 2 * e.n : e.n;
+  ga.part_meanA = mean_out ? pm + e.n : nullptr;
   const int eb = elem_bytes_g(e.dtype);
   ga.vec = (((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
             (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0)) ? 1 : 0;
@@ -295,38 +305,47 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   const int mode = iso_kind == PID_ISO_GAUSSIAN ? MODE_GAUSS : (iso_kind == PID_ISO_STEP ? MODE_STEP : MODE_NONE);
   const int grid = p.nsplit * p.ntiles_super;
   const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;   // most rows a workgroup loads
-  bool ok = false;
+  bool ok = false, fused = false;
   switch (e.dtype) {
-    case PID_F64: ok = gram_dispatch_f64(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
-    case PID_F32: ok = gram_dispatch_f32(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
-    case PID_F16: ok = gram_dispatch_f16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
-    case PID_BF16: ok = gram_dispatch_bf16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
-    default: ok = gram_dispatch_u8(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    case PID_F64: ok = gram_dispatch_f64(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
+    case PID_F32: ok = gram_dispatch_f32(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
+    case PID_F16: ok = gram_dispatch_f16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
+    case PID_BF16: ok = gram_dispatch_bf16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
+    default: ok = gram_dispatch_u8(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
   }
   if (!ok) return hipErrorNotSupported;
+  if (mean_done) *mean_done = fused;
+  const int extra = fused ? 2 : 1;   // reduce the numerators with the masses
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const int64_t work = (int64_t)p.np * 1024 + e.n;
+  const int64_t work = (int64_t)p.np * 1024 + e.n * extra;
   const int rgrid = (int)((work + RED_ELEMS - 1) / RED_ELEMS);
   {
   KernelTimer tm("gram_reduce", st);
   if (p.part_elem == 8)
-    hipLaunchKernelGGL(gram_reduce<double>, rgrid, 256, 0, st, (const double*)ga.part, ga.part_mass,
-                       p.nsplit, p.np, (int)e.n, G, mass);
+    hipLaunchKernelGGL(gram_reduce<double>, rgrid, 256, 0, st, (const double*)ga.part, ga.part_mass, ga.mass_stride,
+                       p.nsplit, p.np, (int)e.n, G, mass, extra);
   else if (mtype_of(p.scheme) == MT_I8)
-    hipLaunchKernelGGL(gram_reduce<int>, rgrid, 256, 0, st, (const int*)ga.part, ga.part_mass,
-                       p.nsplit, p.np, (int)e.n, G, mass);
+    hipLaunchKernelGGL(gram_reduce<int>, rgrid, 256, 0, st, (const int*)ga.part, ga.part_mass, ga.mass_stride,
+                       p.nsplit, p.np, (int)e.n, G, mass, extra);
   else
-    hipLaunchKernelGGL(gram_reduce<float>, rgrid, 256, 0, st, (const float*)ga.part, ga.part_mass,
-                       p.nsplit, p.np, (int)e.n, G, mass);
+    hipLaunchKernelGGL(gram_reduce<float>, rgrid, 256, 0, st, (const float*)ga.part, ga.part_mass, ga.mass_stride,
+                       p.nsplit, p.np, (int)e.n, G, mass, extra);
   }
   if (out.inclusion) {
     KernelTimer tm("pairs_inclusion", st);
     hipLaunchKernelGGL(pairs_inclusion, (int)e.n, 256, 0, st, G, mass, (int)e.n, out.inclusion);
   }
+  {
   KernelTimer tm("pairs_depths", st);
   hipLaunchKernelGGL(pairs_depths, (int)e.n, 64, 0, st, G, mass, (int)e.n,
                      out.mass, out.in_in, out.in_out, out.depth);
+  }
+  if (fused) {
+    hipError_t err2 = hipGetLastError();
+    if (err2 != hipSuccess) return err2;
+    return launch_mean_ratios(mass, e.n, *mean_out, st);
+  }
   return hipGetLastError();
 }
 

@@ -77,8 +77,14 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
 size_t pairs_workspace(const PairsPlan& p, int64_t n);
 // True when the Gram kernel is built for this input dtype, scheme and iso kind.
 bool pairs_supported(int dtype, int iso_kind, int scheme);
+// mean_out non-null: also form the PID-mean outputs in the same pass where
+// the fused form applies; *mean_done reports whether it did (else the caller
+// runs the PID-mean kernels).
 hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,
-                            const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st);
+                            const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st,
+                            const pid_out* mean_out = nullptr, bool* mean_done = nullptr);
+// PID-mean ratios from m (n doubles) followed by A (n doubles).
+hipError_t launch_mean_ratios(const double* m_then_a, int64_t n, const pid_out& out, hipStream_t st);
 
 // ---------------------------------------------------------------- misc
 hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, void* u_out,

@@ -18,7 +18,7 @@ def _lib():
 def test_exports_every_declared_symbol():
     lib = _lib()
     names = pid.declared_symbols()
-    expected = {"pid_workspace_size", "pid_all_pairs", "pid_mean", "pid_extract", "pid_rank",
+    expected = {"pid_workspace_size", "pid_all_pairs", "pid_mean", "pid_both", "pid_extract", "pid_rank",
                 "pid_server_create", "pid_submit", "pid_poll", "pid_wait", "pid_request_times",
                 "pid_server_destroy", "pid_status_string", "pid_last_error", "pid_abi_version",
                 "pid_timing_enable", "pid_timing_get", "pid_timing_select"}
@@ -75,6 +75,9 @@ def test_scheme_checks_on_host():
         == pid.PID_ERR_INVALID_ARG
     assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 3, 0, ctypes.byref(nbytes)) \
         == pid.PID_ERR_INVALID_ARG
+    # the combined call needs both output structs
+    assert lib.pid_both(ctypes.byref(e), ctypes.byref(i), 0, None, None, ctypes.c_void_p(0x1000), 1 << 20,
+                        None) == pid.PID_ERR_INVALID_ARG
     # NULL pointers
     assert lib.pid_all_pairs(None, None, 0, None, None, 0, None) == pid.PID_ERR_INVALID_ARG
     assert lib.pid_rank(None, 3, None, None, None) == pid.PID_ERR_INVALID_ARG

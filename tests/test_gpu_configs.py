@@ -57,6 +57,17 @@ def test_config1_pid_mean(c1):
     assert_ranks(res["rank"], ref["depth"], TOL_F32, label="C1 mean")
 
 
+def test_config1_both_in_one_pass(c1):
+    """The benchmark step: all-pairs (FP16 Gram) and PID-mean from one call."""
+    U, ref = c1
+    rp, rm = pid.pid_both(U, gemm="f16")
+    assert_close(rp, ref, TOL_MIXED, label="C1 both pairs")
+    assert_ranks(rp["rank"], ref["depth"], TOL_MIXED, label="C1 both pairs")
+    refm = oracle.pid_mean_large(_host(U).numpy())
+    assert_close(rm, refm, TOL_F32, label="C1 both mean")
+    assert_ranks(rm["rank"], refm["depth"], TOL_F32, label="C1 both mean")
+
+
 def test_config1_bf16_single_pass_error_is_reported(c1):
     """One BF16 pass on FP32 masks is less accurate than 1e-4 can promise; the
     split scheme exists for that.  Record its error, bounded loosely."""

@@ -263,3 +263,34 @@ def test_rank_entry_point():
     rank, order = pid.pid_rank(_dev(d))
     r, o = oracle.rank_order(d.numpy())
     assert rank.cpu().tolist() == r.tolist() and order.cpu().tolist() == o.tolist()
+
+
+# ------------------------------------------------------------------ both in one call
+BOTH_CASES = [
+    # (n, m, dtype, weighted, gemm)  -- the first three share one pass, the rest fall back
+    (256, 32 * 1000, torch.float32, False, "f16"),
+    (200, 32 * 777 + 20, torch.float32, True, "f16"),
+    (64, 64 * 300, torch.float16, True, "f16"),
+    (130, 32 * 500, torch.float32, False, "bf16_split"),
+    (300, 4000, torch.float16, False, "f16"),      # several super-tiles
+    (37, 5003, torch.float32, True, "f16"),        # row ends not on 16 bytes
+    (50, 4096, torch.float64, False, "f64"),       # FP64 scheme
+]
+
+
+@pytest.mark.parametrize("n,m,dtype,weighted,gemm", BOTH_CASES,
+                         ids=[f"{c[0]}x{c[1]}-{str(c[2])[6:]}-{'w' if c[3] else 'u'}-{c[4]}" for c in BOTH_CASES])
+def test_pid_both(n, m, dtype, weighted, gemm):
+    """pid_both: all-pairs results bitwise those of pid_all_pairs; PID-mean
+    results within the FP32 (FP64) tolerance of the oracle."""
+    U = _soft(n, m, 400 + n, dtype)
+    w = _weights(m, 9) if weighted else None
+    Ud, wd = _dev(U), (None if w is None else _dev(w))
+    rp, rm = pid.pid_both(Ud, wd, gemm=gemm)
+    alone = pid.pid_all_pairs(Ud, wd, gemm=gemm)
+    for key in ("inclusion", "mass", "in_in", "in_out", "depth", "rank", "order"):
+        assert torch.equal(rp[key], alone[key]), key
+    ref = oracle.pid_mean(_ref_input(U), None if w is None else w.numpy())
+    tol = TOL_F64 if dtype == torch.float64 else TOL_F32
+    assert_close(rm, ref, tol, label=f"both mean {n}x{m}")
+    assert_ranks(rm["rank"], ref["depth"], tol, label="both mean")
