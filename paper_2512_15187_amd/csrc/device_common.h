@@ -287,6 +287,68 @@ __device__ __forceinline__ long long wave_sum(long long v) {
   return v;
 }
 
+// ---- sums across lanes without the LDS crossbar ----
+// DPP moves (within rows of 16 lanes) and the gfx950 lane swaps
+// (v_permlane16_swap / v_permlane32_swap) run in the vector ALU; every lane
+// of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+// Sum over each aligned group of eight lanes, the same bits in all eight.
+__device__ __forceinline__ float sum8(float v) {
+  v += dpp_f<0xB1>(v);    // lane ^ 1 (quad_perm 1,0,3,2)
+  v += dpp_f<0x4E>(v);    // lane ^ 2 (quad_perm 2,3,0,1)
+  v += dpp_f<0x141>(v);   // lane 7 - l of the group (row_half_mirror)
+  return v;
+}
+// Lanes below 32 (resp. in even rows of 16) get x + x of the lane 32 (16)
+// above; the others get y of the lane 32 (16) below + their own y.
+__device__ __forceinline__ float fold32(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float fold16(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// Column sums over the eight row lanes of a wave.  Lane 8r + c holds E
+// values v[e] (points c*E + e, summed over its rows).  Halving the values
+// at each step (lanes ^ 32, ^ 16, ^ 8), lane l ends with the sum over the
+// lanes l ^ 8k of point c*E + col_point<E>(l); for E < 8 lanes l and l ^ 8
+// (and l ^ 16 for E = 2) hold the same point and the same bits.
+template <int E>
+__device__ __forceinline__ int col_point(int lane) {
+  static_assert(E == 2 || E == 4 || E == 8, "values per lane");
+  const int b3 = (lane >> 3) & 1, b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
+  if constexpr (E == 8) return 4 * b3 + 2 * b4 + b5;
+  else if constexpr (E == 4) return 2 * b4 + b5;
+  else return b5;
+}
+template <int E>
+__device__ __forceinline__ bool col_writer(int lane) {
+  if constexpr (E == 8) return true;
+  else if constexpr (E == 4) return (lane & 8) == 0;
+  else return (lane & 24) == 0;
+}
+template <int E>
+__device__ __forceinline__ float col_reduce(const float (&v)[E], int lane) {
+  static_assert(E == 2 || E == 4 || E == 8, "values per lane");
+  if constexpr (E == 2) {
+    float a = fold32(v[0], v[1]);
+    a = fold16(a, a);
+    return a + dpp_f<0x128>(a);                    // lane ^ 8 (row_ror:8)
+  } else if constexpr (E == 4) {
+    const float b = fold16(fold32(v[0], v[1]), fold32(v[2], v[3]));
+    return b + dpp_f<0x128>(b);
+  } else {
+    const float b0 = fold16(fold32(v[0], v[1]), fold32(v[2], v[3]));
+    const float b1 = fold16(fold32(v[4], v[5]), fold32(v[6], v[7]));
+    const bool hi = (lane & 8) != 0;
+    return (hi ? b1 : b0) + dpp_f<0x128>(hi ? b0 : b1);
+  }
+}
+
 // ---- float -> 16-bit conversions (round to nearest even) ----
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
   // Round-to-nearest-even on the upper 16 bits; inputs here are finite

@@ -743,21 +743,14 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
         store_lds<2 * EPC>(d + PLANE, lo);
       }
       if (diag) {
-#pragma unroll
-        for (int o = 4; o >= 1; o >>= 1) msum += __shfl_xor(msum, o, 64);
+        msum = sum8(msum);
         if (c == 0) lmass[row] += (double)msum;
       }
     }
     if constexpr (MEAN) {
       // lanes 8r + c hold chunk column c of rows r: add the wave's 8 rows
-#pragma unroll
-      for (int e = 0; e < EPC; ++e) {
-        float v = cp[e];
-        v += __shfl_xor(v, 8, 64);
-        v += __shfl_xor(v, 16, 64);
-        v += __shfl_xor(v, 32, 64);
-        if (lane < 8) wsum[wave * KS + lane * EPC + e] = v;
-      }
+      const float v = col_reduce<EPC>(cp, lane);
+      if (col_writer<EPC>(lane)) wsum[wave * KS + (lane & 7) * EPC + col_point<EPC>(lane)] = v;
     }
   };
   // Column sums of the slab from the per-wave sums (one lane per point).
@@ -778,8 +771,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
       float t = 0.f;
 #pragma unroll
       for (int e = 0; e < EPC; ++e) t += wkeep[e] * ukeep[ci][e] * sv[c * EPC + e];
-#pragma unroll
-      for (int o = 4; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+      t = sum8(t);
       if (c == 0) lA[row] += (double)t;
     }
   };
