@@ -161,8 +161,8 @@ def headline(args):
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    breakdown = {k: kernel_ms(pid, k) for k in ("gram", "gram_reduce", "pairs_inclusion", "pairs_depths",
-                                                 "pidmean", "pidmean_finalize", "rank")
+    breakdown = {k: kernel_ms(pid, k) for k in ("gram", "gram_reduce", "pairs_finish", "pidmean",
+                                                 "pidmean_finalize", "rank")
                  if kernel_ms(pid, k)[1] > 0}
     pid.pid_timing_enable(False)
     log(f"step {t_step * 1e3:.3f} ms; gram {kt['gram'][0] * 1e3:.1f} us in the timed region; breakdown " +

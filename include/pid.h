@@ -193,6 +193,12 @@ typedef struct {
   pid_ensemble ens;
   pid_iso iso;
   pid_out out;
+  /* Optional hipEvent_t (NULL: none).  The request's kernels run on the
+   * server's own streams; when set, its slot stream waits for this event
+   * (hipStreamWaitEvent at admission) before them, so inputs that the
+   * caller's stream is still producing are complete when read.  The event
+   * must stay valid until the request has started. */
+  void* ready;
 } pid_request;
 
 pid_status pid_server_create(int device, void* arena, size_t arena_bytes, int max_slots,
@@ -215,9 +221,10 @@ pid_status pid_server_destroy(pid_server* server);
  * stream.  pid_timing_enable() clears the accumulated times (and waits for
  * pending events); pid_timing_get() waits for the pending events and returns
  * the total milliseconds and launch count of one kernel: "gram" (all-pairs
- * numerators), "gram_reduce", "pairs_inclusion", "pairs_depths", "pidmean"
- * (the streaming PID-mean pass), "pidmean_colsum", "pidmean_finalize",
- * "rank", "extract".  Unknown names report 0. */
+ * numerators), "gram_reduce", "pairs_finish" (inclusion rows, depths and,
+ * after a fused pass, the PID-mean ratios), "pidmean" (the streaming PID-mean
+ * pass), "pidmean_colsum", "pidmean_finalize", "rank", "extract".  Unknown
+ * names report 0. */
 pid_status pid_timing_enable(int on);
 pid_status pid_timing_get(const char* kernel, double* total_ms, int64_t* launches);
 /* Restrict timing to a comma-separated list of the kernel names above (so
@@ -228,7 +235,7 @@ pid_status pid_timing_select(const char* names);
 /* Diagnostics. */
 const char* pid_status_string(pid_status s);
 const char* pid_last_error(void);   /* thread-local text of the last failed call */
-int pid_abi_version(void);          /* 1 */
+int pid_abi_version(void);          /* 2 */
 
 #ifdef __cplusplus
 }

@@ -64,7 +64,7 @@ class pid_out(ctypes.Structure):
 
 class pid_request(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("gemm", ctypes.c_int32), ("ens", pid_ensemble),
-                ("iso", pid_iso), ("out", pid_out)]
+                ("iso", pid_iso), ("out", pid_out), ("ready", ctypes.c_void_p)]
 
 
 _lib = None
@@ -342,10 +342,14 @@ class PidServer:
         lib = load_library()
         e, i = make_ensemble(U, weights), make_iso(iso)
         d, o = _outputs(U.shape[0], U.device, inclusion and variant == "pairs")
-        req = pid_request(0 if variant == "pairs" else 1, GEMM[gemm], e, i, o)
+        # the server's streams wait for the work queued so far on the current
+        # stream (the inputs and the output allocations)
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(U.device))
+        req = pid_request(0 if variant == "pairs" else 1, GEMM[gemm], e, i, o, ctypes.c_void_p(ev.cuda_event))
         t = ctypes.c_uint64(0)
         _check(lib.pid_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
-        self._keep[t.value] = (U, weights, d)
+        self._keep[t.value] = (U, weights, d, ev)
         return t.value, d
 
     def pid_poll(self, ticket):

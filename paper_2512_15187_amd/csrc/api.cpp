@@ -233,12 +233,12 @@ pid_status run_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const
     err = pidk::launch_pid_mean(mp, *ens, kind, ex, mo, static_cast<char*>(ws) + kp, st);
     if (err != hipSuccess) return hip_fail(err, "pid_both PID-mean launch");
   }
-  if (rank_p) {
-    err = pidk::launch_rank(po.depth, ens->n, po.rank, po.order, st);
+  if (rank_p && rank_m) {
+    err = pidk::launch_rank2(po.depth, po.rank, po.order, mo.depth, mo.rank, mo.order, ens->n, st);
     if (err != hipSuccess) return hip_fail(err, "rank launch");
-  }
-  if (rank_m) {
-    err = pidk::launch_rank(mo.depth, ens->n, mo.rank, mo.order, st);
+  } else if (rank_p || rank_m) {
+    const pid_out& r = rank_p ? po : mo;
+    err = pidk::launch_rank(r.depth, ens->n, r.rank, r.order, st);
     if (err != hipSuccess) return hip_fail(err, "rank launch");
   }
   return PID_OK;
@@ -350,7 +350,7 @@ const char* pid_status_string(pid_status s) {
 
 const char* pid_last_error(void) { return g_last_error.c_str(); }
 
-int pid_abi_version(void) { return 1; }
+int pid_abi_version(void) { return 2; }
 
 }  // extern "C"
 

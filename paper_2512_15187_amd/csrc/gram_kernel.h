@@ -137,6 +137,57 @@ __device__ __forceinline__ void mfma_slab(const unsigned char* lbuf, int PLANE, 
   }
 }
 
+// acc += A B^T for one k-step of fragments (hi/lo planes for BF16x3).
+template <int MT, int PL>
+__device__ __forceinline__ void mfma_step(AccVec<MT>& acc, const uint4 (&fa)[PL], const uint4 (&fb)[PL]) {
+  if constexpr (MT == MT_F16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, fa[0]), __builtin_bit_cast(half8, fb[0]),
+                                                 acc, 0, 0, 0);
+  } else if constexpr (MT == MT_BF16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]), __builtin_bit_cast(bf16x8, fb[0]),
+                                                  acc, 0, 0, 0);
+  } else if constexpr (MT == MT_BF16X3) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]), __builtin_bit_cast(bf16x8, fb[0]),
+                                                  acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[0]), __builtin_bit_cast(bf16x8, fb[1]),
+                                                  acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[1]), __builtin_bit_cast(bf16x8, fb[0]),
+                                                  acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(intx4, fa[0]), __builtin_bit_cast(intx4, fb[0]),
+                                                acc, 0, 0, 0);
+  }
+}
+
+// Grouped sub-tiles of one wave (rows r0 against r1 and r2, and r2 against
+// itself when `three`): acc[0] += F(r0) F(r1)^T, acc[1] += F(r0) F(r2)^T,
+// acc[2] += F(r2) F(r2)^T.  Three fragment reads per k-step.
+template <int MT, int KS, int ROWB>
+__device__ __forceinline__ void mfma_slab_g(const unsigned char* lbuf, int PLANE, int lane, bool three, int r0,
+                                            int r1, int r2, AccVec<MT>* acc) {
+  using TR = MTraits<MT>;
+  constexpr int KSTEPS = KS / TR::KK;
+  constexpr int FE = 16 / TR::EB;
+  constexpr int KUNR = KSTEPS > 2 ? 2 : KSTEPS;
+#pragma unroll KUNR
+  for (int kk = 0; kk < KSTEPS; ++kk) {
+    const int koff = (kk * TR::KK + (lane >> 5) * FE) * TR::EB;
+    const unsigned char* p0 = lbuf + (size_t)(r0 * 32 + (lane & 31)) * ROWB + koff;
+    const unsigned char* p1 = lbuf + (size_t)(r1 * 32 + (lane & 31)) * ROWB + koff;
+    const unsigned char* p2 = lbuf + (size_t)(r2 * 32 + (lane & 31)) * ROWB + koff;
+    uint4 f0[TR::PLANES], f1[TR::PLANES], f2[TR::PLANES];
+#pragma unroll
+    for (int q = 0; q < TR::PLANES; ++q) {
+      f0[q] = *reinterpret_cast<const uint4*>(p0 + q * PLANE);
+      f1[q] = *reinterpret_cast<const uint4*>(p1 + q * PLANE);
+      f2[q] = *reinterpret_cast<const uint4*>(p2 + q * PLANE);
+    }
+    mfma_step<MT>(acc[0], f0, f1);
+    mfma_step<MT>(acc[1], f0, f2);
+    if (three) mfma_step<MT>(acc[2], f2, f2);
+  }
+}
+
 // The same with fragment reuse: a fragment is read once while consecutive
 // sub-tiles share it (fewer registers; used where registers also hold the
 // prefetched slab).
@@ -560,7 +611,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 // split's share are read with an offset beyond the buffer's range: they land
 // as zeros without a memory access, so no load sits under a branch that
 // depends on the data and the wait counts are constants.
-template <typename Tin, int MT, int MODE, int MAXT, bool WEIGHTED, int NB, int NT, int NW, bool MEAN>
+template <typename Tin, int MT, int MODE, int MAXT, bool WEIGHTED, int NB, int NT, int NW, bool MEAN, bool GRP>
 __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   using TR = MTraits<MT>;
   constexpr int SEG = 128;                    // bytes of a row per slab
@@ -603,20 +654,48 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   const int PLANE = rows * ROWB;
 
   const int T = diag ? na * (na + 1) / 2 : na * nb;
-  const int t0 = (wave * T) / NW, t1 = ((wave + 1) * T) / NW;
-  const int nt = t1 - t0;
+  int nt;
   int ir[MAXT], ic[MAXT];
-#pragma unroll
-  for (int t = 0; t < MAXT; ++t) {
-    int k = min(t0 + t, T - 1);
-    if (diag) {
-      int c = 0;
-      while ((c + 1) * (c + 2) / 2 <= k) ++c;
-      ic[t] = c;
-      ir[t] = k - c * (c + 1) / 2;
+  // One diagonal super-tile of eight row blocks with 16 waves: groups of 2x2
+  // blocks.  Wave g < 4 owns the diagonal group of blocks X = 2g, Y = X + 1
+  // (sub-tiles XX, XY, YY); the two waves of an off-diagonal group (a, b),
+  // a < b, own rows I = 2a + p against J = 2b and 2b + 1.  Either way the
+  // wave's sub-tiles are (ir0, ic0), (ir0, ic1) [, (ic1, ic1)], so it reads
+  // three fragments per k-step instead of two per sub-tile.
+  // (GRP: the host has checked that the only super-tile is diagonal with
+  // eight row blocks)
+  static_assert(!GRP || (NW == 16 && MAXT >= 3), "grouped sub-tiles: 16 waves, 3 tiles");
+  if constexpr (GRP) {
+    if (wave < 4) {
+      const int X = 2 * wave;
+      ir[0] = X; ic[0] = X;
+      ir[1] = X; ic[1] = X + 1;
+      ir[2] = X + 1; ic[2] = X + 1;
+      nt = 3;
     } else {
-      ir[t] = k / nb;
-      ic[t] = k % nb;
+      const int o = (wave - 4) >> 1, p = (wave - 4) & 1;   // groups (0,1) (0,2) (1,2) (0,3) (1,3) (2,3)
+      const int gb = (o >= 3) ? 3 : (o >= 1 ? 2 : 1);
+      const int ga = o - gb * (gb - 1) / 2;
+      const int I = 2 * ga + p;
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) { ir[t] = I; ic[t] = 2 * gb + min(t, 1); }
+      nt = 2;
+    }
+  } else {
+    const int t0 = (wave * T) / NW, t1 = ((wave + 1) * T) / NW;
+    nt = t1 - t0;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      int k = min(t0 + t, T - 1);
+      if (diag) {
+        int c = 0;
+        while ((c + 1) * (c + 2) / 2 <= k) ++c;
+        ic[t] = c;
+        ir[t] = k - c * (c + 1) / 2;
+      } else {
+        ir[t] = k / nb;
+        ic[t] = k % nb;
+      }
     }
   }
   const int64_t cnt = (a.slabs > split) ? (a.slabs - 1 - split) / a.nsplit + 1 : 0;
@@ -782,6 +861,10 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0;
   const int jrow_base = diag ? 0 : rowsI;
+  auto multiply = [&](const unsigned char* tl) {
+    if constexpr (GRP) mfma_slab_g<MT, KS, ROWB>(tl, PLANE, lane, nt == 3, ir[0], ic[0], ic[1], acc);
+    else mfma_slab<MT, MAXT, KS, ROWB>(tl, PLANE, lane, nt, ir, ic, jrow_base, acc);
+  };
 
   if constexpr (NT == 1) {
     // one tile: convert, barrier, multiply
@@ -797,7 +880,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
       convert(j);
       lds_barrier();            // the tile is complete
       if constexpr (MEAN) colsum();
-      mfma_slab<MT, MAXT, KS, ROWB>(tile_of(j), PLANE, lane, nt, ir, ic, jrow_base, acc);
+      multiply(tile_of(j));
     }
     if constexpr (MEAN) {
       if (cnt > 0) {
@@ -821,7 +904,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
       lds_barrier();            // slab j + 1 is in LDS, tile j is complete, tile j + 1 is free
       issue(j + NB);            // into the slot of slab j, converted in the previous step
       if (j + 1 < cnt) convert(j + 1);
-      mfma_slab<MT, MAXT, KS, ROWB>(tile_of(j), PLANE, lane, nt, ir, ic, jrow_base, acc);
+      multiply(tile_of(j));
     }
   }
   vm_wait<0>();               // no load into LDS outlives the workgroup
@@ -913,11 +996,18 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
       constexpr int NT = decltype(ntc)::value;
       constexpr int NB = gram_dma_nb<Tin, MT, NT>();
       static_assert(NB >= 2, "LDS ring");
+      // eight row blocks in one diagonal super-tile: grouped sub-tiles
+      const bool grp = nwaves == 16 && ga.nsuper == 1 && ga.nbt == 8;
       if constexpr (MODE == MODE_NONE && NT == 1) {
         if (want_mean && nwaves == 16 && ga.nsuper == 1) {
           const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w, true, 16);
-          if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true>, lds, 1024);
-          else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true>, lds, 1024);
+          if (grp) {
+            if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true, true>, lds, 1024);
+            else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true, true>, lds, 1024);
+          } else {
+            if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true, false>, lds, 1024);
+            else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true, false>, lds, 1024);
+          }
           *mean_done = true;
           return;
         }
@@ -925,14 +1015,21 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
       ga.part_meanA = nullptr;
       const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w, false, nwaves);
       if (nwaves == 16) {
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false>, lds, 1024);
-        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false>, lds, 1024);
+        if constexpr (NT == 1) {
+          if (grp) {
+            if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false, true>, lds, 1024);
+            else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false, true>, lds, 1024);
+            return;
+          }
+        }
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false, false>, lds, 1024);
+        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false, false>, lds, 1024);
       } else if (maxt > 2) {
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 5, true, NB, NT, 8, false>, lds, 512);
-        else go(gram_dma_kernel<Tin, MT, MODE, 5, false, NB, NT, 8, false>, lds, 512);
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 5, true, NB, NT, 8, false, false>, lds, 512);
+        else go(gram_dma_kernel<Tin, MT, MODE, 5, false, NB, NT, 8, false, false>, lds, 512);
       } else {
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 2, true, NB, NT, 8, false>, lds, 512);
-        else go(gram_dma_kernel<Tin, MT, MODE, 2, false, NB, NT, 8, false>, lds, 512);
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 2, true, NB, NT, 8, false, false>, lds, 512);
+        else go(gram_dma_kernel<Tin, MT, MODE, 2, false, NB, NT, 8, false, false>, lds, 512);
       }
     };
     // one tile by default (faster with 16 waves); two where asked for and the

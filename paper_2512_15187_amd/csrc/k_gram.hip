@@ -98,41 +98,47 @@ __global__ __launch_bounds__(256) void gram_reduce(const PT* __restrict__ part,
   G[(size_t)j * n + i] = t;
 }
 
-// Inclusion matrix P_ij = G_ij / m_i (0 when m_i = 0); one block per row.
-__global__ __launch_bounds__(256) void pairs_inclusion(const double* __restrict__ G,
-                                                       const double* __restrict__ mass, int n,
-                                                       double* __restrict__ P) {
-  const int i = blockIdx.x;
-  const double mi = mass[i];
-  for (int j = threadIdx.x; j < n; j += blockDim.x)
-    P[(size_t)i * n + j] = (mi > 0.0) ? G[(size_t)i * n + j] / mi : 0.0;
-}
-
-// Depths, one 64-lane block per member i:
+// Depths of member i:
 //   IN_in(i)  = S_i / (N m_i),  S_i = sum_j G_ij
 //   IN_out(i) = (sum_j G_ji / m_j) / N   (terms with m_j = 0 are 0)
 // The lanes form the terms (one correctly rounded division each) for a chunk
-// of j into LDS; lane 0 adds them in ascending j, which is the fixed order
+// of j into LDS; one lane adds them in ascending j, which is the fixed order
 // that makes binary results bitwise reproducible.
 constexpr int DEP_CHUNK = 1024;
 
-__global__ __launch_bounds__(64) void pairs_depths(const double* __restrict__ G,
-                                                   const double* __restrict__ mass, int n,
-                                                   double* __restrict__ m_out,
-                                                   double* __restrict__ in_in,
-                                                   double* __restrict__ in_out,
-                                                   double* __restrict__ depth) {
+// All per-member outputs after the reduction, one block of 256 threads per
+// member i: the inclusion row P_ij = G_ij / m_i (0 when m_i = 0; when asked
+// for), the depths above, and, after the fused PID-mean pass (meanA set),
+// IN_in = A_i / (N m_i) and IN_out = A_i / sum_k m_k (Sec. 4.1), with
+// sum_k m_k formed by every block in the fixed tree of pidmean_ratios.
+struct FinishArgs {
+  const double* G;
+  const double* mass;
+  const double* meanA;      // PID-mean numerators (n), or nullptr
+  int n;
+  double* P;
+  double *m_out, *in_in, *in_out, *depth;
+  double *mm_out, *mm_in, *mm_outo, *mm_depth;   // PID-mean outputs
+};
+
+__global__ __launch_bounds__(256) void pairs_finish(FinishArgs f) {
 #pragma clang fp contract(off)
   __shared__ double tg[DEP_CHUNK], to[DEP_CHUNK];
+  __shared__ double red[256];
   const int i = blockIdx.x;
   const int t = threadIdx.x;
-  const double* row = G + (size_t)i * n;   // G_ij = G_ji (symmetric)
+  const int n = f.n;
+  const double* row = f.G + (size_t)i * n;   // G_ij = G_ji (symmetric)
+  const double mi = f.mass[i];
+  if (f.P) {
+    for (int j = t; j < n; j += 256) f.P[(size_t)i * n + j] = (mi > 0.0) ? row[j] / mi : 0.0;
+  }
   double S = 0.0, O = 0.0;
   for (int j0 = 0; j0 < n; j0 += DEP_CHUNK) {
     const int cnt = min(DEP_CHUNK, n - j0);
-    for (int q = t; q < cnt; q += 64) {
+    for (int q = t; q < cnt; q += 256) {
       const double g = row[j0 + q];
-      const double mj = mass[j0 + q];
+      const double mj = f.mass[j0 + q];
       tg[q] = g;
       to[q] = (mj > 0.0) ? g / mj : 0.0;
     }
@@ -145,14 +151,32 @@ __global__ __launch_bounds__(64) void pairs_depths(const double* __restrict__ G,
     }
     __syncthreads();
   }
+  if (f.meanA) {
+    double md = 0.0;
+    for (int k = t; k < n; k += 256) md += f.mass[k];
+    red[t] = md;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+      if (t < o) red[t] += red[t + o];
+      __syncthreads();
+    }
+  }
   if (t != 0) return;
-  const double mi = mass[i];
   const double ii = (mi > 0.0) ? S / ((double)n * mi) : 0.0;
   const double oo = O / (double)n;
-  if (m_out) m_out[i] = mi;
-  if (in_in) in_in[i] = ii;
-  if (in_out) in_out[i] = oo;
-  if (depth) depth[i] = ii < oo ? ii : oo;
+  if (f.m_out) f.m_out[i] = mi;
+  if (f.in_in) f.in_in[i] = ii;
+  if (f.in_out) f.in_out[i] = oo;
+  if (f.depth) f.depth[i] = ii < oo ? ii : oo;
+  if (f.meanA) {
+    const double a = f.meanA[i], tot = red[0];
+    const double mii = (mi > 0.0) ? a / ((double)n * mi) : 0.0;
+    const double moo = (tot > 0.0) ? a / tot : 0.0;
+    if (f.mm_out) f.mm_out[i] = mi;
+    if (f.mm_in) f.mm_in[i] = mii;
+    if (f.mm_outo) f.mm_outo[i] = moo;
+    if (f.mm_depth) f.mm_depth[i] = mii < moo ? mii : moo;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -332,19 +356,20 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
     hipLaunchKernelGGL(gram_reduce<float>, rgrid, 256, 0, st, (const float*)ga.part, ga.part_mass, ga.mass_stride,
                        p.nsplit, p.np, (int)e.n, G, mass, extra);
   }
-  if (out.inclusion) {
-    KernelTimer tm("pairs_inclusion", st);
-    hipLaunchKernelGGL(pairs_inclusion, (int)e.n, 256, 0, st, G, mass, (int)e.n, out.inclusion);
-  }
   {
-  KernelTimer tm("pairs_depths", st);
-  hipLaunchKernelGGL(pairs_depths, (int)e.n, 64, 0, st, G, mass, (int)e.n,
-                     out.mass, out.in_in, out.in_out, out.depth);
-  }
-  if (fused) {
-    hipError_t err2 = hipGetLastError();
-    if (err2 != hipSuccess) return err2;
-    return launch_mean_ratios(mass, e.n, *mean_out, st);
+    KernelTimer tm("pairs_finish", st);
+    FinishArgs f{};
+    f.G = G;
+    f.mass = mass;
+    f.n = (int)e.n;
+    f.P = out.inclusion;
+    f.m_out = out.mass; f.in_in = out.in_in; f.in_out = out.in_out; f.depth = out.depth;
+    if (fused) {
+      f.meanA = mass + e.n;
+      f.mm_out = mean_out->mass; f.mm_in = mean_out->in_in; f.mm_outo = mean_out->in_out;
+      f.mm_depth = mean_out->depth;
+    }
+    hipLaunchKernelGGL(pairs_finish, (int)e.n, 256, 0, st, f);
   }
   return hipGetLastError();
 }

@@ -59,11 +59,19 @@ hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost
 // rank[i] = #{ j : d_j > d_i  or  (d_j == d_i and j < i) };  order[rank[i]] = i.
 // One wave per member: lanes compare strided j, popcounts of the ballots
 // give the count (an exact integer, so the result is order-independent).
-__global__ __launch_bounds__(256) void rank_kernel(const double* __restrict__ d, int n,
-                                                   int32_t* __restrict__ rank,
-                                                   int32_t* __restrict__ order) {
+// blockIdx.y selects one of two depth arrays (the second may be absent).
+struct RankArgs {
+  const double* d[2];
+  int32_t* rank[2];
+  int32_t* order[2];
+};
+
+__global__ __launch_bounds__(256) void rank_kernel(RankArgs ra, int n) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const double* __restrict__ d = ra.d[blockIdx.y];
+  int32_t* __restrict__ rank = ra.rank[blockIdx.y];
+  int32_t* __restrict__ order = ra.order[blockIdx.y];
   if (i >= n) return;                       // whole wave leaves together
   const double di = d[i];
   int r = 0;
@@ -84,7 +92,16 @@ __global__ __launch_bounds__(256) void rank_kernel(const double* __restrict__ d,
 
 hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st) {
   KernelTimer tm("rank", st);
-  hipLaunchKernelGGL(rank_kernel, (int)((n + 3) / 4), 256, 0, st, depth, (int)n, rank, order);
+  RankArgs ra{{depth, nullptr}, {rank, nullptr}, {order, nullptr}};
+  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((n + 3) / 4), 1), 256, 0, st, ra, (int)n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank2(const double* d0, int32_t* rank0, int32_t* order0, const double* d1, int32_t* rank1,
+                        int32_t* order1, int64_t n, hipStream_t st) {
+  KernelTimer tm("rank", st);
+  RankArgs ra{{d0, d1}, {rank0, rank1}, {order0, order1}};
+  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((n + 3) / 4), 2), 256, 0, st, ra, (int)n);
   return hipGetLastError();
 }
 

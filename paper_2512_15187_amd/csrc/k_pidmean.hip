@@ -978,13 +978,6 @@ static hipError_t launch_mean_finalize(const MeanPlan& p, const pid_ensemble& e,
   return hipGetLastError();
 }
 
-hipError_t launch_mean_ratios(const double* m_then_a, int64_t n, const pid_out& out, hipStream_t st) {
-  KernelTimer tm("pidmean_finalize", st);
-  hipLaunchKernelGGL(pidmean_ratios<false>, 1, 256, 0, st, m_then_a, (int)n, out.mass, out.in_in, out.in_out,
-                     out.depth);
-  return hipGetLastError();
-}
-
 template <typename T>
 static void launch_dma(const MeanPlan& p, const pid_ensemble& e, double* part, hipStream_t st) {
   const T* U = reinterpret_cast<const T*>(e.data);

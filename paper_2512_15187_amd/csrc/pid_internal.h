@@ -83,13 +83,14 @@ bool pairs_supported(int dtype, int iso_kind, int scheme);
 hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,
                             const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st,
                             const pid_out* mean_out = nullptr, bool* mean_done = nullptr);
-// PID-mean ratios from m (n doubles) followed by A (n doubles).
-hipError_t launch_mean_ratios(const double* m_then_a, int64_t n, const pid_out& out, hipStream_t st);
 
 // ---------------------------------------------------------------- misc
 hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, void* u_out,
                           int out_dtype, hipStream_t st);
 hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st);
+// Both rankings of pid_both in one launch.
+hipError_t launch_rank2(const double* d0, int32_t* rank0, int32_t* order0, const double* d1, int32_t* rank1,
+                        int32_t* order1, int64_t n, hipStream_t st);
 // Writes 0 to *flag_dev when all values pass, else a nonzero code.
 hipError_t launch_validate(const pid_ensemble& e, int iso_kind, unsigned int* flag_dev, hipStream_t st);
 

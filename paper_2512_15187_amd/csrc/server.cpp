@@ -166,6 +166,8 @@ struct pid_server {
         j->ws_off = off;
         j->slot = slot;
         j->t_start = now();
+        // inputs still being produced on the caller's stream
+        if (j->req.ready) hipStreamWaitEvent(streams[slot], reinterpret_cast<hipEvent_t>(j->req.ready), 0);
         pid_status st = pidapi::run(j->req.variant, &j->req.ens, &j->req.iso, j->req.gemm, &j->req.out,
                                     arena_base + off, j->ws_bytes, streams[slot]);
         running[slot] = j;

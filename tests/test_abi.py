@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
     assert expected <= set(names), set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pid_abi_version() == 1
+    assert lib.pid_abi_version() == 2
     assert lib.pid_status_string(5) == b"PID_ERR_VALUE_RANGE"
 
 
