@@ -150,17 +150,18 @@ pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* 
                     void* workspace, size_t ws_bytes, void* stream);
 
 /* All-pairs PID and PID-mean of one ensemble (Sec. 3.2 with the weighted
- * sums of Sec. 3.4, and Sec. 4.1) in one call: pairs_out as pid_all_pairs
- * with `gemm`, mean_out as pid_mean.  Where the Gram kernel holds every member
- * of a slab of points at once (N <= 256, soft masks with PID_ISO_NONE, a
- * 16-bit MFMA scheme, rows 16-byte aligned and ending on a 16-byte boundary),
- * it also forms the PID-mean numerators A_i = sum_x w u_i s (s = column sums,
- * Sec. 4.1) from the FP32/FP16 values it streams, so the ensemble is read
- * once; otherwise the PID-mean kernels run after it.  pairs_out results are
- * bitwise those of pid_all_pairs; mean_out agrees with pid_mean within the
- * FP32 tolerance of its sums (the masses are shared with the all-pairs
- * result).  Workspace: pid_workspace_size(variant 2).  Errors as
- * pid_all_pairs; both output structs are required (their fields may be NULL). */
+ * sums of Sec. 3.4, and Sec. 4.1) from one all-pairs pass.  pairs_out as
+ * pid_all_pairs with `gemm` (bitwise the same results).  The PID-mean
+ * numerators are the Gram row sums: A_i = sum_x w u_i(x) s(x) with
+ * s = sum_j u_j equals S_i = sum_j G_ij, so mean_out gets IN_in = S_i/(N m_i)
+ * (the all-pairs IN_in: the recall identity of Sec. 4.1) and
+ * IN_out = S_i / sum_k m_k (sum_k m_k by a fixed tree), with the masses of the
+ * same pass.  mean_out therefore has the accuracy of the `gemm` scheme:
+ * bitwise the oracle's integer forms for PID_GEMM_I8, within the mixed
+ * precision tolerance for FP16/BF16 (pid_mean keeps its FP32/FP64 sums).
+ * Workspace: pid_workspace_size(variant 2) (that of variant 0 plus room for
+ * a second depth array).  Errors as pid_all_pairs; both output structs are
+ * required (their fields may be NULL). */
 pid_status pid_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* pairs_out,
                     const pid_out* mean_out, void* workspace, size_t ws_bytes, void* stream);
 

@@ -224,8 +224,9 @@ def pid_mean(U, weights=None, iso=None, workspace=None, stream=None, validate=Fa
 
 def pid_both(U, weights=None, iso=None, gemm="auto", inclusion=True, workspace=None, stream=None,
              validate=False):
-    """All-pairs PID and PID-mean in one call (one pass over the ensemble
-    where the Gram kernel can form both).  Returns (pairs dict, mean dict)."""
+    """All-pairs PID and PID-mean in one call, from one all-pairs pass (the
+    PID-mean numerators are the Gram row sums).  Returns (pairs dict, mean
+    dict)."""
     lib = load_library()
     e, i = make_ensemble(U, weights, validate), make_iso(iso)
     ws_n = ctypes.c_size_t(0)

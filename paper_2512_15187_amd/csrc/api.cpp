@@ -183,12 +183,10 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
     pidk::MeanPlan p = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
     kb = pidk::mean_workspace(p, ens->n, ens->m);
   } else if (variant == 2) {
-    size_t kp = 0, km = 0;
-    s = workspace_size(ens, iso, 0, gemm, &kp);
+    size_t kp = 0;
+    s = workspace_size(ens, iso, 0, gemm, &kp);   // the all-pairs pass serves both
     if (s != PID_OK) return s;
-    s = workspace_size(ens, iso, 1, gemm, &km);
-    if (s != PID_OK) return s;
-    kb = kp + km;   // all-pairs workspace, then the PID-mean one (used when the pass cannot be shared)
+    kb = kp;
   } else {
     return fail(PID_ERR_INVALID_ARG, "variant must be 0 (all-pairs), 1 (PID-mean) or 2 (both)");
   }
@@ -196,8 +194,8 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
   return PID_OK;
 }
 
-// All-pairs and PID-mean outputs of one ensemble; one pass over it where the
-// Gram kernel can also form the PID-mean numerators.
+// All-pairs and PID-mean outputs of one ensemble from one all-pairs pass: the
+// PID-mean numerators are the Gram row sums.
 pid_status run_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* pairs_out,
                     const pid_out* mean_out, void* ws, size_t ws_bytes, void* stream) {
   int kind = 0;
@@ -205,12 +203,11 @@ pid_status run_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const
   if (s != PID_OK) return s;
   if (!pairs_out || !mean_out) return fail(PID_ERR_INVALID_ARG, "pairs_out or mean_out is NULL");
   if (!ws) return fail(PID_ERR_INVALID_ARG, "workspace is NULL");
-  size_t need = 0, kp = 0;
+  size_t need = 0;
   s = workspace_size(ens, iso, 2, gemm, &need);
   if (s != PID_OK) return s;
   if (ws_bytes < need)
     return fail(PID_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
-  workspace_size(ens, iso, 0, gemm, &kp);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Extras x = carve_extras(ws, need - extra_bytes(ens->n, 2), ens->n, 2);
   if (ens->flags & PID_FLAG_VALIDATE) {
@@ -225,14 +222,8 @@ pid_status run_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const
   int scheme = 0;
   resolve_scheme(ens, kind, gemm, &scheme);
   pidk::PairsPlan p = pidk::pairs_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr, scheme);
-  bool fused = false;
-  hipError_t err = pidk::launch_pid_pairs(p, *ens, kind, ex, po, ws, st, &mo, &fused);
-  if (err != hipSuccess) return hip_fail(err, "pid_both all-pairs launch");
-  if (!fused) {
-    pidk::MeanPlan mp = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
-    err = pidk::launch_pid_mean(mp, *ens, kind, ex, mo, static_cast<char*>(ws) + kp, st);
-    if (err != hipSuccess) return hip_fail(err, "pid_both PID-mean launch");
-  }
+  hipError_t err = pidk::launch_pid_pairs(p, *ens, kind, ex, po, ws, st, &mo);
+  if (err != hipSuccess) return hip_fail(err, "pid_both launch");
   if (rank_p && rank_m) {
     err = pidk::launch_rank2(po.depth, po.rank, po.order, mo.depth, mo.rank, mo.order, ens->n, st);
     if (err != hipSuccess) return hip_fail(err, "rank launch");

@@ -302,6 +302,11 @@ __device__ __forceinline__ float sum8(float v) {
   v += dpp_f<0x141>(v);   // lane 7 - l of the group (row_half_mirror)
   return v;
 }
+// Sum over each row of 16 lanes, the same bits in all sixteen.
+__device__ __forceinline__ float sum16(float v) {
+  v = sum8(v);
+  return v + dpp_f<0x140>(v);   // lane 15 - l of the row (row_mirror)
+}
 // Lanes below 32 (resp. in even rows of 16) get x + x of the lane 32 (16)
 // above; the others get y of the lane 32 (16) below + their own y.
 __device__ __forceinline__ float fold32(float x, float y) {

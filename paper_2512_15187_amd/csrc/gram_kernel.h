@@ -68,9 +68,7 @@ struct GramArgs {
   int64_t slabs;       // total slabs
   int vec;             // rows are 16-byte aligned
   void* part;          // [nsplit][np][1024] (float / int / double)
-  double* part_mass;   // [nsplit][mass_stride]: masses of split s at s * mass_stride
-  double* part_meanA;  // PID-mean numerators of the fused pass (part_mass + n), or nullptr
-  int64_t mass_stride; // n, or 2n when numerators follow the masses
+  double* part_mass;   // [nsplit][n] partial masses
 };
 
 // Super-tile index -> (I, J), I <= J, column-major over J.
@@ -591,7 +589,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
     lds_barrier();
     for (int r = tid; r < rowsI; r += 512) {
       const int gr = 32 * a.sb * SI + r;
-      if (gr < a.n) a.part_mass[(size_t)split * a.mass_stride + gr] = lmass[r];
+      if (gr < a.n) a.part_mass[(size_t)split * a.n + gr] = lmass[r];
     }
   }
 }
@@ -611,7 +609,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 // split's share are read with an offset beyond the buffer's range: they land
 // as zeros without a memory access, so no load sits under a branch that
 // depends on the data and the wait counts are constants.
-template <typename Tin, int MT, int MODE, int MAXT, bool WEIGHTED, int NB, int NT, int NW, bool MEAN, bool GRP>
+template <typename Tin, int MT, int MODE, int MAXT, bool WEIGHTED, int NB, int NT, int NW, bool GRP>
 __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   using TR = MTraits<MT>;
   constexpr int SEG = 128;                    // bytes of a row per slab
@@ -624,12 +622,6 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   constexpr int NTH = 64 * NW;                // threads
   constexpr int DW = LW + (WEIGHTED ? 1 : 0); // loads per slab of wave 0 (rows, weights)
   static_assert(MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3, "16-bit MFMA types");
-  // MEAN: the same pass also forms the PID-mean numerators A_i = sum_x w u_i s
-  // (s = column sums), for one diagonal super-tile holding every row, soft
-  // masks, one tile.  Per slab: column partials from the conversion pass
-  // (registers keep the thread's values), per-wave sums to LDS, s after the
-  // second barrier; A_i of a slab is added at the start of the next step.
-  static_assert(!MEAN || (MODE == MODE_NONE && NT == 1), "fused PID-mean: soft masks, one tile");
   constexpr int CQ = (256 * 8 + 64 * NW - 1) / (64 * NW);   // chunks per thread at most
   static_assert((NB - 2) * DW <= 63, "wait count");
   extern __shared__ __align__(16) unsigned char lds[];
@@ -710,9 +702,6 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   auto tile_of = [&](int64_t j) -> unsigned char* { return tiles + (size_t)(j % NT) * TR::PLANES * PLANE; };
   double* lmass = reinterpret_cast<double*>(tiles + (size_t)NT * TR::PLANES * PLANE);
   float* wsl = reinterpret_cast<float*>(lmass + rows);
-  float* wsum = wsl + (WEIGHTED ? NB * 64 : 0);            // [NW][KS] per-wave column sums
-  float* sv = wsum + (MEAN ? NW * KS : 0);                  // [KS] column sums of the slab
-  double* lA = reinterpret_cast<double*>(sv + (MEAN ? KS : 0));   // [rows] FP64 numerators
 
   // --- loads: wave w streams staging rows [RW w, RW w + RW) (inside one
   // 32-row block, so all in the I or the J range), eight rows per instruction
@@ -755,14 +744,12 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   auto wait_slab = [&]() { wait_slab_n(std::integral_constant<int, NB - 2>()); };
 
   // masses (diagonal super-tiles): the 8 lanes of a row add their chunk
-  // sums (fixed butterfly); the first adds the row sum in FP64, slab by slab
-  for (int r = tid; r < rows; r += NTH) lmass[r] = 0.0;
-  if constexpr (MEAN) {
-    for (int r = tid; r < rows; r += NTH) lA[r] = 0.0;
-  }
-  float ukeep[MEAN ? CQ : 1][EPC], wkeep[EPC];   // this thread's values of the slab (fused PID-mean)
+  // sums (fixed butterfly) and add the row sum in FP64, slab by slab, in
+  // registers: a thread's chunks belong to the same rows in every slab
+  // (row = (tid + NTH ci) / 8), so the sums stay in registers until the end.
+  double accm[CQ];
 #pragma unroll
-  for (int e = 0; e < EPC; ++e) wkeep[e] = 1.f;
+  for (int ci = 0; ci < CQ; ++ci) accm[ci] = 0.0;
 
   // Convert slot j (slab s) into its tile.  No contraction: sqrt(w) * u is
   // rounded to FP32 and then to the MFMA type in every kernel variant, so
@@ -772,9 +759,6 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
     const int64_t s = split + j * a.nsplit;
     const unsigned char* src = stage + (size_t)(j % NB) * rows * SEG;
     unsigned char* tile = tile_of(j);
-    float cp[EPC];
-#pragma unroll
-    for (int e = 0; e < EPC; ++e) cp[e] = 0.f;
 #pragma unroll
     for (int ci = 0; ci < CQ; ++ci) {
       const int qq = tid + NTH * ci;
@@ -793,12 +777,10 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
           const float wv = wsl[(size_t)(j % NB) * 64 + c * EPC + e];
           msum += wv * u;
           uv[e] = sqrtf(wv) * u;
-          if constexpr (MEAN) wkeep[e] = wv;
         } else {
           msum += u;
           uv[e] = u;
         }
-        if constexpr (MEAN) { ukeep[ci][e] = u; cp[e] += u; }
       }
       unsigned char* d = tile + (size_t)row * ROWB + (size_t)c * EPC * TR::EB;
       if constexpr (MT == MT_F16) {
@@ -821,37 +803,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
         store_lds<2 * EPC>(d, hi);
         store_lds<2 * EPC>(d + PLANE, lo);
       }
-      if (diag) {
-        msum = sum8(msum);
-        if (c == 0) lmass[row] += (double)msum;
-      }
-    }
-    if constexpr (MEAN) {
-      // lanes 8r + c hold chunk column c of rows r: add the wave's 8 rows
-      const float v = col_reduce<EPC>(cp, lane);
-      if (col_writer<EPC>(lane)) wsum[wave * KS + (lane & 7) * EPC + col_point<EPC>(lane)] = v;
-    }
-  };
-  // Column sums of the slab from the per-wave sums (one lane per point).
-  auto colsum = [&]() {
-    if (wave == 0 && lane < KS) {
-      float t = 0.f;
-      for (int q = 0; q < NW; ++q) t += wsum[q * KS + lane];
-      sv[lane] = t;
-    }
-  };
-  // A_i += sum over the thread's points of w u_i s, per row (8-lane butterfly).
-  auto add_numerators = [&]() {
-#pragma unroll
-    for (int ci = 0; ci < CQ; ++ci) {
-      const int qq = tid + NTH * ci;
-      if (qq >= rows * 8) break;
-      const int row = qq >> 3, c = qq & 7;
-      float t = 0.f;
-#pragma unroll
-      for (int e = 0; e < EPC; ++e) t += wkeep[e] * ukeep[ci][e] * sv[c * EPC + e];
-      t = sum8(t);
-      if (c == 0) lA[row] += (double)t;
+      if (diag) accm[ci] += (double)sum8(msum);
     }
   };
 
@@ -873,20 +825,10 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
     for (int64_t j = 0; j < cnt; ++j) {
       wait_slab();
       lds_barrier();            // every wave's rows of slab j are in LDS; the tile is free
-      if constexpr (MEAN) {
-        if (j > 0) add_numerators();   // slab j - 1 (its column sums are complete)
-      }
       issue(j + NB - 1);        // into the slot converted in the previous step
       convert(j);
       lds_barrier();            // the tile is complete
-      if constexpr (MEAN) colsum();
       multiply(tile_of(j));
-    }
-    if constexpr (MEAN) {
-      if (cnt > 0) {
-        lds_barrier();
-        add_numerators();
-      }
     }
   } else {
     // two tiles: slab j + 1 is converted while slab j is multiplied, one
@@ -908,6 +850,12 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
     }
   }
   vm_wait<0>();               // no load into LDS outlives the workgroup
+  // row sums to LDS (lane c = 0 of each row)
+#pragma unroll
+  for (int ci = 0; ci < CQ; ++ci) {
+    const int qq = tid + NTH * ci;
+    if (qq < rows * 8 && (qq & 7) == 0) lmass[qq >> 3] = accm[ci];
+  }
 
   // --- partial sub-tiles
 #pragma unroll
@@ -929,8 +877,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
     for (int r = tid; r < rowsI; r += NTH) {
       const int gr = 32 * a.sb * SI + r;
       if (gr < a.n) {
-        a.part_mass[(size_t)split * a.mass_stride + gr] = lmass[r];
-        if constexpr (MEAN) a.part_meanA[(size_t)split * a.mass_stride + gr] = lA[r];
+        a.part_mass[(size_t)split * a.n + gr] = lmass[r];
       }
     }
   }
@@ -946,23 +893,19 @@ constexpr int gram_dma_nb() {
   return nb > 4 ? 4 : nb;
 }
 template <typename Tin, int MT, int NT>
-size_t gram_dma_lds(int rows, bool weighted, bool mean, int nw) {
+size_t gram_dma_lds(int rows, bool weighted) {
   constexpr int KS = 128 / (int)sizeof(Tin);
   constexpr int ROWB = KS * MTraits<MT>::EB + 16;
   constexpr int NB = gram_dma_nb<Tin, MT, NT>();
   return (size_t)NB * rows * 128 + (size_t)NT * MTraits<MT>::PLANES * rows * ROWB + (size_t)rows * 8 +
-         (weighted ? (size_t)NB * 256 : 0) + (mean ? (size_t)(nw + 1) * KS * 4 + (size_t)rows * 8 : 0);
+         (weighted ? (size_t)NB * 256 : 0);
 }
 
 // Launch the LDS-staged kernel when it applies (soft input in FP32, FP16 or
 // BF16 with a 16-bit MFMA type, aligned rows ending on a 16-byte boundary,
 // offsets within 2^31); returns false otherwise.
-// With ga0.part_meanA set, the fused PID-mean numerators are produced when
-// the fused form applies (one diagonal super-tile, soft masks, 16 waves, one
-// tile); *mean_done tells whether they were.
 template <typename Tin, int MT, int MODE>
-bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStream_t st, const KernelTimer& tm,
-                     bool* mean_done) {
+bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStream_t st, const KernelTimer& tm) {
   if constexpr (!((MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) && sizeof(Tin) <= 4 && sizeof(Tin) >= 2)) {
     return false;
   } else {
@@ -991,45 +934,29 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
       hipExtLaunchKernelGGL(k, dim3(grid), dim3(threads), (uint32_t)lds, st, tm.start(), tm.stop(), 0u, ga);
     };
     // sub-tiles per wave: at most 36 over 8 waves (5) or over 16 waves (3)
-    const bool want_mean = ga.part_meanA != nullptr;
     auto pick = [&](auto ntc) {
       constexpr int NT = decltype(ntc)::value;
       constexpr int NB = gram_dma_nb<Tin, MT, NT>();
       static_assert(NB >= 2, "LDS ring");
       // eight row blocks in one diagonal super-tile: grouped sub-tiles
       const bool grp = nwaves == 16 && ga.nsuper == 1 && ga.nbt == 8;
-      if constexpr (MODE == MODE_NONE && NT == 1) {
-        if (want_mean && nwaves == 16 && ga.nsuper == 1) {
-          const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w, true, 16);
-          if (grp) {
-            if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true, true>, lds, 1024);
-            else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true, true>, lds, 1024);
-          } else {
-            if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true, false>, lds, 1024);
-            else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true, false>, lds, 1024);
-          }
-          *mean_done = true;
-          return;
-        }
-      }
-      ga.part_meanA = nullptr;
-      const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w, false, nwaves);
+      const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w);
       if (nwaves == 16) {
         if constexpr (NT == 1) {
           if (grp) {
-            if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false, true>, lds, 1024);
-            else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false, true>, lds, 1024);
+            if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true>, lds, 1024);
+            else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true>, lds, 1024);
             return;
           }
         }
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false, false>, lds, 1024);
-        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false, false>, lds, 1024);
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false>, lds, 1024);
+        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false>, lds, 1024);
       } else if (maxt > 2) {
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 5, true, NB, NT, 8, false, false>, lds, 512);
-        else go(gram_dma_kernel<Tin, MT, MODE, 5, false, NB, NT, 8, false, false>, lds, 512);
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 5, true, NB, NT, 8, false>, lds, 512);
+        else go(gram_dma_kernel<Tin, MT, MODE, 5, false, NB, NT, 8, false>, lds, 512);
       } else {
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 2, true, NB, NT, 8, false, false>, lds, 512);
-        else go(gram_dma_kernel<Tin, MT, MODE, 2, false, NB, NT, 8, false, false>, lds, 512);
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 2, true, NB, NT, 8, false>, lds, 512);
+        else go(gram_dma_kernel<Tin, MT, MODE, 2, false, NB, NT, 8, false>, lds, 512);
       }
     };
     // one tile by default (faster with 16 waves); two where asked for and the
@@ -1066,11 +993,9 @@ void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
 // supported.  maxt: register tiles per wave (5 for one diagonal super-tile of
 // 5..8 row blocks, else 2).  INT8 runs are unweighted.
 template <typename Tin, int MT, int MODE>
-void launch_gram_t(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st,
-                   bool* mean_done) {
+void launch_gram_t(const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st) {
   KernelTimer tm("gram", st, /*by_launch=*/true);
-  *mean_done = false;
-  if (launch_gram_dma<Tin, MT, MODE>(ga, maxt, rows, grid, st, tm, mean_done)) return;
+  if (launch_gram_dma<Tin, MT, MODE>(ga, maxt, rows, grid, st, tm)) return;
   if constexpr (MT == MT_I8) launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st, tm);
   else if (ga.w != nullptr) launch_gram_w<Tin, MT, MODE, true>(ga, maxt, rows, grid, lds, st, tm);
   else launch_gram_w<Tin, MT, MODE, false>(ga, maxt, rows, grid, lds, st, tm);
@@ -1078,11 +1003,11 @@ void launch_gram_t(const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
 
 // Per-input-type dispatchers (one translation unit each); return false when
 // the (MFMA type, extraction mode) combination is not provided.
-bool gram_dispatch_f32(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st, bool* mean_done);
-bool gram_dispatch_f16(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st, bool* mean_done);
-bool gram_dispatch_bf16(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st, bool* mean_done);
-bool gram_dispatch_f64(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st, bool* mean_done);
-bool gram_dispatch_u8(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st, bool* mean_done);
+bool gram_dispatch_f32(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_f16(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_bf16(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_f64(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_u8(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
 bool gram_supported(int dtype, int mt, int mode);
 
 }  // namespace pidk

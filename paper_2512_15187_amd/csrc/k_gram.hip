@@ -23,65 +23,93 @@
 #include "pid_timing.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 namespace pidk {
 
 // ---------------------------------------------------------------------------
 // Fixed-order FP64 reduction of the split partials into the full symmetric
-// G (N x N, row-major) and the masses.  A block owns 32 consecutive partial
-// elements; its 8 thread groups sum the splits k = g, g+8, g+16, ... (each in
-// ascending k, four loads in flight), and group 0 adds the 8 group sums in
-// order g = 0..7.  The order depends on nsplit only, so results are
-// deterministic.
-constexpr int RED_ELEMS = 32;
+// G (N x N, row-major) and the masses.  A block owns RED_ELEMS consecutive
+// partial elements, four per thread of a group (16-byte loads, so a group
+// reads 512 contiguous bytes of each split); its 8 thread groups sum the
+// splits k = g, g+8, g+16, ... (each in ascending k), and the group sums are
+// added in order g = 0..7.  The order depends on nsplit only, so results are
+// deterministic.  The masses follow the packed sub-tiles as elements tot,
+// tot + 1, ... and are read one per lane.
+constexpr int RED_ELEMS = 128;
 constexpr int RED_GROUPS = 8;
+constexpr int RED_EPT = 4;   // elements per thread
 
 template <typename PT>
 __global__ __launch_bounds__(256) void gram_reduce(const PT* __restrict__ part,
-                                                   const double* __restrict__ part_mass, int64_t mass_stride,
+                                                   const double* __restrict__ part_mass,
                                                    int nsplit, int np, int n, double* __restrict__ G,
-                                                   double* __restrict__ mass, int nrows_extra) {
+                                                   double* __restrict__ mass) {
   __shared__ double red[RED_GROUPS][RED_ELEMS];
-  const int64_t tot = (int64_t)np * 1024;
-  const int el = threadIdx.x % RED_ELEMS;
-  const int g = threadIdx.x / RED_ELEMS;
-  const int64_t e = (int64_t)blockIdx.x * RED_ELEMS + el;
-  const bool is_mass = e >= tot;
-  // elements: the packed sub-tiles, then n masses, then (fused PID-mean) n
-  // numerators, which follow the masses of each split in part_mass and the
-  // masses in mass
-  const int64_t nx = (int64_t)n * nrows_extra;
-  double s = 0.0;
-  if (e < tot + nx) {
-    const size_t stride = is_mass ? (size_t)mass_stride : (size_t)np * 1024;
-    const size_t base = is_mass ? (size_t)(e - tot) : (size_t)e;
+  const int64_t tot = (int64_t)np * 1024;   // a multiple of RED_ELEMS
+  const int g = threadIdx.x / (RED_ELEMS / RED_EPT);
+  const int el0 = (threadIdx.x % (RED_ELEMS / RED_EPT)) * RED_EPT;
+  const int64_t e0 = (int64_t)blockIdx.x * RED_ELEMS + el0;
+  const int64_t nx = n;
+  double s[RED_EPT] = {0.0, 0.0, 0.0, 0.0};
+  if (e0 < tot) {
+    const size_t stride = (size_t)np * 1024;
+    struct V4 { PT v[RED_EPT]; };
+    auto ld = [&](int k) -> V4 {
+      const PT* p = part + (size_t)k * stride + (size_t)e0;
+      if constexpr (sizeof(PT) == 4) {
+        return __builtin_bit_cast(V4, __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)));
+      } else {
+        V4 r;
+#pragma unroll
+        for (int q = 0; q < RED_EPT; ++q) r.v[q] = p[q];
+        return r;
+      }
+    };
+    auto add = [&](const V4& v) {
+#pragma unroll
+      for (int r = 0; r < RED_EPT; ++r) s[r] += (double)v.v[r];
+    };
+    int k = g;
+    for (; k + 3 * RED_GROUPS < nsplit; k += 4 * RED_GROUPS) {   // four splits in flight, added in order
+      const V4 a0 = ld(k), a1 = ld(k + RED_GROUPS), a2 = ld(k + 2 * RED_GROUPS), a3 = ld(k + 3 * RED_GROUPS);
+      add(a0); add(a1); add(a2); add(a3);
+    }
+    for (; k < nsplit; k += RED_GROUPS) add(ld(k));
+  } else if (e0 < tot + nx) {
+    // masses: four consecutive members per thread, four splits in flight
+    const int64_t b0 = e0 - tot;
+    const int nv = (int)min((int64_t)RED_EPT, nx - b0);
+    auto ldm = [&](int k, double (&v)[RED_EPT]) {
+#pragma unroll
+      for (int r = 0; r < RED_EPT; ++r) v[r] = (r < nv) ? part_mass[(size_t)k * n + (size_t)(b0 + r)] : 0.0;
+    };
     int k = g;
     for (; k + 3 * RED_GROUPS < nsplit; k += 4 * RED_GROUPS) {
-      double v0, v1, v2, v3;
-      if (is_mass) {
-        v0 = part_mass[base + (size_t)k * stride];
-        v1 = part_mass[base + (size_t)(k + RED_GROUPS) * stride];
-        v2 = part_mass[base + (size_t)(k + 2 * RED_GROUPS) * stride];
-        v3 = part_mass[base + (size_t)(k + 3 * RED_GROUPS) * stride];
-      } else {
-        v0 = (double)part[base + (size_t)k * stride];
-        v1 = (double)part[base + (size_t)(k + RED_GROUPS) * stride];
-        v2 = (double)part[base + (size_t)(k + 2 * RED_GROUPS) * stride];
-        v3 = (double)part[base + (size_t)(k + 3 * RED_GROUPS) * stride];
-      }
-      s += v0; s += v1; s += v2; s += v3;
+      double v0[RED_EPT], v1[RED_EPT], v2[RED_EPT], v3[RED_EPT];
+      ldm(k, v0); ldm(k + RED_GROUPS, v1); ldm(k + 2 * RED_GROUPS, v2); ldm(k + 3 * RED_GROUPS, v3);
+#pragma unroll
+      for (int r = 0; r < RED_EPT; ++r) { s[r] += v0[r]; s[r] += v1[r]; s[r] += v2[r]; s[r] += v3[r]; }
     }
-    for (; k < nsplit; k += RED_GROUPS)
-      s += is_mass ? part_mass[base + (size_t)k * stride] : (double)part[base + (size_t)k * stride];
+    for (; k < nsplit; k += RED_GROUPS) {
+      double v[RED_EPT];
+      ldm(k, v);
+#pragma unroll
+      for (int r = 0; r < RED_EPT; ++r) s[r] += v[r];
+    }
   }
-  red[g][el] = s;
+#pragma unroll
+  for (int r = 0; r < RED_EPT; ++r) red[g][el0 + r] = s[r];
   __syncthreads();
-  if (g != 0 || e >= tot + nx) return;
+  if (threadIdx.x >= RED_ELEMS) return;
+  const int el = threadIdx.x;
+  const int64_t e = (int64_t)blockIdx.x * RED_ELEMS + el;
+  if (e >= tot + nx) return;
   double t = 0.0;
 #pragma unroll
   for (int q = 0; q < RED_GROUPS; ++q) t += red[q][el];
-  if (is_mass) {
+  if (e >= tot) {
     mass[e - tot] = t;
     return;
   }
@@ -108,13 +136,16 @@ constexpr int DEP_CHUNK = 1024;
 
 // All per-member outputs after the reduction, one block of 256 threads per
 // member i: the inclusion row P_ij = G_ij / m_i (0 when m_i = 0; when asked
-// for), the depths above, and, after the fused PID-mean pass (meanA set),
-// IN_in = A_i / (N m_i) and IN_out = A_i / sum_k m_k (Sec. 4.1), with
-// sum_k m_k formed by every block in the fixed tree of pidmean_ratios.
+// for), the depths above, and, with `mean` set, the PID-mean ratios of the
+// same ensemble.  Their numerators are the Gram row sums:
+//   A_i = sum_x w u_i(x) s(x),  s = sum_j u_j   =>   A_i = sum_j G_ij = S_i,
+// so IN_in = A_i / (N m_i) is the all-pairs IN_in (the recall identity of
+// Sec. 4.1) and IN_out = A_i / sum_k m_k, with sum_k m_k formed by every block
+// in the fixed tree of pidmean_ratios.
 struct FinishArgs {
   const double* G;
   const double* mass;
-  const double* meanA;      // PID-mean numerators (n), or nullptr
+  int mean;                 // also write the PID-mean outputs
   int n;
   double* P;
   double *m_out, *in_in, *in_out, *depth;
@@ -151,7 +182,7 @@ __global__ __launch_bounds__(256) void pairs_finish(FinishArgs f) {
     }
     __syncthreads();
   }
-  if (f.meanA) {
+  if (f.mean) {
     double md = 0.0;
     for (int k = t; k < n; k += 256) md += f.mass[k];
     red[t] = md;
@@ -168,10 +199,10 @@ __global__ __launch_bounds__(256) void pairs_finish(FinishArgs f) {
   if (f.in_in) f.in_in[i] = ii;
   if (f.in_out) f.in_out[i] = oo;
   if (f.depth) f.depth[i] = ii < oo ? ii : oo;
-  if (f.meanA) {
-    const double a = f.meanA[i], tot = red[0];
-    const double mii = (mi > 0.0) ? a / ((double)n * mi) : 0.0;
-    const double moo = (tot > 0.0) ? a / tot : 0.0;
+  if (f.mean) {
+    const double tot = red[0];
+    const double moo = (tot > 0.0) ? S / tot : 0.0;
+    const double mii = ii;
     if (f.mm_out) f.mm_out[i] = mi;
     if (f.mm_in) f.mm_in[i] = mii;
     if (f.mm_outo) f.mm_outo[i] = moo;
@@ -259,7 +290,11 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
   p.nbt = (int)((n + 31) / 32);
   // one diagonal super-tile of up to 8 row blocks when N <= 256, else
   // super-blocks of 4 row blocks (128 rows) and all their pairs I <= J
-  p.sb = (p.nbt <= 8) ? p.nbt : 4;
+  static const int tune_sb = [] {
+    const char* v = getenv("PID_TUNE_GRAM_SB");   // 4: 128-row super-blocks also for N <= 256
+    return v ? atoi(v) : 0;
+  }();
+  p.sb = (p.nbt <= 8 && !(tune_sb == 4 && p.nbt > 4)) ? p.nbt : 4;
   p.nsuper = (p.nbt + p.sb - 1) / p.sb;
   p.ntiles_super = p.nsuper * (p.nsuper + 1) / 2;
   p.np = p.nbt * (p.nbt + 1) / 2;
@@ -276,6 +311,11 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
   const int64_t min_splits = (m + 16383) / 16384;
   if (mt != MT_I8 && mt != MT_F64) want = std::max(want, min_splits);
   p.nsplit = (int)(((want + 7) / 8) * 8);
+  static const int tune_splits = [] {
+    const char* v = getenv("PID_TUNE_GRAM_SPLITS");   // a multiple of 8
+    return v ? atoi(v) : 0;
+  }();
+  if (tune_splits > 0 && tune_splits % 8 == 0) p.nsplit = tune_splits;
   p.slabs_per_split = (p.slabs + p.nsplit - 1) / p.nsplit;
   const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;
   const int rowb = p.ks * mt_bytes(mt) + 16;
@@ -289,15 +329,15 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
 size_t pairs_workspace(const PairsPlan& p, int64_t n) {
   Carve c(nullptr);
   c.take<char>((size_t)p.nsplit * p.np * 1024 * p.part_elem);
-  c.take<double>((size_t)p.nsplit * n * 2);   // partial masses, then partial PID-mean numerators
-  c.take<double>((size_t)n * n);              // G
-  c.take<double>((size_t)n * 2);              // masses, then PID-mean numerators
+  c.take<double>((size_t)p.nsplit * n);   // partial masses
+  c.take<double>((size_t)n * n);          // G
+  c.take<double>((size_t)n);              // masses
   return c.off + 256;
 }
 
 hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,
                             const ExtractHost& exh, const pid_out& out, void* ws, hipStream_t st,
-                            const pid_out* mean_out, bool* mean_done) {
+                            const pid_out* mean_out) {
   Carve c(ws);
   GramArgs ga{};
   ga.U = e.data;
@@ -314,14 +354,9 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   ga.nsplit = p.nsplit;
   ga.slabs = p.slabs;
   ga.part = c.take<char>((size_t)p.nsplit * p.np * 1024 * p.part_elem);
-  // [nsplit][n] masses, then [nsplit][n] PID-mean numerators: the reduction
-  // treats them as one [nsplit][2n] array when the fused pass ran
-  double* pm = c.take<double>((size_t)p.nsplit * e.n * 2);
+  ga.part_mass = c.take<double>((size_t)p.nsplit * e.n);
   double* G = c.take<double>((size_t)e.n * e.n);
-  double* mass = c.take<double>((size_t)e.n * 2);
-  ga.part_mass = pm;
-  ga.mass_stride = mean_out ? 2 * e.n : e.n;
-  ga.part_meanA = mean_out ? pm + e.n : nullptr;
+  double* mass = c.take<double>((size_t)e.n);
   const int eb = elem_bytes_g(e.dtype);
   ga.vec = (((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
             (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0)) ? 1 : 0;
@@ -329,32 +364,30 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   const int mode = iso_kind == PID_ISO_GAUSSIAN ? MODE_GAUSS : (iso_kind == PID_ISO_STEP ? MODE_STEP : MODE_NONE);
   const int grid = p.nsplit * p.ntiles_super;
   const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;   // most rows a workgroup loads
-  bool ok = false, fused = false;
+  bool ok = false;
   switch (e.dtype) {
-    case PID_F64: ok = gram_dispatch_f64(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
-    case PID_F32: ok = gram_dispatch_f32(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
-    case PID_F16: ok = gram_dispatch_f16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
-    case PID_BF16: ok = gram_dispatch_bf16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
-    default: ok = gram_dispatch_u8(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st, &fused); break;
+    case PID_F64: ok = gram_dispatch_f64(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    case PID_F32: ok = gram_dispatch_f32(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    case PID_F16: ok = gram_dispatch_f16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    case PID_BF16: ok = gram_dispatch_bf16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
+    default: ok = gram_dispatch_u8(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
   }
   if (!ok) return hipErrorNotSupported;
-  if (mean_done) *mean_done = fused;
-  const int extra = fused ? 2 : 1;   // reduce the numerators with the masses
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const int64_t work = (int64_t)p.np * 1024 + e.n * extra;
+  const int64_t work = (int64_t)p.np * 1024 + e.n;
   const int rgrid = (int)((work + RED_ELEMS - 1) / RED_ELEMS);
   {
   KernelTimer tm("gram_reduce", st);
   if (p.part_elem == 8)
-    hipLaunchKernelGGL(gram_reduce<double>, rgrid, 256, 0, st, (const double*)ga.part, ga.part_mass, ga.mass_stride,
-                       p.nsplit, p.np, (int)e.n, G, mass, extra);
+    hipLaunchKernelGGL(gram_reduce<double>, rgrid, 256, 0, st, (const double*)ga.part, ga.part_mass, p.nsplit, p.np,
+                       (int)e.n, G, mass);
   else if (mtype_of(p.scheme) == MT_I8)
-    hipLaunchKernelGGL(gram_reduce<int>, rgrid, 256, 0, st, (const int*)ga.part, ga.part_mass, ga.mass_stride,
-                       p.nsplit, p.np, (int)e.n, G, mass, extra);
+    hipLaunchKernelGGL(gram_reduce<int>, rgrid, 256, 0, st, (const int*)ga.part, ga.part_mass, p.nsplit, p.np,
+                       (int)e.n, G, mass);
   else
-    hipLaunchKernelGGL(gram_reduce<float>, rgrid, 256, 0, st, (const float*)ga.part, ga.part_mass, ga.mass_stride,
-                       p.nsplit, p.np, (int)e.n, G, mass, extra);
+    hipLaunchKernelGGL(gram_reduce<float>, rgrid, 256, 0, st, (const float*)ga.part, ga.part_mass, p.nsplit, p.np,
+                       (int)e.n, G, mass);
   }
   {
     KernelTimer tm("pairs_finish", st);
@@ -364,8 +397,8 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
     f.n = (int)e.n;
     f.P = out.inclusion;
     f.m_out = out.mass; f.in_in = out.in_in; f.in_out = out.in_out; f.depth = out.depth;
-    if (fused) {
-      f.meanA = mass + e.n;
+    if (mean_out) {
+      f.mean = 1;
       f.mm_out = mean_out->mass; f.mm_in = mean_out->in_in; f.mm_outo = mean_out->in_out;
       f.mm_depth = mean_out->depth;
     }

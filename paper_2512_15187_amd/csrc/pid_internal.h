@@ -77,12 +77,11 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
 size_t pairs_workspace(const PairsPlan& p, int64_t n);
 // True when the Gram kernel is built for this input dtype, scheme and iso kind.
 bool pairs_supported(int dtype, int iso_kind, int scheme);
-// mean_out non-null: also form the PID-mean outputs in the same pass where
-// the fused form applies; *mean_done reports whether it did (else the caller
-// runs the PID-mean kernels).
+// mean_out non-null: also write the PID-mean outputs, from the Gram row sums
+// (A_i = sum_j G_ij) and the masses of the same pass.
 hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,
                             const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st,
-                            const pid_out* mean_out = nullptr, bool* mean_done = nullptr);
+                            const pid_out* mean_out = nullptr);
 
 // ---------------------------------------------------------------- misc
 hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, void* u_out,

@@ -267,7 +267,7 @@ def test_rank_entry_point():
 
 # ------------------------------------------------------------------ both in one call
 BOTH_CASES = [
-    # (n, m, dtype, weighted, gemm)  -- the first three share one pass, the rest fall back
+    # (n, m, dtype, weighted, gemm)
     (256, 32 * 1000, torch.float32, False, "f16"),
     (200, 32 * 777 + 20, torch.float32, True, "f16"),
     (64, 64 * 300, torch.float16, True, "f16"),
@@ -282,7 +282,8 @@ BOTH_CASES = [
                          ids=[f"{c[0]}x{c[1]}-{str(c[2])[6:]}-{'w' if c[3] else 'u'}-{c[4]}" for c in BOTH_CASES])
 def test_pid_both(n, m, dtype, weighted, gemm):
     """pid_both: all-pairs results bitwise those of pid_all_pairs; PID-mean
-    results within the FP32 (FP64) tolerance of the oracle."""
+    from the Gram row sums, within the tolerance of the Gram's scheme, with
+    IN_in and the masses equal to the all-pairs ones (recall identity)."""
     U = _soft(n, m, 400 + n, dtype)
     w = _weights(m, 9) if weighted else None
     Ud, wd = _dev(U), (None if w is None else _dev(w))
@@ -290,7 +291,25 @@ def test_pid_both(n, m, dtype, weighted, gemm):
     alone = pid.pid_all_pairs(Ud, wd, gemm=gemm)
     for key in ("inclusion", "mass", "in_in", "in_out", "depth", "rank", "order"):
         assert torch.equal(rp[key], alone[key]), key
+    assert torch.equal(rm["in_in"], rp["in_in"]) and torch.equal(rm["mass"], rp["mass"])
     ref = oracle.pid_mean(_ref_input(U), None if w is None else w.numpy())
-    tol = TOL_F64 if dtype == torch.float64 else TOL_F32
-    assert_close(rm, ref, tol, label=f"both mean {n}x{m}")
-    assert_ranks(rm["rank"], ref["depth"], tol, label="both mean")
+    assert_close(rm, ref, TOL_OF[gemm], label=f"both mean {n}x{m}")
+    assert_ranks(rm["rank"], ref["depth"], TOL_OF[gemm], label="both mean")
+
+
+@pytest.mark.parametrize("n,m,kind", [(40, 5000, "u8"), (257, 2222, "step")])
+def test_pid_both_binary_bitexact(n, m, kind):
+    """Binary input through INT8: both depth kinds bitwise equal to the
+    oracle's integer forms."""
+    if kind == "u8":
+        B = synth.random_binary(n, m, 60 + n)
+        rp, rm = pid.pid_both(_dev(B), gemm="i8")
+    else:
+        F = _fields(n, m, 61 + n)
+        iso = dict(kind="step", c=0.5, side=1)
+        rp, rm = pid.pid_both(_dev(F), iso=iso)
+        B = torch.from_numpy(oracle.extract(F.numpy(), iso).astype(np.uint8))
+    assert_bitwise(rp, oracle.binary_pid(B.numpy()), label=f"both-bin pairs {kind}")
+    refm = oracle.binary_pid_mean(B.numpy())
+    assert_bitwise(rm, refm, keys=("in_in", "in_out", "depth", "mass"), label=f"both-bin mean {kind}")
+    assert_ranks(rm["rank"], refm["depth"], 0)

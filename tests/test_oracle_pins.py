@@ -174,6 +174,19 @@ def test_pidmean_recall_identity(seed):
         np.testing.assert_allclose(lit[key], b[key], atol=1e-15, rtol=0)
 
 
+@pytest.mark.parametrize("seed", [33, 34])
+def test_pidmean_numerators_are_gram_row_sums(seed):
+    """``A_i = sum_x w u_i s(x) = sum_j G_ij`` with ``s = sum_j u_j``: PID-mean's
+    IN_out is the Gram row sum over the total mass (Sec. 4.1 against Sec. 3.2);
+    the all-pairs and PID-mean depths of one ensemble share these sums."""
+    U = synth.random_soft(11, 350, seed).numpy()
+    w = _rng(seed).uniform(0.5, 1.5, size=350)
+    G, m = oracle.gram(U, w), oracle.mass(U, w)
+    b = oracle.pid_mean(U, w)
+    np.testing.assert_allclose(b["in_out"], G.sum(axis=1) / m.sum(), rtol=1e-14, atol=0)
+    np.testing.assert_allclose(b["in_in"], G.sum(axis=1) / (len(U) * m), rtol=1e-14, atol=0)
+
+
 def test_equal_masses_pidmean_equals_pid():
     """Integer translations of one pattern inside the grid have equal masses;
     then the mass-weighted and unweighted means of IN_out coincide."""
