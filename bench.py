@@ -4,7 +4,9 @@
 Default (headline) workload: the 2D soft-mask ensemble, N = 256 members on a
 512 x 512 grid (M = 262,144 points), FP32 masks.  One step = the whole hot
 path on that batch: all-pairs PID (FP16 MFMA Gram numerators, FP64 masses,
-ratios, depths, ranks) plus PID-mean (one streaming pass, depths, ranks).
+ratios, depths, ranks) plus PID-mean (its numerators are the Gram row sums of
+the same pass; depths, ranks), one pid_both call.  The streaming PID-mean
+kernel of pid_mean is measured in GB/s on the large 3D workload (extras).
 ``value`` = N^2 * M / (seconds per step), pair*points/s, inputs resident in
 HBM.  The line also carries the roofline of the dominant kernel measured with
 HIP events inside the timed region, the FP64 CPU oracle timed on the host, the
@@ -204,8 +206,8 @@ def headline(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
         "config": {"workload": "2D soft masks, N=256 on 512x512 (M=262144), FP32 masks; all-pairs PID "
-                               "(FP16 MFMA Gram, FP64 normalisation) and PID-mean (FP32/FP64 sums) from one "
-                               "call (pid_both: one pass over the masks), with both rankings",
+                               "(FP16 MFMA Gram, FP64 normalisation) and PID-mean (from the Gram row sums) "
+                               "from one call (pid_both: one pass over the masks), with both rankings",
                    "n": n, "m": m, "scheme": "f16", "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "extra": extra,
     }

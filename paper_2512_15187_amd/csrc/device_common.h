@@ -302,11 +302,6 @@ __device__ __forceinline__ float sum8(float v) {
   v += dpp_f<0x141>(v);   // lane 7 - l of the group (row_half_mirror)
   return v;
 }
-// Sum over each row of 16 lanes, the same bits in all sixteen.
-__device__ __forceinline__ float sum16(float v) {
-  v = sum8(v);
-  return v + dpp_f<0x140>(v);   // lane 15 - l of the row (row_mirror)
-}
 // Lanes below 32 (resp. in even rows of 16) get x + x of the lane 32 (16)
 // above; the others get y of the lane 32 (16) below + their own y.
 __device__ __forceinline__ float fold32(float x, float y) {
@@ -317,41 +312,14 @@ __device__ __forceinline__ float fold16(float x, float y) {
   const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-// Column sums over the eight row lanes of a wave.  Lane 8r + c holds E
-// values v[e] (points c*E + e, summed over its rows).  Halving the values
-// at each step (lanes ^ 32, ^ 16, ^ 8), lane l ends with the sum over the
-// lanes l ^ 8k of point c*E + col_point<E>(l); for E < 8 lanes l and l ^ 8
-// (and l ^ 16 for E = 2) hold the same point and the same bits.
-template <int E>
-__device__ __forceinline__ int col_point(int lane) {
-  static_assert(E == 2 || E == 4 || E == 8, "values per lane");
-  const int b3 = (lane >> 3) & 1, b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
-  if constexpr (E == 8) return 4 * b3 + 2 * b4 + b5;
-  else if constexpr (E == 4) return 2 * b4 + b5;
-  else return b5;
-}
-template <int E>
-__device__ __forceinline__ bool col_writer(int lane) {
-  if constexpr (E == 8) return true;
-  else if constexpr (E == 4) return (lane & 8) == 0;
-  else return (lane & 24) == 0;
-}
-template <int E>
-__device__ __forceinline__ float col_reduce(const float (&v)[E], int lane) {
-  static_assert(E == 2 || E == 4 || E == 8, "values per lane");
-  if constexpr (E == 2) {
-    float a = fold32(v[0], v[1]);
-    a = fold16(a, a);
-    return a + dpp_f<0x128>(a);                    // lane ^ 8 (row_ror:8)
-  } else if constexpr (E == 4) {
-    const float b = fold16(fold32(v[0], v[1]), fold32(v[2], v[3]));
-    return b + dpp_f<0x128>(b);
-  } else {
-    const float b0 = fold16(fold32(v[0], v[1]), fold32(v[2], v[3]));
-    const float b1 = fold16(fold32(v[4], v[5]), fold32(v[6], v[7]));
-    const bool hi = (lane & 8) != 0;
-    return (hi ? b1 : b0) + dpp_f<0x128>(hi ? b0 : b1);
-  }
+// Sum over the lanes l, l ^ T, l ^ 2T, ... (T = 16 or 32; T = 64: the value
+// itself), the same bits in all of them.
+template <int T>
+__device__ __forceinline__ float sum_from(float v) {
+  static_assert(T == 16 || T == 32 || T == 64, "lane stride");
+  if constexpr (T == 16) v = fold16(v, v);
+  if constexpr (T <= 32) v = fold32(v, v);
+  return v;
 }
 
 // ---- float -> 16-bit conversions (round to nearest even) ----

@@ -480,8 +480,13 @@ __global__ __launch_bounds__(512) void pidmean_dma_kernel(
 #pragma unroll
     for (int i = 0; i < RPL; ++i)
       sp += to_ct<CT>(*reinterpret_cast<const T*>(rt + (size_t)(hr + LPP * i) * SEG + (size_t)pt * sizeof(T)));
+    // the wave's rows (lanes pt, pt + TPP, ...)
+    if constexpr (std::is_same<CT, float>::value) {
+      sp = sum_from<TPP>(sp);
+    } else {
 #pragma unroll
-    for (int o = TPP; o < 64; o <<= 1) sp += __shfl_xor(sp, o, 64);   // the wave's rows
+      for (int o = TPP; o < 64; o <<= 1) sp += __shfl_xor(sp, o, 64);
+    }
     CT* ps = psum + (size_t)(k & 1) * nw * TPP;
     if (hr == 0) ps[wave * TPP + pt] = pv ? sp : CT(0);
     lds_barrier();
