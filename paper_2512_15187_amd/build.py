@@ -58,7 +58,7 @@ def check_m0(asm_path: str):
     for i, l in enumerate(lines):
         if re.search(r"\bm0\b", l):
             ok = (l.startswith("s_mov_b32 m0, ") and i + 1 < len(lines)
-                  and re.match(r"buffer_load_dword\w* v\d+, s\[\d+:\d+\], 0 offen lds$", lines[i + 1]))
+                  and re.match(r"buffer_load_dword\w* v\d+, s\[\d+:\d+\], (0|s\d+) offen lds$", lines[i + 1]))
             if not ok:
                 bad.append(l)
     if bad:

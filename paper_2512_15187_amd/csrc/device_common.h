@@ -187,6 +187,22 @@ __device__ __forceinline__ void dma_to_lds(const BufRes& rs, const void* dst, ui
                  :: "s"(l), "v"(voff), "s"(rs.w) : "memory", "m0");
   }
 }
+// The same with a wave-uniform byte offset `soff` added to every lane's
+// (in a scalar register; voff + soff must stay below 2^32).
+template <int B>
+__device__ __forceinline__ void dma_to_lds(const BufRes& rs, const void* dst, uint32_t voff, uint32_t soff) {
+  const uint32_t l = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)dst);
+  const uint32_t so = __builtin_amdgcn_readfirstlane(soff);
+  asm volatile("" : "+v"(voff));
+  if constexpr (B == 16) {
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+                 :: "s"(l), "v"(voff), "s"(rs.w), "s"(so) : "memory", "m0");
+  } else {
+    static_assert(B == 4, "4- or 16-byte lanes");
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, %3 offen lds"
+                 :: "s"(l), "v"(voff), "s"(rs.w), "s"(so) : "memory", "m0");
+  }
+}
 
 // Wait until at most N vector memory operations of this wave are outstanding.
 template <int N>
@@ -288,20 +304,8 @@ __device__ __forceinline__ long long wave_sum(long long v) {
 }
 
 // ---- sums across lanes without the LDS crossbar ----
-// DPP moves (within rows of 16 lanes) and the gfx950 lane swaps
-// (v_permlane16_swap / v_permlane32_swap) run in the vector ALU; every lane
-// of the wave must be active.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
-}
-// Sum over each aligned group of eight lanes, the same bits in all eight.
-__device__ __forceinline__ float sum8(float v) {
-  v += dpp_f<0xB1>(v);    // lane ^ 1 (quad_perm 1,0,3,2)
-  v += dpp_f<0x4E>(v);    // lane ^ 2 (quad_perm 2,3,0,1)
-  v += dpp_f<0x141>(v);   // lane 7 - l of the group (row_half_mirror)
-  return v;
-}
+// The gfx950 lane swaps (v_permlane16_swap / v_permlane32_swap) run in the
+// vector ALU; every lane of the wave must be active.
 // Lanes below 32 (resp. in even rows of 16) get x + x of the lane 32 (16)
 // above; the others get y of the lane 32 (16) below + their own y.
 __device__ __forceinline__ float fold32(float x, float y) {

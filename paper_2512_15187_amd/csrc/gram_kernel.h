@@ -166,23 +166,32 @@ __device__ __forceinline__ void mfma_slab_g(const unsigned char* lbuf, int PLANE
   using TR = MTraits<MT>;
   constexpr int KSTEPS = KS / TR::KK;
   constexpr int FE = 16 / TR::EB;
-  constexpr int KUNR = KSTEPS > 2 ? 2 : KSTEPS;
-#pragma unroll KUNR
-  for (int kk = 0; kk < KSTEPS; ++kk) {
-    const int koff = (kk * TR::KK + (lane >> 5) * FE) * TR::EB;
-    const unsigned char* p0 = lbuf + (size_t)(r0 * 32 + (lane & 31)) * ROWB + koff;
-    const unsigned char* p1 = lbuf + (size_t)(r1 * 32 + (lane & 31)) * ROWB + koff;
-    const unsigned char* p2 = lbuf + (size_t)(r2 * 32 + (lane & 31)) * ROWB + koff;
-    uint4 f0[TR::PLANES], f1[TR::PLANES], f2[TR::PLANES];
+  // k-steps whose fragments are read before their MFMAs (all reads issued
+  // back to back, one wait): two, or one with hi/lo planes
+  constexpr int KG = (TR::PLANES == 1 && KSTEPS % 2 == 0) ? 2 : 1;
+  const unsigned char* p0 = lbuf + (size_t)(r0 * 32 + (lane & 31)) * ROWB + (lane >> 5) * FE * TR::EB;
+  const unsigned char* p1 = lbuf + (size_t)(r1 * 32 + (lane & 31)) * ROWB + (lane >> 5) * FE * TR::EB;
+  const unsigned char* p2 = lbuf + (size_t)(r2 * 32 + (lane & 31)) * ROWB + (lane >> 5) * FE * TR::EB;
 #pragma unroll
-    for (int q = 0; q < TR::PLANES; ++q) {
-      f0[q] = *reinterpret_cast<const uint4*>(p0 + q * PLANE);
-      f1[q] = *reinterpret_cast<const uint4*>(p1 + q * PLANE);
-      f2[q] = *reinterpret_cast<const uint4*>(p2 + q * PLANE);
+  for (int k0 = 0; k0 < KSTEPS; k0 += KG) {
+    uint4 f0[KG][TR::PLANES], f1[KG][TR::PLANES], f2[KG][TR::PLANES];
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const int koff = (k0 + g) * TR::KK * TR::EB;
+#pragma unroll
+      for (int q = 0; q < TR::PLANES; ++q) {
+        f0[g][q] = *reinterpret_cast<const uint4*>(p0 + koff + q * PLANE);
+        f1[g][q] = *reinterpret_cast<const uint4*>(p1 + koff + q * PLANE);
+        f2[g][q] = *reinterpret_cast<const uint4*>(p2 + koff + q * PLANE);
+      }
     }
-    mfma_step<MT>(acc[0], f0, f1);
-    mfma_step<MT>(acc[1], f0, f2);
-    if (three) mfma_step<MT>(acc[2], f2, f2);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      mfma_step<MT>(acc[0], f0[g], f1[g]);
+      mfma_step<MT>(acc[1], f0[g], f2[g]);
+      if (three) mfma_step<MT>(acc[2], f2[g], f2[g]);
+    }
   }
 }
 
@@ -638,7 +647,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   const int split = (q / a.ntiles_super) * 8 + xcd;
   int SI, SJ;
   super_ij(st, SI, SJ);
-  const bool diag = (SI == SJ);
+  const bool diag = GRP || (SI == SJ);   // (the grouped form has one, diagonal, super-tile)
   const int na = min(a.sb, a.nbt - a.sb * SI);
   const int nb = min(a.sb, a.nbt - a.sb * SJ);
   const int rowsI = 32 * na;
@@ -690,7 +699,8 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
       }
     }
   }
-  const int64_t cnt = (a.slabs > split) ? (a.slabs - 1 - split) / a.nsplit + 1 : 0;
+  // slabs of this split (32-bit: the host keeps m * sizeof(Tin) below 2^31)
+  const int cnt = (a.slabs > split) ? (int)((a.slabs - 1 - split) / a.nsplit + 1) : 0;
   auto grow = [&](int lrow) -> int {
     return (lrow < rowsI) ? (32 * a.sb * SI + lrow) : (32 * a.sb * SJ + lrow - rowsI);
   };
@@ -699,7 +709,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   // [rows], weights [NB][64]
   unsigned char* stage = lds;
   unsigned char* tiles = stage + (size_t)NB * rows * SEG;
-  auto tile_of = [&](int64_t j) -> unsigned char* { return tiles + (size_t)(j % NT) * TR::PLANES * PLANE; };
+  auto tile_of = [&](int j) -> unsigned char* { return tiles + (size_t)(j % NT) * TR::PLANES * PLANE; };
   double* lmass = reinterpret_cast<double*>(tiles + (size_t)NT * TR::PLANES * PLANE);
   float* wsl = reinterpret_cast<float*>(lmass + rows);
 
@@ -714,23 +724,35 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   const uint32_t ldb = (uint32_t)(a.ld * (int64_t)sizeof(Tin));
   const int lr8 = lane >> 3;                 // row within an instruction
   const int lc = lane & 7;                   // 16-byte chunk within the row segment
-  auto issue = [&](int64_t j) {
-    const int64_t s = split + j * a.nsplit;
-    const bool ok = j < cnt;
-    if (loader) {
-      const bool pok = ok && s * KS + lc * EPC < a.m;
+  // Per lane, fixed across slabs: the byte offset of its chunk within row
+  // block i (OOB for rows past n) and the number of points left of its chunk.
+  // Per slab, in scalar registers: the slab's byte offset in a row (the
+  // loads' scalar offset) and its first point (past m for slabs beyond the
+  // split's share).  All offsets stay below 2^32: OOB + slab offset < 2^31 +
+  // m * sizeof(Tin) (the host keeps both below 2^31).
+  uint32_t vrow[LW];
 #pragma unroll
-      for (int i = 0; i < LW; ++i) {
-        const int r = 8 * i + lr8;
-        const uint32_t vo = (pok && r < nvalid) ? (uint32_t)r * ldb + (uint32_t)(s * SEG) + (uint32_t)lc * 16u : OOB;
-        dma_to_lds<16>(rsU, stage + ((size_t)(j % NB) * rows + RW * wave + 8 * i) * SEG, vo);
-      }
+  for (int i = 0; i < LW; ++i) {
+    const int r = 8 * i + lr8;
+    vrow[i] = (r < nvalid) ? (uint32_t)r * ldb + (uint32_t)lc * 16u : OOB;
+  }
+  const int plim = (int)a.m - lc * EPC;      // chunk in range: first point of the slab < plim
+  auto issue = [&](int j) {
+    const int64_t s = split + (int64_t)j * a.nsplit;
+    const bool ok = j < cnt;
+    const uint32_t sbyte = ok ? (uint32_t)(s * SEG) : 0u;
+    const int spt = ok ? (int)(s * KS) : INT_MAX;
+    if (loader) {
+      const bool pok = spt < plim;
+#pragma unroll
+      for (int i = 0; i < LW; ++i)
+        dma_to_lds<16>(rsU, stage + ((size_t)(j % NB) * rows + RW * wave + 8 * i) * SEG, pok ? vrow[i] : OOB,
+                       sbyte);
     }
     if constexpr (WEIGHTED) {
       if (wave == 0) {
-        const int64_t x = s * KS + lane;
-        const uint32_t vo = (ok && lane < KS && x < a.m) ? (uint32_t)(x * 4) : OOB;
-        dma_to_lds<4>(rsW, wsl + (size_t)(j % NB) * 64, vo);
+        const bool wok = lane < KS && spt < (int)a.m - lane;
+        dma_to_lds<4>(rsW, wsl + (size_t)(j % NB) * 64, wok ? (uint32_t)lane * 4u : OOB, sbyte / sizeof(Tin) * 4u);
       }
     }
   };
@@ -743,10 +765,10 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   // the slab about to be used has landed (NB - 2 later ones may be in flight)
   auto wait_slab = [&]() { wait_slab_n(std::integral_constant<int, NB - 2>()); };
 
-  // masses (diagonal super-tiles): the 8 lanes of a row add their chunk
-  // sums (fixed butterfly) and add the row sum in FP64, slab by slab, in
-  // registers: a thread's chunks belong to the same rows in every slab
-  // (row = (tid + NTH ci) / 8), so the sums stay in registers until the end.
+  // masses (diagonal super-tiles): a thread's chunks belong to the same rows
+  // in every slab (row = (tid + NTH ci) / 8), so each lane adds its chunk sum
+  // (FP32) to an FP64 register slab by slab; the 8 lanes of a row are added
+  // once at the end.
   double accm[CQ];
 #pragma unroll
   for (int ci = 0; ci < CQ; ++ci) accm[ci] = 0.0;
@@ -754,15 +776,16 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   // Convert slot j (slab s) into its tile.  No contraction: sqrt(w) * u is
   // rounded to FP32 and then to the MFMA type in every kernel variant, so
   // results do not depend on which variant ran.
-  auto convert = [&](int64_t j) {
+  auto convert = [&](int j) {
 #pragma clang fp contract(off)
-    const int64_t s = split + j * a.nsplit;
+    const int64_t s = split + (int64_t)j * a.nsplit;
     const unsigned char* src = stage + (size_t)(j % NB) * rows * SEG;
     unsigned char* tile = tile_of(j);
 #pragma unroll
     for (int ci = 0; ci < CQ; ++ci) {
+      // whole waves (rows * 8 and NTH are multiples of 64): a scalar branch
+      if (NTH * ci + 64 * wave >= rows * 8) break;
       const int qq = tid + NTH * ci;
-      if (qq >= rows * 8) break;
       const int row = qq >> 3, c = qq & 7;
       const Vec16<Tin> raw = *reinterpret_cast<const Vec16<Tin>*>(src + (size_t)row * SEG + c * 16);
       const int64_t x0 = s * KS + c * EPC;
@@ -775,18 +798,21 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
         if constexpr (MODE != MODE_NONE) u = (rv && x0 + e < a.m) ? u : 0.f;   // zeros read past the ends
         if constexpr (WEIGHTED) {
           const float wv = wsl[(size_t)(j % NB) * 64 + c * EPC + e];
-          msum += wv * u;
+          msum = (e == 0) ? wv * u : msum + wv * u;
           uv[e] = sqrtf(wv) * u;
         } else {
-          msum += u;
+          msum = (e == 0) ? u : msum + u;
           uv[e] = u;
         }
       }
       unsigned char* d = tile + (size_t)row * ROWB + (size_t)c * EPC * TR::EB;
       if constexpr (MT == MT_F16) {
+        // a product is rounded to FP32 first (no fused convert); plain
+        // values convert directly
+        constexpr bool PRODUCT = WEIGHTED || MODE != MODE_NONE;
         f16 o[EPC];
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) o[e] = to_f16_rounded(uv[e]);
+        for (int e = 0; e < EPC; ++e) o[e] = PRODUCT ? to_f16_rounded(uv[e]) : (f16)uv[e];
         store_lds<2 * EPC>(d, o);
       } else if constexpr (MT == MT_BF16) {
         uint16_t o[EPC];
@@ -803,7 +829,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
         store_lds<2 * EPC>(d, hi);
         store_lds<2 * EPC>(d + PLANE, lo);
       }
-      if (diag) accm[ci] += (double)sum8(msum);
+      if (diag) accm[ci] += (double)msum;
     }
   };
 
@@ -822,7 +848,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
     // one tile: convert, barrier, multiply
 #pragma unroll
     for (int j = 0; j < NB - 1; ++j) issue(j);
-    for (int64_t j = 0; j < cnt; ++j) {
+    for (int j = 0; j < cnt; ++j) {
       wait_slab();
       lds_barrier();            // every wave's rows of slab j are in LDS; the tile is free
       issue(j + NB - 1);        // into the slot converted in the previous step
@@ -841,7 +867,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
       lds_barrier();
       convert(0);
     }
-    for (int64_t j = 0; j < cnt; ++j) {
+    for (int j = 0; j < cnt; ++j) {
       wait_slab();              // slab j + 1
       lds_barrier();            // slab j + 1 is in LDS, tile j is complete, tile j + 1 is free
       issue(j + NB);            // into the slot of slab j, converted in the previous step
@@ -850,11 +876,15 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
     }
   }
   vm_wait<0>();               // no load into LDS outlives the workgroup
-  // row sums to LDS (lane c = 0 of each row)
+  // row sums to LDS: the 8 lanes of a row (fixed butterfly), then lane c = 0
 #pragma unroll
   for (int ci = 0; ci < CQ; ++ci) {
+    if (NTH * ci + 64 * wave >= rows * 8) break;
+    double t = accm[ci];
+#pragma unroll
+    for (int o = 1; o <= 4; o <<= 1) t += __shfl_xor(t, o, 64);
     const int qq = tid + NTH * ci;
-    if (qq < rows * 8 && (qq & 7) == 0) lmass[qq >> 3] = accm[ci];
+    if ((qq & 7) == 0) lmass[qq >> 3] = t;
   }
 
   // --- partial sub-tiles
