@@ -137,7 +137,7 @@ def headline(args):
     log("generating the 2D soft-mask ensemble N=256 on 512x512 (FP32)")
     U, _ = synth.config1(device=dev)
     n, m = U.shape
-    # one call computes both: the Gram kernel also forms the PID-mean sums
+    # one call computes both: PID-mean from the Gram row sums of the same pass
     both = pid.PreparedCall("both", U, gemm="f16", inclusion=True)
 
     def step():
@@ -167,7 +167,15 @@ def headline(args):
                                                  "pidmean_finalize", "rank")
                  if kernel_ms(pid, k)[1] > 0}
     pid.pid_timing_enable(False)
-    log(f"step {t_step * 1e3:.3f} ms; gram {kt['gram'][0] * 1e3:.1f} us in the timed region; breakdown " +
+    # for context, outside the timed region: the same steps with no events
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t1) / args.steps
+    log(f"step {t_step * 1e3:.3f} ms ({t_plain * 1e3:.3f} ms without kernel events); gram "
+        f"{kt['gram'][0] * 1e3:.1f} us in the timed region; breakdown " +
         ", ".join(f"{k} {v[0] * 1e3:.1f} us" for k, v in breakdown.items()))
 
     gram_ms = kt["gram"][0]
@@ -181,7 +189,8 @@ def headline(args):
     res_mean = {k: v.clone() for k, v in both.out_mean.items()}
     U_host = U.cpu().numpy()
 
-    extra = {"kernel_us": {k: round(v[0] * 1e3, 2) for k, v in breakdown.items()}}
+    extra = {"kernel_us": {k: round(v[0] * 1e3, 2) for k, v in breakdown.items()},
+             "step_us_without_kernel_events": round(t_plain * 1e6, 2)}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")

@@ -32,13 +32,13 @@ namespace pidk {
 // Fixed-order FP64 reduction of the split partials into the full symmetric
 // G (N x N, row-major) and the masses.  A block owns RED_ELEMS consecutive
 // partial elements, four per thread of a group (16-byte loads, so a group
-// reads 512 contiguous bytes of each split); its 8 thread groups sum the
-// splits k = g, g+8, g+16, ... (each in ascending k), and the group sums are
-// added in order g = 0..7.  The order depends on nsplit only, so results are
+// reads 256 contiguous bytes of each split); its 16 thread groups sum the
+// splits k = g, g+16, g+32, ... (each in ascending k), and the group sums are
+// added in order g = 0..15.  The order depends on nsplit only, so results are
 // deterministic.  The masses follow the packed sub-tiles as elements tot,
-// tot + 1, ... and are read one per lane.
-constexpr int RED_ELEMS = 128;
-constexpr int RED_GROUPS = 8;
+// tot + 1, ..., four per thread as well.
+constexpr int RED_ELEMS = 64;
+constexpr int RED_GROUPS = 16;
 constexpr int RED_EPT = 4;   // elements per thread
 
 template <typename PT>

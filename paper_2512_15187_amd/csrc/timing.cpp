@@ -27,6 +27,7 @@ std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, std::pair<double, int64_t>> g_tot;
 std::set<std::string> g_sel;   // kernels to time; empty = all
+constexpr size_t kPoolEvents = 512;   // pre-created when timing is switched on
 
 hipEvent_t take_event() {
   if (!g_pool.empty()) {
@@ -88,6 +89,12 @@ pid_status pid_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
   resolve_locked();
   g_tot.clear();
+  // events are created here, not in the launches being timed
+  while (on && g_pool.size() < kPoolEvents) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    g_pool.push_back(e);
+  }
   g_on.store(on != 0);
   return PID_OK;
 }
