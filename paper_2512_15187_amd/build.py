@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpid.so")
+# stand-alone counter-run driver (no torch), linked against libpid.so
+MEASURE = os.path.join(HERE, "pid_measure")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -96,8 +98,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     shutil.move(tmp, LIB)
+    cmd = [HIPCC, *COMMON, os.path.join(CSRC, "measure_main.hip"), "-o", MEASURE + ".tmp", "-L" + HERE, "-lpid",
+           "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"driver build failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    shutil.move(MEASURE + ".tmp", MEASURE)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {MEASURE}")
     return LIB
 
 
