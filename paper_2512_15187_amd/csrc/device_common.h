@@ -47,15 +47,35 @@ __device__ __forceinline__ double to_double(double v) { return v; }
 template <typename T>
 __device__ __forceinline__ double to_double(T v) { return (double)to_float(v); }
 
+// erfc(z) / 2 in FP32 by Abramowitz & Stegun 7.1.26: for x >= 0,
+//   erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x),
+// with |error| <= 1.5e-7, and erfc(-x) = 2 - erfc(x).  About a third of the
+// instructions of erfcf; with FP32 rounding and the hardware reciprocal and
+// exponential the result is within ~3e-7 of Phi, far below the FP16 rounding
+// of the values it feeds and the 1e-4 depth tolerance of the mixed-precision
+// paths.
+__device__ __forceinline__ float half_erfc_fast(float z) {
+  const float x = fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));   // 1 ulp
+  float q = fmaf(t, 1.061405429f, -1.453152027f);
+  q = fmaf(t, q, 1.421413741f);
+  q = fmaf(t, q, -0.284496736f);
+  q = fmaf(t, q, 0.254829592f);
+  const float h = 0.5f * t * q * __expf(-x * x);   // erfc(|z|) / 2
+  return z >= 0.0f ? h : 1.0f - h;
+}
+
 // Membership probability in float from a stored value (all input types but
-// double; doubles use extract_d).
-template <int MODE, typename T>
+// double; doubles use extract_d).  FAST selects half_erfc_fast for the
+// Gaussian model (the 16-bit MFMA Gram and PID-mean loaders); otherwise erfcf.
+template <int MODE, typename T, bool FAST = false>
 __device__ __forceinline__ float extract_f(T raw, const Extract& e) {
   float f = to_float(raw);
   if constexpr (MODE == MODE_NONE) {
     return f;
   } else if constexpr (MODE == MODE_GAUSS) {
-    return 0.5f * erfcf((f - e.cf) * e.af);
+    if constexpr (FAST) return half_erfc_fast((f - e.cf) * e.af);
+    else return 0.5f * erfcf((f - e.cf) * e.af);
   } else {
     return (e.side > 0) ? (f > e.c_dn ? 1.0f : 0.0f) : (f < e.c_up ? 1.0f : 0.0f);
   }

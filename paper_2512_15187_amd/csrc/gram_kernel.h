@@ -418,7 +418,7 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
           for (int e = 0; e < G4; ++e) {
             AccE u;
             if constexpr (MT == MT_F64 || sizeof(Tin) == 8) u = (AccE)extract_d<MODE>(pv.v[g + e], a.ex);
-            else u = (AccE)extract_f<MODE>(pv.v[g + e], a.ex);
+            else u = (AccE)extract_f<MODE, Tin, MT != MT_F32>(pv.v[g + e], a.ex);
             if (!rvalid) u = AccE(0);
             if (!full) u = (x0 + g + e < a.m) ? u : AccE(0);
             if constexpr (WEIGHTED) { msum += (AccE)wv[g + e] * u; uv[e] = (AccE)sqrtf(wv[g + e]) * u; }
@@ -790,12 +790,17 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
       const Vec16<Tin> raw = *reinterpret_cast<const Vec16<Tin>*>(src + (size_t)row * SEG + c * 16);
       const int64_t x0 = s * KS + c * EPC;
       const bool rv = grow(row) < a.n;
+      const int lim = (int)min((int64_t)EPC, a.m - x0);   // points of the chunk inside M
       float msum = 0.f;
       float uv[EPC];
 #pragma unroll
       for (int e = 0; e < EPC; ++e) {
-        float u = extract_f<MODE>(raw.v[e], a.ex);
-        if constexpr (MODE != MODE_NONE) u = (rv && x0 + e < a.m) ? u : 0.f;   // zeros read past the ends
+        float u = extract_f<MODE, Tin, true>(raw.v[e], a.ex);
+        if constexpr (MODE != MODE_NONE) {
+          // zeros read past the ends (a mask, so the model is not branched around)
+          const bool ok = rv && e < lim;
+          u = __int_as_float(__float_as_int(u) & (ok ? -1 : 0));
+        }
         if constexpr (WEIGHTED) {
           const float wv = wsl[(size_t)(j % NB) * 64 + c * EPC + e];
           msum = (e == 0) ? wv * u : msum + wv * u;

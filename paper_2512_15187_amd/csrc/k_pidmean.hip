@@ -35,7 +35,7 @@ __device__ __forceinline__ CT to_ct(T raw) {
 template <int MODE, typename T, typename CT>
 __device__ __forceinline__ CT extract_ct(T raw, const Extract& e) {
   if constexpr (std::is_same<CT, double>::value) return extract_d<MODE>(raw, e);
-  else return extract_f<MODE>(raw, e);
+  else return extract_f<MODE, T, true>(raw, e);
 }
 
 // ---------------------------------------------------------------------------
