@@ -539,6 +539,55 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
   for (int r = 0; r < MPW; ++r) { accm[r] = 0; acca[r] = 0; }
 
   int it = 0;
+  if constexpr (PACKED && !SFROM) {
+    // U8 masks (values 0/1) in one pass: byte-parallel arithmetic on the
+    // 16 bytes of a lane, four points per 32-bit word.  Column sums of the
+    // wave's members are packed byte adds (each byte <= MPW), the workgroup's
+    // column sums too (each byte <= nw * MPW <= 128); per member, m adds the
+    // bytes and A the byte products with s, both by v_dot4_u32_u8.
+    static_assert(MPW * 8 <= 255, "byte lanes hold the column sums of a workgroup");
+    uint32_t* sbw = reinterpret_cast<uint32_t*>(smem_raw);
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
+      const int64_t x0 = tile * TP + (int64_t)lane * PPL;
+      const bool full = (x0 + PPL <= m);
+      uint32_t raw[MPW][4];
+      uint32_t spw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int r = 0; r < MPW; ++r) {
+        const int i = mbase + r;
+        Vec16<T> v{};
+        if (i < n) {
+          const T* row = U + (int64_t)i * ld;
+          if (VEC && full) v = load16_nt(row + x0);
+          else v = load16_guarded(row, x0, m);
+        }
+        const uint4 q = __builtin_bit_cast(uint4, v);
+        raw[r][0] = q.x; raw[r][1] = q.y; raw[r][2] = q.z; raw[r][3] = q.w;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) spw[w] += raw[r][w];
+      }
+      uint32_t* sb = sbw + (size_t)(it & 1) * nw * 256;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) sb[wave * 256 + lane * 4 + w] = spw[w];
+      lds_barrier();
+      uint32_t sw[4] = {0u, 0u, 0u, 0u};
+      for (int q = 0; q < nw; ++q) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) sw[w] += sb[q * 256 + lane * 4 + w];
+      }
+#pragma unroll
+      for (int r = 0; r < MPW; ++r) {
+        uint32_t tm = 0u, ta = 0u;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          tm = __builtin_amdgcn_udot4(raw[r][w], 0x01010101u, tm, false);
+          ta = __builtin_amdgcn_udot4(raw[r][w], sw[w], ta, false);
+        }
+        accm[r] += (int)tm;
+        acca[r] += (int)ta;
+      }
+    }
+  } else
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
     const int64_t x0 = tile * TP + (int64_t)lane * PPL;
     const bool full = (x0 + PPL <= m);
