@@ -125,7 +125,8 @@ typedef struct {
 } pid_out;
 
 /* Bytes of device workspace needed by pid_all_pairs (variant 0), pid_mean
- * (variant 1) or pid_both (variant 2) for this ensemble, isovalue model and
+ * (variant 1), pid_both (variant 2) or pid_pairs_depths (variant 3; gemm is
+ * ignored) for this ensemble, isovalue model and
  * scheme.  The size depends on n, m, dtype, iso kind, weights (NULL or not)
  * and scheme only.  iso may be NULL (= PID_ISO_NONE). */
 pid_status pid_workspace_size(const pid_ensemble* ens, const pid_iso* iso, int variant,
@@ -140,6 +141,22 @@ pid_status pid_workspace_size(const pid_ensemble* ens, const pid_iso* iso, int v
  * with S_i = sum_j G_ij; IN_out = (sum over ascending j of G_ij/m_j) / N). */
 pid_status pid_all_pairs(const pid_ensemble* ens, const pid_iso* iso, int gemm,
                          const pid_out* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* All-pairs PID depths (Sec. 3.2 Eq. pid with the weighted sums of Sec. 3.4)
+ * without the N x N inclusion matrix, in O(N M) work: by linearity,
+ *   IN_in(i)  = S_i / (N m_i),  S_i = sum_x w u_i(x) s(x),  s = sum_j u_j,
+ *   IN_out(i) = (1/N) sum_j G_ji / m_j = (1/N) sum_x w u_i(x) t(x),
+ *   t(x) = sum_j u_j(x) / m_j  (members with m_j = 0 contribute 0),
+ * so three streaming passes replace the Gram product: the PID-mean pass
+ * (masses, IN_in), t into the workspace, and the row sums B_i = sum_x w u_i t
+ * (IN_out = B_i / N).  FP32 sums inside a tile and in t, FP64 across tiles
+ * (FP64 for FP64 input); binary input uses the same soft arithmetic for t and
+ * B (IN_in stays exact).  out->inclusion is ignored; the other fields as
+ * pid_all_pairs.  Workspace: pid_workspace_size(variant 3).  For large N, where
+ * the Gram product's N^2 M work dominates, this reads the masks three times
+ * instead. */
+pid_status pid_pairs_depths(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out,
+                            void* workspace, size_t ws_bytes, void* stream);
 
 /* PID-mean (Sec. 4.1): one streaming pass over the ensemble computes, for
  * every member, m_i and A_i = sum_x w u_i(x) s(x) with s(x) = sum_j u_j(x);

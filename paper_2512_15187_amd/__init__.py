@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "pid_workspace_size": ([P(pid_ensemble), P(pid_iso), I32, I32, P(ctypes.c_size_t)], I32),
         "pid_all_pairs": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_mean": ([P(pid_ensemble), P(pid_iso), P(pid_out), V, ctypes.c_size_t, V], I32),
+        "pid_pairs_depths": ([P(pid_ensemble), P(pid_iso), P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_both": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_extract": ([P(pid_ensemble), P(pid_iso), V, I32, V], I32),
         "pid_rank": ([V, I64, V, V, V], I32),
@@ -218,6 +219,21 @@ def pid_mean(U, weights=None, iso=None, workspace=None, stream=None, validate=Fa
     d, o = _outputs(U.shape[0], U.device, False)
     _check(lib.pid_mean(ctypes.byref(e), ctypes.byref(i), ctypes.byref(o),
                         ctypes.c_void_p(ws.data_ptr()), ws_n.value, _stream_ptr(stream)))
+    d["_workspace"] = ws
+    return d
+
+
+def pid_pairs_depths(U, weights=None, iso=None, workspace=None, stream=None, validate=False):
+    """All-pairs PID depths without the inclusion matrix (three streaming
+    passes, O(N M)).  Returns mass, in_in, in_out, depth (float64), rank, order."""
+    lib = load_library()
+    e, i = make_ensemble(U, weights, validate), make_iso(iso)
+    ws_n = ctypes.c_size_t(0)
+    _check(lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 3, 0, ctypes.byref(ws_n)))
+    ws = _workspace(ws_n.value, U.device, workspace)
+    d, o = _outputs(U.shape[0], U.device, False)
+    _check(lib.pid_pairs_depths(ctypes.byref(e), ctypes.byref(i), ctypes.byref(o),
+                                ctypes.c_void_p(ws.data_ptr()), ws_n.value, _stream_ptr(stream)))
     d["_workspace"] = ws
     return d
 

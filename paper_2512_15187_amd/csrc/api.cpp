@@ -187,8 +187,11 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
     s = workspace_size(ens, iso, 0, gemm, &kp);   // the all-pairs pass serves both
     if (s != PID_OK) return s;
     kb = kp;
+  } else if (variant == 3) {
+    kb = pidk::pairs_linear_workspace(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
   } else {
-    return fail(PID_ERR_INVALID_ARG, "variant must be 0 (all-pairs), 1 (PID-mean) or 2 (both)");
+    return fail(PID_ERR_INVALID_ARG,
+                "variant must be 0 (all-pairs), 1 (PID-mean), 2 (both) or 3 (all-pairs depths)");
   }
   *bytes = ((kb + 255) / 256) * 256 + extra_bytes(ens->n, variant == 2 ? 2 : 1);
   return PID_OK;
@@ -237,7 +240,7 @@ pid_status run_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const
 
 pid_status run(int variant, const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* out,
                void* ws, size_t ws_bytes, void* stream) {
-  if (variant != 0 && variant != 1) return fail(PID_ERR_INVALID_ARG, "variant must be 0 or 1 here");
+  if (variant != 0 && variant != 1 && variant != 3) return fail(PID_ERR_INVALID_ARG, "variant must be 0, 1 or 3 here");
   int kind = 0;
   pid_status s = check_ensemble(ens, iso, &kind);
   if (s != PID_OK) return s;
@@ -265,11 +268,15 @@ pid_status run(int variant, const pid_ensemble* ens, const pid_iso* iso, int gem
     resolve_scheme(ens, kind, gemm, &scheme);
     pidk::PairsPlan p = pidk::pairs_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr, scheme);
     err = pidk::launch_pid_pairs(p, *ens, kind, ex, o, ws, st);
+  } else if (variant == 3) {
+    o.inclusion = nullptr;
+    err = pidk::launch_pairs_linear(*ens, kind, ex, o, ws, st);
   } else {
     pidk::MeanPlan p = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
     err = pidk::launch_pid_mean(p, *ens, kind, ex, o, ws, st);
   }
-  if (err != hipSuccess) return hip_fail(err, variant == 0 ? "pid_all_pairs launch" : "pid_mean launch");
+  if (err != hipSuccess)
+    return hip_fail(err, variant == 0 ? "pid_all_pairs launch" : (variant == 3 ? "pid_pairs_depths launch" : "pid_mean launch"));
   if (want_rank) {
     err = pidk::launch_rank(o.depth, ens->n, o.rank, o.order, st);
     if (err != hipSuccess) return hip_fail(err, "rank launch");
@@ -289,6 +296,11 @@ pid_status pid_workspace_size(const pid_ensemble* ens, const pid_iso* iso, int v
 pid_status pid_all_pairs(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* out,
                          void* workspace, size_t ws_bytes, void* stream) {
   return pidapi::run(0, ens, iso, gemm, out, workspace, ws_bytes, stream);
+}
+
+pid_status pid_pairs_depths(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  return pidapi::run(3, ens, iso, PID_GEMM_AUTO, out, workspace, ws_bytes, stream);
 }
 
 pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out, void* workspace,

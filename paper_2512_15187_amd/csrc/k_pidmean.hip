@@ -768,6 +768,51 @@ __global__ __launch_bounds__(256) void pidmean_ratios(const void* __restrict__ r
 }
 
 // ---------------------------------------------------------------------------
+// All-pairs depths in O(N M) (no inclusion matrix).  With G_ji = sum_x w u_j u_i
+// (Sec. 3.2 / 3.4),
+//   IN_out(i) = (1/N) sum_j G_ji / m_j = (1/N) sum_x w u_i(x) t(x),
+//   t(x) = sum_j u_j(x) / m_j   (terms with m_j = 0 are 0),
+// so IN_out needs one column sum weighted by the inverse masses and one row
+// dot product; IN_in(i) = S_i / (N m_i) is the PID-mean IN_in (Sec. 4.1).
+
+// Inverse masses (0 for m = 0) in the compute type of the passes.
+template <typename CT>
+__global__ __launch_bounds__(256) void inv_mass_kernel(const double* __restrict__ mass, int n,
+                                                       CT* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) coef[i] = mass[i] > 0.0 ? (CT)(1.0 / mass[i]) : CT(0);
+}
+
+// t(x) = sum_j coef_j u_j(x), one point per thread (rows read coalesced
+// across the threads of a block), j in ascending order.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void colsum_scaled_kernel(const T* __restrict__ U, int64_t ld, int n, int64_t m,
+                                                            Extract ex, const ComputeT<T>* __restrict__ coef,
+                                                            ComputeT<T>* __restrict__ tout) {
+  using CT = ComputeT<T>;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m; x += (int64_t)gridDim.x * blockDim.x) {
+    CT t = CT(0);
+    for (int i = 0; i < n; ++i) t += coef[i] * extract_ct<MODE, T, CT>(U[(int64_t)i * ld + x], ex);
+    tout[x] = t;
+  }
+}
+
+// red = [m (n), B (n)] with B_i = sum_x w u_i t; in_in from the PID-mean pass.
+__global__ __launch_bounds__(256) void pairs_linear_ratios(const double* __restrict__ red,
+                                                           const double* __restrict__ in_in_pm, int n,
+                                                           double* __restrict__ m_out, double* __restrict__ in_in,
+                                                           double* __restrict__ in_out, double* __restrict__ depth) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ii = in_in_pm[i];
+  const double oo = red[n + i] / (double)n;
+  if (m_out) m_out[i] = red[i];
+  if (in_in) in_in[i] = ii;
+  if (in_out) in_out[i] = oo;
+  if (depth) depth[i] = ii < oo ? ii : oo;
+}
+
+// ---------------------------------------------------------------------------
 // Host side: plan, workspace and launch.
 
 static int elem_bytes(int dtype) {
@@ -1104,6 +1149,110 @@ hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   return launch_mean_finalize(p, e, part, red, nparts, out, st);
+}
+
+
+// ---------------------------------------------------------------------------
+// All-pairs depths without the inclusion matrix: the PID-mean pass (masses,
+// IN_in), then t = sum_j u_j / m_j into memory, then B_i = sum_x w u_i t with
+// the two-pass row kernel (soft arithmetic, also for binary input).
+static MeanPlan rows_plan(int64_t n, int64_t m, int dtype) {
+  // the two-pass configuration of mean_plan, soft arithmetic
+  MeanPlan p{};
+  const int eb = elem_bytes(dtype);
+  const int64_t cus = device_cu_count();
+  p.ntiles = (m + 64 * (16 / eb) - 1) / (64 * (16 / eb));
+  p.mpw = (n <= 32) ? 4 : (n <= 64 ? 8 : 16);
+  p.nwaves = (int)std::min<int64_t>(8, (n + p.mpw - 1) / p.mpw);
+  p.two_pass = 1;
+  p.groups = (int)((n + (int64_t)p.nwaves * p.mpw - 1) / ((int64_t)p.nwaves * p.mpw));
+  const int64_t g = std::max<int64_t>((p.ntiles + 15) / 16, std::max<int64_t>(1, cus * 2 / p.groups));
+  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, g));
+  return p;
+}
+
+size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted) {
+  const MeanPlan p1 = mean_plan(n, m, dtype, iso_kind, weighted);
+  const MeanPlan p3 = rows_plan(n, m, dtype);
+  // the same pieces, in the same order, as launch_pairs_linear carves
+  Carve c(nullptr);
+  c.take<char>(mean_workspace(p1, n, m));
+  c.take<double>((size_t)n);                     // masses
+  c.take<double>((size_t)n);                     // IN_in
+  c.take<double>((size_t)n);                     // coefficients 1 / m_j
+  c.take<double>((size_t)m);                     // t(x)
+  c.take<double>((size_t)p3.grid * 2 * n);       // row partials
+  c.take<double>((size_t)2 * n);                 // reduced m, B
+  return c.off + 256;
+}
+
+template <typename T>
+static void launch_linear_t(const pid_ensemble& e, int iso_kind, const Extract& ex, bool vec, const MeanPlan& p3,
+                            void* coef, void* tbuf, double* part, hipStream_t st) {
+  using CT = ComputeT<T>;
+  const T* U = reinterpret_cast<const T*>(e.data);
+  const int grid = (int)std::min<int64_t>((e.m + 255) / 256, device_cu_count() * 8);
+  {
+    KernelTimer tm("pidmean_colsum", st);
+    if (iso_kind == PID_ISO_GAUSSIAN)
+      hipLaunchKernelGGL((colsum_scaled_kernel<T, MODE_GAUSS>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
+                         (const CT*)coef, (CT*)tbuf);
+    else if (iso_kind == PID_ISO_STEP)
+      hipLaunchKernelGGL((colsum_scaled_kernel<T, MODE_STEP>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
+                         (const CT*)coef, (CT*)tbuf);
+    else
+      hipLaunchKernelGGL((colsum_scaled_kernel<T, MODE_NONE>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
+                         (const CT*)coef, (CT*)tbuf);
+  }
+  if (iso_kind == PID_ISO_GAUSSIAN) dispatch_mpw<T, MODE_GAUSS>(p3, e, ex, vec, tbuf, part, st);
+  else if (iso_kind == PID_ISO_STEP) dispatch_mpw<T, MODE_STEP>(p3, e, ex, vec, tbuf, part, st);
+  else dispatch_mpw<T, MODE_NONE>(p3, e, ex, vec, tbuf, part, st);
+}
+
+hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const ExtractHost& exh, const pid_out& out,
+                               void* ws, hipStream_t st) {
+  const MeanPlan p1 = mean_plan(e.n, e.m, e.dtype, iso_kind, e.weights != nullptr);
+  const MeanPlan p3 = rows_plan(e.n, e.m, e.dtype);
+  Carve c(ws);
+  void* ws1 = c.take<char>(mean_workspace(p1, e.n, e.m));
+  double* mass = c.take<double>((size_t)e.n);
+  double* inin = c.take<double>((size_t)e.n);
+  void* coef = c.take<double>((size_t)e.n);
+  void* tbuf = c.take<double>((size_t)e.m);
+  double* part = c.take<double>((size_t)p3.grid * 2 * e.n);
+  double* red = c.take<double>((size_t)2 * e.n);
+  // pass 1: masses and IN_in
+  pid_out o1{};
+  o1.mass = mass;
+  o1.in_in = inin;
+  hipError_t err = launch_pid_mean(p1, e, iso_kind, exh, o1, ws1, st);
+  if (err != hipSuccess) return err;
+  // coefficients 1 / m_j
+  const bool dbl = e.dtype == PID_F64;
+  if (dbl)
+    hipLaunchKernelGGL(inv_mass_kernel<double>, (int)((e.n + 255) / 256), 256, 0, st, mass, (int)e.n, (double*)coef);
+  else
+    hipLaunchKernelGGL(inv_mass_kernel<float>, (int)((e.n + 255) / 256), 256, 0, st, mass, (int)e.n, (float*)coef);
+  // passes 2 and 3: t, then B
+  Extract ex = __builtin_bit_cast(Extract, exh);
+  const int eb = elem_bytes(e.dtype);
+  const bool vec = ((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
+                   (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0);
+  switch (e.dtype) {
+    case PID_F64: launch_linear_t<double>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
+    case PID_F32: launch_linear_t<float>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
+    case PID_F16: launch_linear_t<f16>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
+    case PID_BF16: launch_linear_t<bf16_t>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
+    default: launch_linear_t<uint8_t>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
+  }
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  KernelTimer tm("pidmean_finalize", st);
+  dim3 rgrid((unsigned)e.n, 2);
+  hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, p3.grid, (int)e.n, red);
+  hipLaunchKernelGGL(pairs_linear_ratios, (int)((e.n + 255) / 256), 256, 0, st, red, inin, (int)e.n, out.mass,
+                     out.in_in, out.in_out, out.depth);
+  return hipGetLastError();
 }
 
 }  // namespace pidk

@@ -55,6 +55,11 @@ size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m);
 hipError_t launch_pid_mean(const MeanPlan& p, const pid_ensemble& e, int iso_kind,
                            const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st);
 
+// All-pairs depths (no inclusion matrix) in three streaming passes.
+size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted);
+hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, const pid_out& out,
+                               void* ws, hipStream_t st);
+
 // ---------------------------------------------------------------- all-pairs
 enum Scheme { SCH_F64 = 1, SCH_F32 = 2, SCH_F16 = 3, SCH_BF16 = 4, SCH_BF16_SPLIT = 5, SCH_I8 = 6 };
 

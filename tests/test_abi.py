@@ -18,7 +18,8 @@ def _lib():
 def test_exports_every_declared_symbol():
     lib = _lib()
     names = pid.declared_symbols()
-    expected = {"pid_workspace_size", "pid_all_pairs", "pid_mean", "pid_both", "pid_extract", "pid_rank",
+    expected = {"pid_workspace_size", "pid_all_pairs", "pid_mean", "pid_both", "pid_pairs_depths", "pid_extract",
+                "pid_rank",
                 "pid_server_create", "pid_submit", "pid_poll", "pid_wait", "pid_request_times",
                 "pid_server_destroy", "pid_status_string", "pid_last_error", "pid_abi_version",
                 "pid_timing_enable", "pid_timing_get", "pid_timing_select"}
@@ -73,8 +74,11 @@ def test_scheme_checks_on_host():
     # unknown scheme / variant
     assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 0, 42, ctypes.byref(nbytes)) \
         == pid.PID_ERR_INVALID_ARG
-    assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 3, 0, ctypes.byref(nbytes)) \
+    assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 4, 0, ctypes.byref(nbytes)) \
         == pid.PID_ERR_INVALID_ARG
+    # variant 3 (all-pairs depths without the matrix) is sized on the host
+    assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 3, 0, ctypes.byref(nbytes)) == pid.PID_OK
+    assert nbytes.value > 0
     # the combined call needs both output structs
     assert lib.pid_both(ctypes.byref(e), ctypes.byref(i), 0, None, None, ctypes.c_void_p(0x1000), 1 << 20,
                         None) == pid.PID_ERR_INVALID_ARG

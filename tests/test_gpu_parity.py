@@ -297,6 +297,48 @@ def test_pid_both(n, m, dtype, weighted, gemm):
     assert_ranks(rm["rank"], ref["depth"], TOL_OF[gemm], label="both mean")
 
 
+# ------------------------------------------------- all-pairs depths, O(N M)
+# Tolerance: t(x) = sum_j u_j / m_j and the tile sums of B_i = sum_x w u_i t are
+# FP32 (N and up to 16 x 1024 positive terms, relative error ~1e-6 typical,
+# N * 6e-8 at worst), so 1e-5 absolute on the depths; FP64 input sums in FP64.
+LIN_CASES = [
+    # (n, m, dtype, weighted)
+    (64, 64 * 300, torch.float32, False),
+    (200, 32 * 777 + 20, torch.float32, True),
+    (300, 4000, torch.float16, False),      # members in several groups
+    (37, 5003, torch.float32, True),        # rows not 16-byte aligned
+    (9, 100, torch.bfloat16, False),
+    (50, 4096, torch.float64, False),
+]
+
+
+@pytest.mark.parametrize("n,m,dtype,weighted", LIN_CASES,
+                         ids=[f"{c[0]}x{c[1]}-{str(c[2])[6:]}-{'w' if c[3] else 'u'}" for c in LIN_CASES])
+def test_pairs_depths_linear(n, m, dtype, weighted):
+    """pid_pairs_depths against the all-pairs oracle (no inclusion matrix)."""
+    U = _soft(n, m, 500 + n, dtype)
+    w = _weights(m, 11) if weighted else None
+    res = pid.pid_pairs_depths(_dev(U), None if w is None else _dev(w))
+    ref = oracle.pid(_ref_input(U), None if w is None else w.numpy())
+    tol = TOL_F64 if dtype == torch.float64 else 1e-5
+    assert_close(res, ref, tol, keys=("mass_rel", "in_in", "in_out", "depth"), label=f"linear {n}x{m}")
+    assert_ranks(res["rank"], ref["depth"], tol, label="linear")
+
+
+def test_pairs_depths_linear_fields_and_binary():
+    """Gaussian fields, and binary input (IN_in exact; IN_out in soft arithmetic)."""
+    F = _fields(48, 3001, 71)
+    iso = dict(kind="gaussian", c=0.5, sigma=0.05, side=1)
+    res = pid.pid_pairs_depths(_dev(F), iso=iso)
+    ref = oracle.pid(oracle.extract(F.numpy(), iso))
+    assert_close(res, ref, 1e-5, keys=("mass_rel", "in_in", "in_out", "depth"), label="linear gauss")
+    B = synth.random_binary(70, 2000, 72)
+    rb = pid.pid_pairs_depths(_dev(B))
+    refb = oracle.binary_pid(B.numpy())
+    assert np.array_equal(np64(rb["in_in"]), refb["in_in"]), "binary IN_in not exact"
+    assert_close(rb, refb, 1e-5, keys=("mass_rel", "in_in", "in_out", "depth"), label="linear binary")
+
+
 @pytest.mark.parametrize("n,m,kind", [(40, 5000, "u8"), (257, 2222, "step")])
 def test_pid_both_binary_bitexact(n, m, kind):
     """Binary input through INT8: both depth kinds bitwise equal to the
