@@ -300,6 +300,22 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
             out[f"{name}_pp_per_s"] = nf * nf * mf / t
     del F
 
+    # all-pairs depths without the matrix (three streaming passes) against
+    # the FP16 Gram at a large N, where the Gram's N^2 M work dominates
+    log("large-N all-pairs depths: N=2048 on 256x256 (FP16 masks), Gram vs O(N M)")
+    UL = synth.config1(device=dev, res=256, n=2048)[0].to(torch.float16)
+    nl, ml = UL.shape
+    gl = pid.PreparedCall("pairs", UL, gemm="f16")
+    dl = pid.PreparedCall("depths", UL)
+    tg = timed(gl.run, k, 2, torch)
+    td = timed(dl.run, k, 2, torch)
+    out["largeN_n2048_m65536_gram_f16_call_ms"] = tg * 1e3
+    out["largeN_n2048_m65536_linear_call_ms"] = td * 1e3
+    out["largeN_linear_speedup"] = tg / td
+    out["largeN_linear_GBps_3_reads"] = 3 * nl * ml * 2 / td / 1e9
+    out["largeN_max_depth_diff_linear_vs_gram"] = float((gl.out["depth"] - dl.out["depth"]).abs().max())
+    del UL, gl, dl
+
     # 2D FP64 plain PID, N=50 on 128x128
     U0, _ = synth.config0(device=dev)
     p0 = pid.PreparedCall("pairs", U0, gemm="f64")

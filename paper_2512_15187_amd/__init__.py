@@ -285,12 +285,13 @@ def pid_rank(depth, stream=None):
 class PreparedCall:
     """One depth call with its structs, outputs and workspace allocated once,
     so that repeated ``run()`` calls allocate nothing (benchmark loops,
-    serving drivers).  variant: "pairs", "mean" or "both" (then ``out`` holds
-    the all-pairs results and ``out_mean`` the PID-mean ones)."""
+    serving drivers).  variant: "pairs", "mean", "both" (then ``out`` holds
+    the all-pairs results and ``out_mean`` the PID-mean ones) or "depths"
+    (all-pairs depths without the inclusion matrix)."""
 
     def __init__(self, variant, U, weights=None, iso=None, gemm="auto", inclusion=False):
         lib = load_library()
-        self.variant = {"pairs": 0, "mean": 1, "both": 2}[variant]
+        self.variant = {"pairs": 0, "mean": 1, "both": 2, "depths": 3}[variant]
         self.gemm = GEMM[gemm]
         self.e, self.i = make_ensemble(U, weights), make_iso(iso)
         n = ctypes.c_size_t(0)
@@ -298,7 +299,7 @@ class PreparedCall:
                                       ctypes.byref(n)))
         self.ws_bytes = n.value
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=U.device)
-        self.out, self.o = _outputs(U.shape[0], U.device, inclusion and self.variant != 1)
+        self.out, self.o = _outputs(U.shape[0], U.device, inclusion and self.variant in (0, 2))
         if self.variant == 2:
             self.out_mean, self.om = _outputs(U.shape[0], U.device, False)
         self._keep = (U, weights)
@@ -313,6 +314,9 @@ class PreparedCall:
         elif self.variant == 1:
             _check(lib.pid_mean(ctypes.byref(self.e), ctypes.byref(self.i), ctypes.byref(self.o), ws,
                                 self.ws_bytes, st))
+        elif self.variant == 3:
+            _check(lib.pid_pairs_depths(ctypes.byref(self.e), ctypes.byref(self.i), ctypes.byref(self.o), ws,
+                                        self.ws_bytes, st))
         else:
             _check(lib.pid_both(ctypes.byref(self.e), ctypes.byref(self.i), self.gemm, ctypes.byref(self.o),
                                 ctypes.byref(self.om), ws, self.ws_bytes, st))

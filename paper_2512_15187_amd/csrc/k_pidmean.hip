@@ -668,22 +668,69 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Column sums s(x) for the two-pass case (N larger than one workgroup holds).
-template <typename T, int MODE, bool BIN>
-__global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ U, int64_t ld, int n,
-                                                     int64_t m, Extract ex, void* __restrict__ sout) {
+// Column sums over the members for the two-pass cases: s(x) = sum_j u_j(x)
+// (exact integers for binary input) and, for all-pairs depths without the
+// matrix, t(x) = sum_j coef_j u_j(x).  Block (bx, g) owns 64 * PPL points (16
+// bytes of every row per lane) and the members [g chunk, (g + 1) chunk); its 4
+// waves take the members q, q + 4, ... of that range in ascending order, four
+// rows in flight, and add their sums in order q = 0..3; the member groups'
+// sums are added in order g = 0, 1, ... by colsum_combine.
+template <typename T, int MODE, bool BIN, bool SCALED>
+__global__ __launch_bounds__(256) void colsum_part_kernel(const T* __restrict__ U, int64_t ld, int n, int64_t m,
+                                                          Extract ex, const ComputeT<T>* __restrict__ coef,
+                                                          int chunk, void* __restrict__ part_v, int vec) {
   using CT = ComputeT<T>;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m;
-       x += (int64_t)gridDim.x * blockDim.x) {
+  using AT = typename std::conditional<BIN, int, CT>::type;
+  constexpr int PPL = Vec16<T>::N;
+  __shared__ AT part[4][64 * PPL];
+  const int lane = threadIdx.x & 63;
+  const int q = threadIdx.x >> 6;
+  const int64_t x0 = (int64_t)blockIdx.x * (64 * PPL) + (int64_t)lane * PPL;
+  const bool full = vec && x0 + PPL <= m;
+  const int i0 = blockIdx.y * chunk, i1 = min(n, i0 + chunk);
+  AT t[PPL];
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) t[p] = AT(0);
+  auto row = [&](int i) -> Vec16<T> {
+    const T* r = U + (int64_t)i * ld;
+    return full ? load16_nt(r + x0) : load16_guarded(r, x0, m);
+  };
+  auto add = [&](int i, const Vec16<T>& v) {
     if constexpr (BIN) {
-      int s = 0;
-      for (int i = 0; i < n; ++i) s += extract_bit<MODE>(U[(int64_t)i * ld + x], ex);
-      reinterpret_cast<int*>(sout)[x] = s;
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) t[p] += extract_bit<MODE>(v.v[p], ex);
     } else {
-      CT s = CT(0);
-      for (int i = 0; i < n; ++i) s += extract_ct<MODE, T, CT>(U[(int64_t)i * ld + x], ex);
-      reinterpret_cast<CT*>(sout)[x] = s;
+      const CT c = SCALED ? coef[i] : CT(1);
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        const CT u = extract_ct<MODE, T, CT>(v.v[p], ex);
+        t[p] += SCALED ? c * u : u;
+      }
     }
+  };
+  int i = i0 + q;
+  for (; i + 12 < i1; i += 16) {
+    const Vec16<T> a0 = row(i), a1 = row(i + 4), a2 = row(i + 8), a3 = row(i + 12);
+    add(i, a0); add(i + 4, a1); add(i + 8, a2); add(i + 12, a3);
+  }
+  for (; i < i1; i += 4) add(i, row(i));
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) part[q][lane * PPL + p] = t[p];
+  __syncthreads();
+  AT* out = reinterpret_cast<AT*>(part_v) + (size_t)blockIdx.y * m;
+  for (int e = threadIdx.x; e < 64 * PPL; e += 256) {
+    const int64_t x = (int64_t)blockIdx.x * (64 * PPL) + e;
+    if (x < m) out[x] = ((part[0][e] + part[1][e]) + part[2][e]) + part[3][e];
+  }
+}
+
+template <typename AT>
+__global__ __launch_bounds__(256) void colsum_combine(const AT* __restrict__ part, int groups, int64_t m,
+                                                      AT* __restrict__ out) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m; x += (int64_t)gridDim.x * blockDim.x) {
+    AT s = part[x];
+    for (int g = 1; g < groups; ++g) s += part[(size_t)g * m + x];
+    out[x] = s;
   }
 }
 
@@ -783,20 +830,6 @@ __global__ __launch_bounds__(256) void inv_mass_kernel(const double* __restrict_
   if (i < n) coef[i] = mass[i] > 0.0 ? (CT)(1.0 / mass[i]) : CT(0);
 }
 
-// t(x) = sum_j coef_j u_j(x), one point per thread (rows read coalesced
-// across the threads of a block), j in ascending order.
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void colsum_scaled_kernel(const T* __restrict__ U, int64_t ld, int n, int64_t m,
-                                                            Extract ex, const ComputeT<T>* __restrict__ coef,
-                                                            ComputeT<T>* __restrict__ tout) {
-  using CT = ComputeT<T>;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m; x += (int64_t)gridDim.x * blockDim.x) {
-    CT t = CT(0);
-    for (int i = 0; i < n; ++i) t += coef[i] * extract_ct<MODE, T, CT>(U[(int64_t)i * ld + x], ex);
-    tout[x] = t;
-  }
-}
-
 // red = [m (n), B (n)] with B_i = sum_x w u_i t; in_in from the PID-mean pass.
 __global__ __launch_bounds__(256) void pairs_linear_ratios(const double* __restrict__ red,
                                                            const double* __restrict__ in_in_pm, int n,
@@ -828,6 +861,16 @@ static bool is_binary(int dtype, int iso_kind, bool weighted) {
   if (weighted) return false;
   return iso_kind == PID_ISO_STEP || (dtype == PID_U8 && iso_kind == PID_ISO_NONE);
 }
+
+// Member groups of a column-sum pass: enough blocks of 4 waves to fill the
+// GPU (8 per CU), at least 16 members per group, at most 64 groups.
+static int colsum_groups(int64_t n, int64_t m, int eb) {
+  const int64_t bx = (m + 64 * (16 / eb) - 1) / (64 * (16 / eb));
+  int64_t g = ((int64_t)device_cu_count() * 8 + bx - 1) / bx;
+  g = std::min<int64_t>(g, std::max<int64_t>(1, (n + 15) / 16));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 64));
+}
+
 
 // Optional tuning overrides, read once: PID_TUNE_MEAN_MPW (members per wave:
 // 4, 8 or 16) and PID_TUNE_MEAN_TPW (tiles per workgroup, 1..64).  They
@@ -925,6 +968,7 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
     p.two_pass = 1;
     nw = 8;
     p.groups = (int)((n + (int64_t)nw * mpw - 1) / ((int64_t)nw * mpw));
+    p.colsum_groups = colsum_groups(n, m, eb);
   }
   p.mpw = mpw;
   p.nwaves = nw;
@@ -942,7 +986,10 @@ size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m) {
   Carve c(nullptr);
   c.take<double>((size_t)std::max(std::max(p.grid, p.pipe_grid), p.dma_grid) * 2 * n);   // partials
   c.take<double>((size_t)2 * n);            // reduced A and m
-  if (p.two_pass) c.take<double>((size_t)m);  // column sums
+  if (p.two_pass) {
+    c.take<double>((size_t)m);              // column sums
+    c.take<double>((size_t)m * (size_t)p.colsum_groups);   // their member-group partials
+  }
   return c.off + 256;
 }
 
@@ -1041,23 +1088,42 @@ static void dispatch_mode(const MeanPlan& p, const pid_ensemble& e, int iso_kind
   }
 }
 
+template <typename T, int MODE, bool BIN, bool SCALED>
+static void launch_colsum_g(const pid_ensemble& e, const Extract& ex, int groups, const void* coef, void* gpart,
+                            void* sout, bool vec, hipStream_t st) {
+  using CT = ComputeT<T>;
+  using AT = typename std::conditional<BIN, int, CT>::type;
+  constexpr int PPL = Vec16<T>::N;
+  const T* U = reinterpret_cast<const T*>(e.data);
+  const dim3 grid((unsigned)((e.m + 64 * PPL - 1) / (64 * PPL)), (unsigned)groups);
+  const int chunk = (int)((e.n + groups - 1) / groups);
+  KernelTimer tm("pidmean_colsum", st);
+  void* dst = groups > 1 ? gpart : sout;
+  hipLaunchKernelGGL((colsum_part_kernel<T, MODE, BIN, SCALED>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
+                     (const CT*)coef, chunk, dst, vec ? 1 : 0);
+  if (groups > 1) {
+    const int cgrid = (int)std::min<int64_t>((e.m + 255) / 256, device_cu_count() * 8);
+    hipLaunchKernelGGL(colsum_combine<AT>, cgrid, 256, 0, st, (const AT*)gpart, groups, e.m, (AT*)sout);
+  }
+}
+
 template <typename T>
 static void launch_colsum(const MeanPlan& p, const pid_ensemble& e, int iso_kind, const Extract& ex,
-                          void* sout, hipStream_t st) {
-  const T* U = reinterpret_cast<const T*>(e.data);
-  int grid = (int)std::min<int64_t>((e.m + 255) / 256, device_cu_count() * 8);
-  KernelTimer tm("pidmean_colsum", st);
+                          void* sout, void* gpart, bool vec, hipStream_t st) {
+  const int g = p.colsum_groups;
   if (p.binary) {
-    if (iso_kind == PID_ISO_STEP)
-      hipLaunchKernelGGL((colsum_kernel<T, MODE_STEP, true>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex, sout);
-    else
-      hipLaunchKernelGGL((colsum_kernel<T, MODE_NONE, true>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex, sout);
+    if constexpr (!std::is_same<T, double>::value) {
+      if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, true, false>(e, ex, g, nullptr, gpart, sout, vec, st);
+      else launch_colsum_g<T, MODE_NONE, true, false>(e, ex, g, nullptr, gpart, sout, vec, st);
+    } else {
+      launch_colsum_g<T, MODE_STEP, true, false>(e, ex, g, nullptr, gpart, sout, vec, st);
+    }
   } else if (iso_kind == PID_ISO_GAUSSIAN) {
-    hipLaunchKernelGGL((colsum_kernel<T, MODE_GAUSS, false>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex, sout);
+    launch_colsum_g<T, MODE_GAUSS, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   } else if (iso_kind == PID_ISO_STEP) {
-    hipLaunchKernelGGL((colsum_kernel<T, MODE_STEP, false>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex, sout);
+    launch_colsum_g<T, MODE_STEP, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   } else {
-    hipLaunchKernelGGL((colsum_kernel<T, MODE_NONE, false>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex, sout);
+    launch_colsum_g<T, MODE_NONE, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   }
 }
 
@@ -1102,6 +1168,7 @@ hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_
   void* part = c.take<double>((size_t)std::max(std::max(plan.grid, plan.pipe_grid), plan.dma_grid) * 2 * e.n);
   void* red = c.take<double>((size_t)2 * e.n);
   void* sbuf = plan.two_pass ? (void*)c.take<double>((size_t)e.m) : nullptr;
+  void* gpart = plan.two_pass ? (void*)c.take<double>((size_t)e.m * (size_t)plan.colsum_groups) : nullptr;
   const int eb = elem_bytes(e.dtype);
   const bool vec = ((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
                    (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0);
@@ -1131,19 +1198,19 @@ hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_
   const int nparts = p.pipe_lb ? p.pipe_grid : p.grid;
   switch (e.dtype) {
     case PID_F64:
-      if (p.two_pass) launch_colsum<double>(p, e, iso_kind, ex, sbuf, st);
+      if (p.two_pass) launch_colsum<double>(p, e, iso_kind, ex, sbuf, gpart, vec, st);
       dispatch_mode<double>(p, e, iso_kind, ex, vec, sbuf, part, st); break;
     case PID_F32:
-      if (p.two_pass) launch_colsum<float>(p, e, iso_kind, ex, sbuf, st);
+      if (p.two_pass) launch_colsum<float>(p, e, iso_kind, ex, sbuf, gpart, vec, st);
       dispatch_mode<float>(p, e, iso_kind, ex, vec, sbuf, part, st); break;
     case PID_F16:
-      if (p.two_pass) launch_colsum<f16>(p, e, iso_kind, ex, sbuf, st);
+      if (p.two_pass) launch_colsum<f16>(p, e, iso_kind, ex, sbuf, gpart, vec, st);
       dispatch_mode<f16>(p, e, iso_kind, ex, vec, sbuf, part, st); break;
     case PID_BF16:
-      if (p.two_pass) launch_colsum<bf16_t>(p, e, iso_kind, ex, sbuf, st);
+      if (p.two_pass) launch_colsum<bf16_t>(p, e, iso_kind, ex, sbuf, gpart, vec, st);
       dispatch_mode<bf16_t>(p, e, iso_kind, ex, vec, sbuf, part, st); break;
     default:
-      if (p.two_pass) launch_colsum<uint8_t>(p, e, iso_kind, ex, sbuf, st);
+      if (p.two_pass) launch_colsum<uint8_t>(p, e, iso_kind, ex, sbuf, gpart, vec, st);
       dispatch_mode<uint8_t>(p, e, iso_kind, ex, vec, sbuf, part, st); break;
   }
   hipError_t err = hipGetLastError();
@@ -1181,6 +1248,7 @@ size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, boo
   c.take<double>((size_t)n);                     // IN_in
   c.take<double>((size_t)n);                     // coefficients 1 / m_j
   c.take<double>((size_t)m);                     // t(x)
+  c.take<double>((size_t)m * (size_t)colsum_groups(n, m, elem_bytes(dtype)));   // member-group partials of t
   c.take<double>((size_t)p3.grid * 2 * n);       // row partials
   c.take<double>((size_t)2 * n);                 // reduced m, B
   return c.off + 256;
@@ -1188,22 +1256,10 @@ size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, boo
 
 template <typename T>
 static void launch_linear_t(const pid_ensemble& e, int iso_kind, const Extract& ex, bool vec, const MeanPlan& p3,
-                            void* coef, void* tbuf, double* part, hipStream_t st) {
-  using CT = ComputeT<T>;
-  const T* U = reinterpret_cast<const T*>(e.data);
-  const int grid = (int)std::min<int64_t>((e.m + 255) / 256, device_cu_count() * 8);
-  {
-    KernelTimer tm("pidmean_colsum", st);
-    if (iso_kind == PID_ISO_GAUSSIAN)
-      hipLaunchKernelGGL((colsum_scaled_kernel<T, MODE_GAUSS>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
-                         (const CT*)coef, (CT*)tbuf);
-    else if (iso_kind == PID_ISO_STEP)
-      hipLaunchKernelGGL((colsum_scaled_kernel<T, MODE_STEP>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
-                         (const CT*)coef, (CT*)tbuf);
-    else
-      hipLaunchKernelGGL((colsum_scaled_kernel<T, MODE_NONE>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
-                         (const CT*)coef, (CT*)tbuf);
-  }
+                            void* coef, int tg, void* tpart, void* tbuf, double* part, hipStream_t st) {
+  if (iso_kind == PID_ISO_GAUSSIAN) launch_colsum_g<T, MODE_GAUSS, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
+  else if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
+  else launch_colsum_g<T, MODE_NONE, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
   if (iso_kind == PID_ISO_GAUSSIAN) dispatch_mpw<T, MODE_GAUSS>(p3, e, ex, vec, tbuf, part, st);
   else if (iso_kind == PID_ISO_STEP) dispatch_mpw<T, MODE_STEP>(p3, e, ex, vec, tbuf, part, st);
   else dispatch_mpw<T, MODE_NONE>(p3, e, ex, vec, tbuf, part, st);
@@ -1219,6 +1275,8 @@ hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const Extrac
   double* inin = c.take<double>((size_t)e.n);
   void* coef = c.take<double>((size_t)e.n);
   void* tbuf = c.take<double>((size_t)e.m);
+  const int tg = colsum_groups(e.n, e.m, elem_bytes(e.dtype));
+  void* tpart = c.take<double>((size_t)e.m * (size_t)tg);
   double* part = c.take<double>((size_t)p3.grid * 2 * e.n);
   double* red = c.take<double>((size_t)2 * e.n);
   // pass 1: masses and IN_in
@@ -1239,11 +1297,11 @@ hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const Extrac
   const bool vec = ((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
                    (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0);
   switch (e.dtype) {
-    case PID_F64: launch_linear_t<double>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
-    case PID_F32: launch_linear_t<float>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
-    case PID_F16: launch_linear_t<f16>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
-    case PID_BF16: launch_linear_t<bf16_t>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
-    default: launch_linear_t<uint8_t>(e, iso_kind, ex, vec, p3, coef, tbuf, part, st); break;
+    case PID_F64: launch_linear_t<double>(e, iso_kind, ex, vec, p3, coef, tg, tpart, tbuf, part, st); break;
+    case PID_F32: launch_linear_t<float>(e, iso_kind, ex, vec, p3, coef, tg, tpart, tbuf, part, st); break;
+    case PID_F16: launch_linear_t<f16>(e, iso_kind, ex, vec, p3, coef, tg, tpart, tbuf, part, st); break;
+    case PID_BF16: launch_linear_t<bf16_t>(e, iso_kind, ex, vec, p3, coef, tg, tpart, tbuf, part, st); break;
+    default: launch_linear_t<uint8_t>(e, iso_kind, ex, vec, p3, coef, tg, tpart, tbuf, part, st); break;
   }
   err = hipGetLastError();
   if (err != hipSuccess) return err;

@@ -46,6 +46,7 @@ struct MeanPlan {
   int pipe_lb;      // >0: pipelined single pass with LB-byte loads (aligned rows)
   int pipe_grid;    // its grid
   int fb_mpw, fb_nwaves;   // the unpipelined kernel's slices when rows are not aligned
+  int colsum_groups;   // two-pass: member groups of the column-sum pass
   int dma_rpw;      // >0: LDS-staged single pass, rows per wave (soft masks)
   int dma_nwaves, dma_grid;
   size_t dma_lds;

@@ -309,6 +309,7 @@ LIN_CASES = [
     (37, 5003, torch.float32, True),        # rows not 16-byte aligned
     (9, 100, torch.bfloat16, False),
     (50, 4096, torch.float64, False),
+    (600, 6000, torch.float32, True),       # member groups in both column-sum passes
 ]
 
 
