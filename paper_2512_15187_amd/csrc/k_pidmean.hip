@@ -227,8 +227,11 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_pipe_kernel(
 #pragma unroll
     for (int r = 0; r < MPW; ++r) buf[r] = bufload_nt<T, LB>(rsU, vo, (uint32_t)min(r, rl) * ldb);
     if constexpr (WEIGHTED) {
+      // wave 0 reads the tile's weights (shared through LDS); the other
+      // waves issue the same loads past the buffer's end (no memory access,
+      // the same instructions, so the wait counts stay the same)
       constexpr int WB = PPL * 4 < 16 ? PPL * 4 : 16;   // bytes per weight load
-      const uint32_t wo = ok ? x * 4u : OOB;
+      const uint32_t wo = (ok && wave == 0) ? x * 4u : OOB;
 #pragma unroll
       for (int o = 0; o < PPL; o += WB / 4) {
         const VecB<float, WB> t = bufload_nt<float, WB>(rsW, wo + 4u * o, 0u);
@@ -245,6 +248,8 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_pipe_kernel(
 #pragma unroll
   for (int r = 0; r < MPW; ++r) { accm[r] = CT(0); acca[r] = CT(0); }
   double* lacc = reinterpret_cast<double*>(sbuf + (size_t)2 * nw * TP) + (size_t)wave * MPW * 2;
+  float* wsh = reinterpret_cast<float*>(reinterpret_cast<double*>(sbuf + (size_t)2 * nw * TP) + (size_t)nw * MPW * 2);
+                                                          // [2][TP] weights of the tile (wave 0's loads)
   if (lane == 0) {
 #pragma unroll
     for (int r = 0; r < 2 * MPW; ++r) lacc[r] = 0.0;
@@ -294,7 +299,18 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_pipe_kernel(
     CT* sb = sbuf + (size_t)parity * nw * TP;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) sb[wave * TP + lane * PPL + p] = sp[p];
+    if constexpr (WEIGHTED) {
+      if (wave == 0) {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) wsh[(size_t)parity * TP + lane * PPL + p] = wb[p];
+      }
+    }
     lds_barrier();
+    float wl[WEIGHTED ? PPL : 1];
+    if constexpr (WEIGHTED) {
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) wl[p] = wsh[(size_t)parity * TP + lane * PPL + p];
+    }
     CT s[PPL];
 #pragma unroll
     for (int p = 0; p < PPL; ++p) s[p] = CT(0);
@@ -304,7 +320,7 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_pipe_kernel(
     }
     if constexpr (WEIGHTED) {
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) s[p] *= (CT)wb[p];   // s now holds w * s
+      for (int p = 0; p < PPL; ++p) s[p] *= (CT)wl[p];   // s now holds w * s
     }
 #pragma unroll
     for (int r = 0; r < MPW; ++r) {
@@ -314,7 +330,7 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_pipe_kernel(
         CT uv;
         if constexpr (KEEP_RAW) uv = extract_ct<MODE, T, CT>(buf[r].v[p], ex);
         else uv = u[r][p];
-        if constexpr (WEIGHTED) tm += (CT)wb[p] * uv;
+        if constexpr (WEIGHTED) tm += (CT)wl[p] * uv;
         else tm += uv;
         ta += s[p] * uv;
       }
@@ -943,7 +959,8 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
       const int64_t resident = cus * std::max(1, (mpw == 32 ? 8 : 16) / p.nwaves);
       p.pipe_grid = (int)std::max<int64_t>(1, std::min<int64_t>(pt, resident));
       const int cb = (dtype == PID_F64) ? 8 : 4;
-      p.lds_bytes = (size_t)2 * p.nwaves * ptp * cb + (size_t)2 * p.nwaves * mpw * 8;
+      p.lds_bytes = (size_t)2 * p.nwaves * ptp * cb + (size_t)2 * p.nwaves * mpw * 8 +
+                    (weighted ? (size_t)2 * ptp * 4 : 0);   // column sums, FP64 sums, tile weights
       // the unpipelined kernel for rows that are not aligned: at most 16
       // members per wave, at most tpw tiles per workgroup
       p.fb_mpw = (n <= 32) ? 4 : (n <= 64 ? 8 : 16);
