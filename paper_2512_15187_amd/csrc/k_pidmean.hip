@@ -1051,11 +1051,18 @@ static void launch_soft_t(const MeanPlan& p, const pid_ensemble& e, const Extrac
                            e.ld, (int)e.n, e.m, e.weights, ex, p.ntiles, sglob, part, vec ? 1 : 0);
       return;
     }
-    // single pass; 16 waves only where N needs them
-    if (p.nwaves > 8) { if (wtd) launch_soft_one<T, MODE, MPW, true, 16>(p, e, ex, vec, p.nwaves, sglob, part, st, tm);
-                        else launch_soft_one<T, MODE, MPW, false, 16>(p, e, ex, vec, p.nwaves, sglob, part, st, tm); }
-    else { if (wtd) launch_soft_one<T, MODE, MPW, true, 8>(p, e, ex, vec, p.nwaves, sglob, part, st, tm);
-           else launch_soft_one<T, MODE, MPW, false, 8>(p, e, ex, vec, p.nwaves, sglob, part, st, tm); }
+    // single pass; 16 waves only where N needs them.  The plan gives U8 and
+    // FP64 input at most 8 waves, so their 16-wave variants are not built (a
+    // larger block would fail at launch, reported by the caller's check).
+    if constexpr (sizeof(T) == 4 || sizeof(T) == 2) {
+      if (p.nwaves > 8) {
+        if (wtd) launch_soft_one<T, MODE, MPW, true, 16>(p, e, ex, vec, p.nwaves, sglob, part, st, tm);
+        else launch_soft_one<T, MODE, MPW, false, 16>(p, e, ex, vec, p.nwaves, sglob, part, st, tm);
+        return;
+      }
+    }
+    if (wtd) launch_soft_one<T, MODE, MPW, true, 8>(p, e, ex, vec, p.nwaves, sglob, part, st, tm);
+    else launch_soft_one<T, MODE, MPW, false, 8>(p, e, ex, vec, p.nwaves, sglob, part, st, tm);
   }
 }
 
