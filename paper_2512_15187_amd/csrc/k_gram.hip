@@ -33,7 +33,8 @@ namespace pidk {
 // G (N x N, row-major) and the masses.  A block owns RED_ELEMS consecutive
 // partial elements, four per thread of a group (16-byte loads, so a group
 // reads 256 contiguous bytes of each split); its 16 thread groups sum the
-// splits k = g, g+16, g+32, ... (each in ascending k), and the group sums are
+// splits k = g, g+16, g+32, ... (each in ascending k, up to eight loads in
+// flight), and the group sums are
 // added in order g = 0..15.  The order depends on nsplit only, so results are
 // deterministic.  The masses follow the packed sub-tiles as elements tot,
 // tot + 1, ..., four per thread as well.
@@ -72,6 +73,13 @@ __global__ __launch_bounds__(256) void gram_reduce(const PT* __restrict__ part,
       for (int r = 0; r < RED_EPT; ++r) s[r] += (double)v.v[r];
     };
     int k = g;
+    for (; k + 7 * RED_GROUPS < nsplit; k += 8 * RED_GROUPS) {   // eight splits in flight, added in order
+      V4 a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = ld(k + q * RED_GROUPS);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) add(a[q]);
+    }
     for (; k + 3 * RED_GROUPS < nsplit; k += 4 * RED_GROUPS) {   // four splits in flight, added in order
       const V4 a0 = ld(k), a1 = ld(k + RED_GROUPS), a2 = ld(k + 2 * RED_GROUPS), a3 = ld(k + 3 * RED_GROUPS);
       add(a0); add(a1); add(a2); add(a3);
@@ -129,9 +137,13 @@ __global__ __launch_bounds__(256) void gram_reduce(const PT* __restrict__ part,
 // Depths of member i:
 //   IN_in(i)  = S_i / (N m_i),  S_i = sum_j G_ij
 //   IN_out(i) = (sum_j G_ji / m_j) / N   (terms with m_j = 0 are 0)
-// The lanes form the terms (one correctly rounded division each) for a chunk
-// of j into LDS; one lane adds them in ascending j, which is the fixed order
-// that makes binary results bitwise reproducible.
+// With an exact integer Gram (INT8 scheme) the lanes form the IN_out terms
+// (one correctly rounded division each) for a chunk of j into LDS and one
+// lane adds them in ascending j: the fixed order that makes binary results
+// bitwise reproducible.  Otherwise every lane sums its strided j and the
+// partials meet in a fixed butterfly and wave order (deterministic, not
+// sequential).  S_i and sum_k m_k always take the parallel order: for an
+// integer Gram they are exact in any order.
 constexpr int DEP_CHUNK = 1024;
 
 // All per-member outputs after the reduction, one block of 256 threads per
@@ -140,8 +152,8 @@ constexpr int DEP_CHUNK = 1024;
 // same ensemble.  Their numerators are the Gram row sums:
 //   A_i = sum_x w u_i(x) s(x),  s = sum_j u_j   =>   A_i = sum_j G_ij = S_i,
 // so IN_in = A_i / (N m_i) is the all-pairs IN_in (the recall identity of
-// Sec. 4.1) and IN_out = A_i / sum_k m_k, with sum_k m_k formed by every block
-// in the fixed tree of pidmean_ratios.
+// Sec. 4.1) and IN_out = A_i / sum_k m_k, with sum_k m_k formed by every
+// block in the same order.
 struct FinishArgs {
   const double* G;
   const double* mass;
@@ -152,47 +164,59 @@ struct FinishArgs {
   double *mm_out, *mm_in, *mm_outo, *mm_depth;   // PID-mean outputs
 };
 
+// sum over the 64 lanes, the same butterfly on every lane
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma clang fp contract(off)
+  for (int o = 32; o >= 1; o >>= 1) v = v + __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <bool SERIAL_OUT>
 __global__ __launch_bounds__(256) void pairs_finish(FinishArgs f) {
 #pragma clang fp contract(off)
-  __shared__ double tg[DEP_CHUNK], to[DEP_CHUNK];
-  __shared__ double red[256];
+  __shared__ double tg[SERIAL_OUT ? DEP_CHUNK : 1];
+  __shared__ double red[3][4];
   const int i = blockIdx.x;
   const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
   const int n = f.n;
   const double* row = f.G + (size_t)i * n;   // G_ij = G_ji (symmetric)
   const double mi = f.mass[i];
-  if (f.P) {
-    for (int j = t; j < n; j += 256) f.P[(size_t)i * n + j] = (mi > 0.0) ? row[j] / mi : 0.0;
+  double S = 0.0, O = 0.0, md = 0.0;
+  for (int j = t; j < n; j += 256) {
+    const double g = row[j];
+    const double mj = f.mass[j];
+    if (f.P) f.P[(size_t)i * n + j] = (mi > 0.0) ? g / mi : 0.0;
+    S = S + g;
+    md = md + mj;
+    if constexpr (!SERIAL_OUT) O = O + ((mj > 0.0) ? g / mj : 0.0);
   }
-  double S = 0.0, O = 0.0;
-  for (int j0 = 0; j0 < n; j0 += DEP_CHUNK) {
-    const int cnt = min(DEP_CHUNK, n - j0);
-    for (int q = t; q < cnt; q += 256) {
-      const double g = row[j0 + q];
-      const double mj = f.mass[j0 + q];
-      tg[q] = g;
-      to[q] = (mj > 0.0) ? g / mj : 0.0;
-    }
-    __syncthreads();
-    if (t == 0) {
-      for (int q = 0; q < cnt; ++q) {
-        S = S + tg[q];
-        O = O + to[q];
+  S = wave_sum_d(S);
+  md = wave_sum_d(md);
+  if constexpr (!SERIAL_OUT) O = wave_sum_d(O);
+  if (lane == 0) { red[0][wv] = S; red[1][wv] = O; red[2][wv] = md; }
+  if constexpr (SERIAL_OUT) {
+    // (every thread passes the same number of barriers)
+    double acc = 0.0;
+    for (int j0 = 0; j0 < n; j0 += DEP_CHUNK) {
+      const int cnt = min(DEP_CHUNK, n - j0);
+      for (int q = t; q < cnt; q += 256) {
+        const double mj = f.mass[j0 + q];
+        tg[q] = (mj > 0.0) ? row[j0 + q] / mj : 0.0;
       }
-    }
-    __syncthreads();
-  }
-  if (f.mean) {
-    double md = 0.0;
-    for (int k = t; k < n; k += 256) md += f.mass[k];
-    red[t] = md;
-    __syncthreads();
-    for (int o = 128; o >= 1; o >>= 1) {
-      if (t < o) red[t] += red[t + o];
+      __syncthreads();
+      if (t == 0)
+        for (int q = 0; q < cnt; ++q) acc = acc + tg[q];
       __syncthreads();
     }
+    O = acc;
+  } else {
+    __syncthreads();
   }
   if (t != 0) return;
+  S = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  if constexpr (!SERIAL_OUT) O = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  const double tot = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
   const double ii = (mi > 0.0) ? S / ((double)n * mi) : 0.0;
   const double oo = O / (double)n;
   if (f.m_out) f.m_out[i] = mi;
@@ -200,13 +224,11 @@ __global__ __launch_bounds__(256) void pairs_finish(FinishArgs f) {
   if (f.in_out) f.in_out[i] = oo;
   if (f.depth) f.depth[i] = ii < oo ? ii : oo;
   if (f.mean) {
-    const double tot = red[0];
     const double moo = (tot > 0.0) ? S / tot : 0.0;
-    const double mii = ii;
     if (f.mm_out) f.mm_out[i] = mi;
-    if (f.mm_in) f.mm_in[i] = mii;
+    if (f.mm_in) f.mm_in[i] = ii;
     if (f.mm_outo) f.mm_outo[i] = moo;
-    if (f.mm_depth) f.mm_depth[i] = mii < moo ? mii : moo;
+    if (f.mm_depth) f.mm_depth[i] = ii < moo ? ii : moo;
   }
 }
 
@@ -402,7 +424,8 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
       f.mm_out = mean_out->mass; f.mm_in = mean_out->in_in; f.mm_outo = mean_out->in_out;
       f.mm_depth = mean_out->depth;
     }
-    hipLaunchKernelGGL(pairs_finish, (int)e.n, 256, 0, st, f);
+    if (mt == MT_I8) hipLaunchKernelGGL(pairs_finish<true>, (int)e.n, 256, 0, st, f);
+    else hipLaunchKernelGGL(pairs_finish<false>, (int)e.n, 256, 0, st, f);
   }
   return hipGetLastError();
 }
