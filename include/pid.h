@@ -249,6 +249,13 @@ pid_status pid_timing_get(const char* kernel, double* total_ms, int64_t* launche
  * that a benchmark brackets only the kernel it reports); NULL or "" times
  * every kernel again.  Takes effect for launches after the call. */
 pid_status pid_timing_select(const char* names);
+/* Bracket only every `every`-th launch of each timed kernel (launches 0,
+ * every, 2*every, ... counted per kernel name since the last enable or
+ * sample call), so that a benchmark can measure a kernel's duration inside
+ * its timed loop while paying the events' cost on a fraction of the
+ * launches; pid_timing_get() then counts the bracketed launches only.
+ * 1 (the default) brackets all.  PID_ERR_INVALID_ARG outside 1..2^20. */
+pid_status pid_timing_sample(int every);
 
 /* Diagnostics. */
 const char* pid_status_string(pid_status s);

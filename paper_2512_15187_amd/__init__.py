@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "pid_timing_enable": ([I32], I32),
         "pid_timing_get": ([ctypes.c_char_p, P(ctypes.c_double), P(I64)], I32),
         "pid_timing_select": ([ctypes.c_char_p], I32),
+        "pid_timing_sample": ([I32], I32),
         "pid_status_string": ([I32], ctypes.c_char_p),
         "pid_last_error": ([], ctypes.c_char_p),
         "pid_abi_version": ([], I32),
@@ -334,6 +335,11 @@ def pid_timing_select(names=None):
     if names is not None and not isinstance(names, str):
         names = ",".join(names)
     _check(load_library().pid_timing_select(None if names is None else names.encode()))
+
+
+def pid_timing_sample(every: int = 1):
+    """Bracket only every `every`-th launch of each timed kernel."""
+    _check(load_library().pid_timing_sample(int(every)))
 
 
 def pid_timing_get(kernel: str):

@@ -75,14 +75,20 @@ __global__ __launch_bounds__(256) void rank_kernel(RankArgs ra, int n) {
   if (i >= n) return;                       // whole wave leaves together
   const double di = d[i];
   int r = 0;
-  for (int j0 = 0; j0 < n; j0 += 64) {
-    const int j = j0 + lane;
-    bool before = false;
-    if (j < n) {
-      const double dj = d[j];
-      before = (dj > di) || (dj == di && j < i);
+  // four 64-member chunks per round: their loads are issued together
+  for (int j0 = 0; j0 < n; j0 += 256) {
+    double dj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + 64 * q + lane;
+      dj[q] = j < n ? d[j] : 0.0;
     }
-    r += __popcll(__ballot(before));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + 64 * q + lane;
+      const bool before = j < n && ((dj[q] > di) || (dj[q] == di && j < i));
+      r += __popcll(__ballot(before));
+    }
   }
   if (lane == 0) {
     if (rank) rank[i] = r;

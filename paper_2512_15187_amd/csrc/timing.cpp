@@ -1,7 +1,8 @@
 // Per-kernel timing with HIP events recorded around each library launch on
 // the stream the kernel is launched on.  Off by default; when on, every launch
-// records one event pair, and pid_timing_get() resolves the pending pairs
-// (waiting for them) and reports the accumulated time per kernel name.
+// (or every k-th launch of each kernel, pid_timing_sample) records one event
+// pair, and pid_timing_get() resolves the pending pairs (waiting for them) and
+// reports the accumulated time per kernel name.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -27,6 +28,8 @@ std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, std::pair<double, int64_t>> g_tot;
 std::set<std::string> g_sel;   // kernels to time; empty = all
+std::map<std::string, int64_t> g_seen;   // launches of each timed kernel since enabling
+int64_t g_every = 1;                     // bracket launch 0, k, 2k, ... of each kernel
 constexpr size_t kPoolEvents = 512;   // pre-created when timing is switched on
 
 hipEvent_t take_event() {
@@ -63,6 +66,7 @@ KernelTimer::KernelTimer(const char* name, hipStream_t st, bool by_launch)
   if (!g_on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_sel.empty() && g_sel.find(name) == g_sel.end()) return;
+  if (g_every > 1 && g_seen[name]++ % g_every != 0) return;
   a_ = take_event();
   b_ = take_event();
   if (!a_ || !b_) {
@@ -89,6 +93,7 @@ pid_status pid_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
   resolve_locked();
   g_tot.clear();
+  g_seen.clear();
   // events are created here, not in the launches being timed
   while (on && g_pool.size() < kPoolEvents) {
     hipEvent_t e = nullptr;
@@ -113,6 +118,14 @@ pid_status pid_timing_select(const char* names) {
       cur.push_back(*c);
     }
   }
+  return PID_OK;
+}
+
+pid_status pid_timing_sample(int every) {
+  if (every < 1 || every > (1 << 20)) return PID_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_every = every;
+  g_seen.clear();
   return PID_OK;
 }
 

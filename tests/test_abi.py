@@ -22,7 +22,8 @@ def test_exports_every_declared_symbol():
                 "pid_rank",
                 "pid_server_create", "pid_submit", "pid_poll", "pid_wait", "pid_request_times",
                 "pid_server_destroy", "pid_status_string", "pid_last_error", "pid_abi_version",
-                "pid_timing_enable", "pid_timing_get", "pid_timing_select"}
+                "pid_timing_enable", "pid_timing_get", "pid_timing_select",
+                "pid_timing_sample"}
     assert expected <= set(names), set(names)
     for n in names:
         assert hasattr(lib, n), n
@@ -91,3 +92,11 @@ def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises((RuntimeError, ValueError)):
         pid.pid_mean(torch.zeros(3, 5))
+
+
+def test_timing_sample_bounds():
+    lib = _lib()
+    assert lib.pid_timing_sample(0) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_timing_sample((1 << 20) + 1) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_timing_sample(4) == 0
+    assert lib.pid_timing_sample(1) == 0
