@@ -16,6 +16,8 @@ integers.  Each function names the passage of the paper it follows:
 * fuzzy extraction ``p = P(inside | isovalue ~ N(c, s^2))`` -- Sec. 3.5 (isovalue distribution)
 * binary reduction to the eID subset operator              -- Sec. 3.1 Eq. 1 and Sec. 3.2 Eq. binary_reduction
 * ranking: deepest first                                   -- Sec. 5.1
+* contour-boxplot bands: median, unions and intersections
+  of the binarised deepest members                         -- Sec. 1 (pipeline), Sec. 6 and 6.1
 
 Readings taken where the paper is silent or inconsistent (all listed in the
 design notes of the repository):
@@ -26,7 +28,8 @@ design notes of the repository):
 * inside side: ``side = +1`` means ``f > c`` is inside (``p = Phi((f-c)/s)``),
   ``side = -1`` is the sublevel set ``f < c`` of Sec. 3.1 Eq. 2;
 * binary threshold is strict: ``side*(f - c) > 0`` is inside;
-* ranks: rank 0 is the deepest member, ties broken by the lower index.
+* ranks: rank 0 is the deepest member, ties broken by the lower index;
+* boxplot binarisation: a point is inside a member when ``u >= threshold``.
 
 Pinned by ``tests/test_oracle_pins.py`` against exact-rational brute force,
 eID set counting, closed forms for nested chains, a hand-worked fixture, the
@@ -44,7 +47,7 @@ __all__ = [
     "extract", "mass", "incl", "gram", "inclusion_matrix", "pid", "pid_mean",
     "pid_mean_literal", "pid_linear", "rank_order", "eid_sets",
     "binary_pid", "binary_pid_mean", "pid_large", "pid_mean_large",
-    "exact_pid", "exact_pid_mean",
+    "exact_pid", "exact_pid_mean", "boxplot_bands",
 ]
 
 
@@ -339,3 +342,35 @@ def pid_mean_large(data, w=None, iso=None, chunk=1 << 18):
     in_out = A / mbar if mbar > 0 else np.zeros_like(A)
     return dict(mass=m, mbar=mbar, in_in=in_in, in_out=in_out,
                 depth=np.minimum(in_in, in_out))
+
+
+# ------------------------------------------------------- Sec. 1, Sec. 6 / 6.1
+BAND_MEDIAN, BAND_UNION_INNER, BAND_INTER_INNER, BAND_UNION_OUTER, BAND_INTER_OUTER = 1, 2, 4, 8, 16
+
+
+def boxplot_bands(U, order, k_inner, k_outer, threshold):
+    """Contour-boxplot bands of an ensemble ranked by depth.
+
+    The members are binarised (inside where ``u >= threshold``: 0.5 for soft
+    masks, 0.02 for normalised densities in the examples of Sec. 6); the
+    median is the deepest member ``order[0]``; a band of the ``k`` deepest
+    members ``order[:k]`` is bounded by the per-point union and intersection
+    of their binarised masks (Sec. 1 and Sec. 6: envelopes of the 50 % and
+    100 % groups).  ``k_inner`` and ``k_outer`` are the group sizes.  Returns
+    boolean arrays of length M and ``code``, one byte per point with the
+    bits BAND_MEDIAN, BAND_UNION_INNER, BAND_INTER_INNER, BAND_UNION_OUTER,
+    BAND_INTER_OUTER."""
+    U = _f64(U)
+    order = [int(i) for i in order]
+    B = U >= float(threshold)
+    def union(k):
+        return np.any(B[order[:k]], axis=0)
+    def inter(k):
+        return np.all(B[order[:k]], axis=0)
+    out = dict(median=B[order[0]].copy(), union_inner=union(k_inner), inter_inner=inter(k_inner),
+               union_outer=union(k_outer), inter_outer=inter(k_outer))
+    code = (out["median"] * BAND_MEDIAN + out["union_inner"] * BAND_UNION_INNER
+            + out["inter_inner"] * BAND_INTER_INNER + out["union_outer"] * BAND_UNION_OUTER
+            + out["inter_outer"] * BAND_INTER_OUTER)
+    out["code"] = code.astype(np.uint8)
+    return out

@@ -406,3 +406,57 @@ def test_binary_float_product_is_the_integer_product():
     assert (a["gram"] == b["gram"]).all()
     for key in ("in_in", "in_out", "depth", "inclusion"):
         assert (a[key] == b[key]).all()
+
+
+# ------------------------------------------------ contour-boxplot bands
+def test_boxplot_bands_handworked():
+    """Three members, six points, ranked deepest first as 2, 0, 1; inside
+    where u >= 0.5 (0.5 itself is inside).  Binarised rows:
+    b0 = 110010, b1 = 010011, b2 = 110001.  Median = b2; the two deepest
+    (2, 0): union 110011, intersection 110000; all three: union 110011,
+    intersection 010000."""
+    U = np.array([[0.9, 0.5, 0.1, 0.0, 0.6, 0.49],
+                  [0.2, 0.7, 0.3, 0.0, 0.8, 1.0],
+                  [1.0, 0.5, 0.0, 0.0, 0.4, 0.51]])
+    r = oracle.boxplot_bands(U, [2, 0, 1], 2, 3, 0.5)
+    assert r["median"].tolist() == [1, 1, 0, 0, 0, 1]
+    assert r["union_inner"].tolist() == [1, 1, 0, 0, 1, 1]
+    assert r["inter_inner"].tolist() == [1, 1, 0, 0, 0, 0]
+    assert r["union_outer"].tolist() == [1, 1, 0, 0, 1, 1]
+    assert r["inter_outer"].tolist() == [0, 1, 0, 0, 0, 0]
+    # bits: median 1, inner union 2, inner intersection 4, outer union 8, outer intersection 16
+    assert r["code"].tolist() == [15, 31, 0, 0, 10, 11]
+
+
+def test_boxplot_bands_nesting_and_special_cases():
+    rng = _rng(77)
+    n, m = 9, 400
+    U = rng.random((n, m))
+    order = rng.permutation(n)
+    r = oracle.boxplot_bands(U, order, 4, 7, 0.5)
+    # intersections shrink and unions grow with the group; the median lies between
+    assert np.all(r["inter_outer"] <= r["inter_inner"])
+    assert np.all(r["inter_inner"] <= r["median"])
+    assert np.all(r["median"] <= r["union_inner"])
+    assert np.all(r["union_inner"] <= r["union_outer"])
+    # a group of one is the median itself
+    r1 = oracle.boxplot_bands(U, order, 1, 1, 0.5)
+    for k in ("union_inner", "inter_inner", "union_outer", "inter_outer"):
+        assert np.array_equal(r1[k], r1["median"])
+    assert np.array_equal(r1["median"], U[order[0]] >= 0.5)
+    # the whole ensemble does not depend on the order
+    rn = oracle.boxplot_bands(U, rng.permutation(n), n, n, 0.5)
+    assert np.array_equal(rn["union_outer"], (U >= 0.5).any(axis=0))
+    assert np.array_equal(rn["inter_outer"], (U >= 0.5).all(axis=0))
+
+
+def test_boxplot_bands_de_morgan():
+    """On binary masks the union of the complements is the complement of the
+    intersection (and vice versa)."""
+    B = synth.random_binary(7, 300, 5).numpy().astype(np.float64)
+    order = [3, 1, 6, 0, 2, 5, 4]
+    a = oracle.boxplot_bands(B, order, 3, 7, 0.5)
+    c = oracle.boxplot_bands(1.0 - B, order, 3, 7, 0.5)
+    assert np.array_equal(c["union_inner"], ~a["inter_inner"])
+    assert np.array_equal(c["inter_outer"], ~a["union_outer"])
+    assert np.array_equal(c["median"], ~a["median"])
