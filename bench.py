@@ -323,6 +323,18 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
     out["largeN_max_depth_diff_linear_vs_gram"] = float((gl.out["depth"] - dl.out["depth"]).abs().max())
     del UL, gl, dl
 
+    # contour-boxplot bands on the headline ensemble: median, 50 % and 100 %
+    # groups of its all-pairs ranking (reads the 256 rows once, writes M bytes)
+    order = pid.pid_all_pairs(U, gemm="f16")["order"]
+    t = timed(lambda: pid.pid_bands(U, order, n // 2, n, 0.5), k, 2, torch)
+    pid.pid_timing_enable(True)          # after the warm-up (the first launch loads the kernel)
+    timed(lambda: pid.pid_bands(U, order, n // 2, n, 0.5), k, 0, torch)
+    kb, _ = kernel_ms(pid, "bands")
+    pid.pid_timing_enable(False)
+    out["bands_n256_m262144_call_us"] = t * 1e6
+    out["bands_kernel_us"] = kb * 1e3
+    out["bands_kernel_GBps"] = (n * m * 4 + m) / (kb * 1e-3) / 1e9
+
     # 2D FP64 plain PID, N=50 on 128x128
     U0, _ = synth.config0(device=dev)
     p0 = pid.PreparedCall("pairs", U0, gemm="f64")

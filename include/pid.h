@@ -184,9 +184,30 @@ pid_status pid_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const
 
 /* Fuzzy-contour extraction alone (Sec. 3.5): writes u = model(value) for the
  * N x M ensemble into `u_out` (dense N x M, row stride M) as float (out_dtype
- * PID_F32) or double (PID_F64).  Same arithmetic as the fused loaders. */
+ * PID_F32) or double (PID_F64); Phi by erfcf for float output and erfc for
+ * double output. */
 pid_status pid_extract(const pid_ensemble* ens, const pid_iso* iso, void* u_out, int out_dtype,
                        void* stream);
+
+/* Contour-boxplot bands of a ranked ensemble (the depth -> percentile ->
+ * boxplot pipeline of Sec. 1; the envelopes of Sec. 6 / 6.1).  Each member
+ * is binarised after extraction (iso, as above): a point is inside when
+ * u >= threshold (0.5 for soft masks, 0.02 for normalised densities in the
+ * paper's examples), the decision taken in FP64.  `order` (device, int32,
+ * at least k_outer entries) lists members deepest first, as pid_rank's
+ * order; the median is order[0], the inner band the k_inner deepest, the
+ * outer band the k_outer deepest (e.g. ceil(N/2) and N for the 50 % and
+ * 100 % groups), 1 <= k_inner <= k_outer <= N.  `out` (device, M bytes,
+ * owned by the caller) receives per point the bits
+ *   1 median inside, 2 union of the inner band, 4 intersection of the inner
+ *   band, 8 union of the outer band, 16 intersection of the outer band,
+ *   128 some order entry among the first k_outer was outside 0..N-1 (such an
+ *   entry is skipped, never read through).
+ * Ensemble weights are ignored.  Reads k_outer rows of M values once; one
+ * launch, asynchronous on `stream`.  PID_ERR_INVALID_ARG on NULL pointers,
+ * bad k or a non-finite threshold. */
+pid_status pid_bands(const pid_ensemble* ens, const pid_iso* iso, const int32_t* order, int64_t k_inner,
+                     int64_t k_outer, double threshold, uint8_t* out, void* stream);
 
 /* Ranks from depths (device arrays of n): rank 0 = deepest, ties by index. */
 pid_status pid_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, void* stream);
@@ -241,7 +262,7 @@ pid_status pid_server_destroy(pid_server* server);
  * the total milliseconds and launch count of one kernel: "gram" (all-pairs
  * numerators), "gram_reduce", "pairs_finish" (inclusion rows, depths and,
  * after a fused pass, the PID-mean ratios), "pidmean" (the streaming PID-mean
- * pass), "pidmean_colsum", "pidmean_finalize", "rank", "extract".  Unknown
+ * pass), "pidmean_colsum", "pidmean_finalize", "rank", "extract", "bands".  Unknown
  * names report 0. */
 pid_status pid_timing_enable(int on);
 pid_status pid_timing_get(const char* kernel, double* total_ms, int64_t* launches);

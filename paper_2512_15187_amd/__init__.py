@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
         "pid_both": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_extract": ([P(pid_ensemble), P(pid_iso), V, I32, V], I32),
         "pid_rank": ([V, I64, V, V, V], I32),
+        "pid_bands": ([P(pid_ensemble), P(pid_iso), V, I64, I64, ctypes.c_double, V, V], I32),
         "pid_server_create": ([I32, V, ctypes.c_size_t, I32, P(V)], I32),
         "pid_submit": ([V, P(pid_request), P(ctypes.c_uint64)], I32),
         "pid_poll": ([V, ctypes.c_uint64, P(I32), P(I32)], I32),
@@ -265,6 +266,26 @@ def pid_extract(U, iso, out_dtype=torch.float32, stream=None):
     odt = {torch.float32: PID_F32, torch.float64: PID_F64}[out_dtype]
     _check(lib.pid_extract(ctypes.byref(e), ctypes.byref(i), ctypes.c_void_p(out.data_ptr()), odt,
                            _stream_ptr(stream)))
+    return out
+
+
+BAND_MEDIAN, BAND_UNION_INNER, BAND_INTER_INNER, BAND_UNION_OUTER, BAND_INTER_OUTER = 1, 2, 4, 8, 16
+BAND_BAD_ORDER = 128
+
+
+def pid_bands(U, order, k_inner, k_outer, threshold=0.5, iso=None, stream=None):
+    """Contour-boxplot bands (one uint8 code per point, bits BAND_*) of the
+    ensemble U ranked by ``order`` (int32 device tensor, deepest first)."""
+    lib = load_library()
+    _require_gpu(order, "order")
+    if order.dtype != torch.int32 or order.dim() != 1 or not order.is_contiguous():
+        raise ValueError("order must be a contiguous 1-D int32 tensor")
+    if order.numel() < k_outer:
+        raise ValueError("order has fewer than k_outer entries")
+    e, i = make_ensemble(U), make_iso(iso)
+    out = torch.empty(U.shape[1], dtype=torch.uint8, device=U.device)
+    _check(lib.pid_bands(ctypes.byref(e), ctypes.byref(i), ctypes.c_void_p(order.data_ptr()), int(k_inner),
+                         int(k_outer), float(threshold), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

@@ -327,6 +327,26 @@ pid_status pid_extract(const pid_ensemble* ens, const pid_iso* iso, void* u_out,
   return PID_OK;
 }
 
+pid_status pid_bands(const pid_ensemble* ens, const pid_iso* iso, const int32_t* order, int64_t k_inner,
+                     int64_t k_outer, double threshold, uint8_t* out, void* stream) {
+  int kind = 0;
+  pid_status s = check_ensemble(ens, iso, &kind);
+  if (s != PID_OK) return s;
+  if (!order) return fail(PID_ERR_INVALID_ARG, "order is NULL");
+  if (!out) return fail(PID_ERR_INVALID_ARG, "out is NULL");
+  if (k_inner < 1 || k_inner > k_outer || k_outer > ens->n)
+    return fail(PID_ERR_INVALID_ARG, "need 1 <= k_inner <= k_outer <= n (got %lld, %lld, n = %lld)",
+                (long long)k_inner, (long long)k_outer, (long long)ens->n);
+  if (!std::isfinite(threshold)) return fail(PID_ERR_INVALID_ARG, "threshold must be finite");
+  const int eb = elem_bytes(ens->dtype);
+  if ((ens->m + 16 / eb - 1) / (16 / eb) > (int64_t)64 * 0x7fffffff)
+    return fail(PID_ERR_UNSUPPORTED, "m too large (%lld)", (long long)ens->m);
+  hipError_t err = pidk::launch_bands(*ens, kind, make_extract(iso), order, k_inner, k_outer, threshold, out,
+                                      reinterpret_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "pid_bands launch");
+  return PID_OK;
+}
+
 pid_status pid_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, void* stream) {
   if (!depth) return fail(PID_ERR_INVALID_ARG, "depth is NULL");
   if (n < 1 || n > (1 << 30)) return fail(PID_ERR_INVALID_ARG, "bad n %lld", (long long)n);

@@ -96,6 +96,9 @@ hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* o
 // Both rankings of pid_both in one launch.
 hipError_t launch_rank2(const double* d0, int32_t* rank0, int32_t* order0, const double* d1, int32_t* rank1,
                         int32_t* order1, int64_t n, hipStream_t st);
+// Contour-boxplot bands: one byte per point (pid_bands).
+hipError_t launch_bands(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, const int32_t* order,
+                        int64_t k_inner, int64_t k_outer, double threshold, uint8_t* out, hipStream_t st);
 // Writes 0 to *flag_dev when all values pass, else a nonzero code.
 hipError_t launch_validate(const pid_ensemble& e, int iso_kind, unsigned int* flag_dev, hipStream_t st);
 

@@ -23,7 +23,7 @@ def test_exports_every_declared_symbol():
                 "pid_server_create", "pid_submit", "pid_poll", "pid_wait", "pid_request_times",
                 "pid_server_destroy", "pid_status_string", "pid_last_error", "pid_abi_version",
                 "pid_timing_enable", "pid_timing_get", "pid_timing_select",
-                "pid_timing_sample"}
+                "pid_timing_sample", "pid_bands"}
     assert expected <= set(names), set(names)
     for n in names:
         assert hasattr(lib, n), n
@@ -100,3 +100,15 @@ def test_timing_sample_bounds():
     assert lib.pid_timing_sample((1 << 20) + 1) == pid.PID_ERR_INVALID_ARG
     assert lib.pid_timing_sample(4) == 0
     assert lib.pid_timing_sample(1) == 0
+
+
+def test_bands_rejects_bad_arguments():
+    """Argument checks happen before any launch (no GPU needed)."""
+    lib = _lib()
+    e = _ens()
+    order, out = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    bad = [(0, 4, 0.5), (3, 2, 0.5), (1, 5, 0.5), (1, 4, float("nan")), (1, 4, float("inf"))]
+    for ki, ko, thr in bad:
+        assert lib.pid_bands(ctypes.byref(e), None, order, ki, ko, thr, out, None) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_bands(ctypes.byref(e), None, None, 1, 4, 0.5, out, None) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_bands(ctypes.byref(e), None, order, 1, 4, 0.5, None, None) == pid.PID_ERR_INVALID_ARG
