@@ -15,7 +15,8 @@ comparator, BF16 split, fused scalar-field extraction with its binary INT8
 variant, large 3D PID-mean in GB/s, 2D FP64).
 
 ``--mode serve`` runs the serving workload instead (Poisson arrivals of mixed
-requests) and prints p50/p99 latency and requests/s.
+requests) and prints p50/p99 latency and requests/s; ``--mode sweep`` times
+PID-mean on the shapes of the paper's scalability study.
 """
 from __future__ import annotations
 
@@ -430,12 +431,42 @@ def copy_calibration(args):
                       "copy_GBps_read_plus_write": 2 * (1 << 30) / t / 1e9}), flush=True)
 
 
+def sweep(args):
+    """The shapes of the paper's scalability study (Sec. 5.2): binary 3D
+    ellipsoid ensembles (80 % normal, 20 % outliers) as U8 masks, PID-mean by
+    the exact integer path; N from 100 to 40,000 at 50^3 voxels, and 128^3 to
+    512^3 voxels at N = 50.  Inputs resident in HBM; one JSON line."""
+    import torch
+    import paper_2512_15187_amd as pid
+    import synth
+    dev = "cuda:0"
+    rows = []
+    shapes = [(n, 50) for n in (100, 1000, 10000, 20000, 40000)] + \
+             [(50, r) for r in (128, 192, 256, 352, 512)]
+    for n, res in shapes:
+        U = synth.ellipsoids_3d(n, res, synth.BASE_SEED + 7 + n + res, device=dev)
+        m = res ** 3
+        call = pid.PreparedCall("mean", U)
+        t = timed(call.run, 5, 2, torch)
+        pid.pid_timing_enable(True)
+        timed(call.run, 5, 0, torch)
+        kern = kernel_ms(pid, "pidmean")[0] + kernel_ms(pid, "pidmean_finalize")[0]
+        pid.pid_timing_enable(False)
+        rows.append({"n": n, "res": res, "call_ms": round(t * 1e3, 4), "kernels_ms": round(kern, 4),
+                     "member_voxels_per_s": n * m / t, "GBps_u8_masks": n * m / t / 1e9})
+        log(f"sweep N={n} {res}^3: {t * 1e3:.3f} ms per call ({n * m / t / 1e9:.0f} GB/s of U8 masks)")
+        del call, U
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "PID-mean on binary 3D ellipsoid ensembles (Sec. 5.2 shapes)",
+                      "unit": "ms per call", "dtype": "u8", "data": "synthetic", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["headline", "serve", "copycal"], default="headline")
+    ap.add_argument("--mode", choices=["headline", "serve", "copycal", "sweep"], default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: timed requests (after 1 s warm-up)")
@@ -448,6 +479,8 @@ def main():
         serve(args)
     elif args.mode == "copycal":
         copy_calibration(args)
+    elif args.mode == "sweep":
+        sweep(args)
     else:
         headline(args)
 

@@ -18,8 +18,9 @@ Conventions (the same for every generator):
 The shapes follow the workloads of the paper: 2D closed curves with Fourier
 perturbations turned into soft masks (the synthetic contour ensembles of the
 ranking-consistency study, Sec. 5.1), scalar-field ensembles whose fuzzy
-contours come from an isovalue distribution (Sec. 3.5), and large 3D
-perturbed-sphere ensembles (the scalability study, Sec. 5.2).
+contours come from an isovalue distribution (Sec. 3.5), large 3D
+perturbed-sphere ensembles, and binary 3D ellipsoid ensembles with 20 %
+outliers (the scalability study, Sec. 5.2).
 """
 from __future__ import annotations
 
@@ -236,6 +237,53 @@ def perturbed_spheres_3d(n, res, seed, r0=0.3, lmax=6, device="cpu",
         r = r0 * (1.0 + C @ B)                              # n x chunk
         out[:, s:s + idx.numel()] = torch.sigmoid(K * (r - rho[None, :])).to(dtype)
     return out, w_seed
+
+
+def ellipsoid_params(n, seed, frac_out=0.2):
+    """Per-member ellipsoid centre (3), semi-axes (3) and a rotation angle about
+    z for the scalability ensembles of Sec. 5.2 (80 % normal members, 20 %
+    outliers).  Normal members: centre N(1/2, 0.01^2) per axis, semi-axes
+    (0.30, 0.22, 0.15) x (1 + N(0, 0.04^2)), angle N(0, 0.05^2).  Outliers
+    (the last round(frac_out * n) members): centre N(1/2, 0.05^2), semi-axes
+    x U(0.6, 1.3) each, angle U(0.5, 1.5) rad."""
+    rng = _rng(seed)
+    n_out = int(math.floor(frac_out * n + 0.5))
+    base = np.array([0.30, 0.22, 0.15])
+    cen = rng.normal(0.5, 0.01, size=(n, 3))
+    ax = base * (1.0 + rng.normal(0.0, 0.04, size=(n, 3)))
+    ang = rng.normal(0.0, 0.05, size=n)
+    if n_out:
+        cen[n - n_out:] = rng.normal(0.5, 0.05, size=(n_out, 3))
+        ax[n - n_out:] = base * rng.uniform(0.6, 1.3, size=(n_out, 3))
+        ang[n - n_out:] = rng.uniform(0.5, 1.5, size=n_out)
+    return cen, ax, ang
+
+
+def ellipsoids_3d(n, res, seed, frac_out=0.2, device="cpu", members_per_chunk=None):
+    """Binary 3D ellipsoid masks (uint8 0/1, N x res^3) with controlled
+    contamination, the shape of the scalability study (Sec. 5.2): inside where
+    ``sum_k ((R (x - c))_k / a_k)^2 <= 1`` on cell centres, evaluated in
+    float32 a chunk of members at a time (on ``device``)."""
+    cen, ax, ang = ellipsoid_params(n, seed, frac_out)
+    M = res ** 3
+    if members_per_chunk is None:          # about 2^26 float temporaries per chunk
+        members_per_chunk = max(1, min(256, (1 << 26) // M))
+    out = torch.empty((n, M), dtype=torch.uint8, device=device)
+    t = (torch.arange(res, device=device, dtype=torch.float32) + 0.5) / res
+    z = t.view(res, 1, 1).expand(res, res, res).reshape(-1)
+    y = t.view(1, res, 1).expand(res, res, res).reshape(-1)
+    x = t.view(1, 1, res).expand(res, res, res).reshape(-1)
+    for s in range(0, n, members_per_chunk):
+        e = min(n, s + members_per_chunk)
+        c = torch.tensor(cen[s:e], dtype=torch.float32, device=device)
+        a = torch.tensor(ax[s:e], dtype=torch.float32, device=device)
+        th = torch.tensor(ang[s:e], dtype=torch.float32, device=device)[:, None]
+        dx, dy, dz = x[None] - c[:, 0:1], y[None] - c[:, 1:2], z[None] - c[:, 2:3]
+        rx = torch.cos(th) * dx - torch.sin(th) * dy
+        ry = torch.sin(th) * dx + torch.cos(th) * dy
+        q = (rx / a[:, 0:1]) ** 2 + (ry / a[:, 1:2]) ** 2 + (dz / a[:, 2:3]) ** 2
+        out[s:e] = (q <= 1.0).to(torch.uint8)
+    return out
 
 
 def volume_weights(m, seed, device="cpu", lo=0.5, hi=1.5):

@@ -136,3 +136,4 @@ def test_bands_headline_size_sampled():
     pts = np.sort(_rng(53).choice(m, size=8192, replace=False))
     ref = oracle.boxplot_bands(U[:, torch.from_numpy(pts)].to(torch.float64).numpy(), order, 128, 256, 0.5)
     assert np.array_equal(code[pts], ref["code"])
+
