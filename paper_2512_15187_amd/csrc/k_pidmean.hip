@@ -533,6 +533,16 @@ __global__ __launch_bounds__(512) void pidmean_dma_kernel(
 // ---------------------------------------------------------------------------
 // Binary path (U8 masks, or STEP on fields), exact integers.
 // part layout: [2][n][grid.x] long long (m, S).
+// 16 bytes of stored elements from an address that is 8-byte but not
+// necessarily 16-byte aligned (rows whose byte length is a multiple of 8
+// only): two 8-byte non-temporal loads.
+template <typename T>
+__device__ __forceinline__ Vec16<T> load16_nt8(const T* p) {
+  struct Two { VecB<T, 8> a, b; };
+  const Two t{loadB_nt<T, 8>(p), loadB_nt<T, 8>(p + 8 / sizeof(T))};
+  return __builtin_bit_cast(Vec16<T>, t);
+}
+
 template <typename T, int MODE, int MPW, bool SFROM, int NWMAX>
 __global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
     const T* __restrict__ U, int64_t ld, int n, int64_t m, Extract ex, int64_t ntiles,
@@ -540,7 +550,8 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
   constexpr int PPL = Vec16<T>::N;
   constexpr int TP = 64 * PPL;
   constexpr bool PACKED = (sizeof(T) == 1 && MODE == MODE_NONE);
-  const bool VEC = vec != 0;
+  const bool VEC = vec == 2;    // rows 16-byte aligned
+  const bool VEC8 = vec == 1;   // rows 8-byte aligned
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int* sbuf = reinterpret_cast<int*>(smem_raw);
   const int lane = threadIdx.x & 63;
@@ -575,6 +586,7 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
         if (i < n) {
           const T* row = U + (int64_t)i * ld;
           if (VEC && full) v = load16_nt(row + x0);
+          else if (VEC8 && full) v = load16_nt8(row + x0);
           else v = load16_guarded(row, x0, m);
         }
         const uint4 q = __builtin_bit_cast(uint4, v);
@@ -619,6 +631,7 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
       if (i < n) {
         const T* row = U + (int64_t)i * ld;
         if (VEC && full) v = load16_nt(row + x0);
+        else if (VEC8 && full) v = load16_nt8(row + x0);
         else v = load16_guarded(row, x0, m);
       }
       if constexpr (PACKED) {
@@ -702,14 +715,15 @@ __global__ __launch_bounds__(256) void colsum_part_kernel(const T* __restrict__ 
   const int lane = threadIdx.x & 63;
   const int q = threadIdx.x >> 6;
   const int64_t x0 = (int64_t)blockIdx.x * (64 * PPL) + (int64_t)lane * PPL;
-  const bool full = vec && x0 + PPL <= m;
+  const bool full = vec == 2 && x0 + PPL <= m;   // rows 16-byte aligned
+  const bool half = vec == 1 && x0 + PPL <= m;   // rows 8-byte aligned
   const int i0 = blockIdx.y * chunk, i1 = min(n, i0 + chunk);
   AT t[PPL];
 #pragma unroll
   for (int p = 0; p < PPL; ++p) t[p] = AT(0);
   auto row = [&](int i) -> Vec16<T> {
     const T* r = U + (int64_t)i * ld;
-    return full ? load16_nt(r + x0) : load16_guarded(r, x0, m);
+    return full ? load16_nt(r + x0) : (half ? load16_nt8(r + x0) : load16_guarded(r, x0, m));
   };
   auto add = [&](int i, const Vec16<T>& v) {
     if constexpr (BIN) {
@@ -1066,6 +1080,14 @@ static void launch_soft_t(const MeanPlan& p, const pid_ensemble& e, const Extrac
   }
 }
 
+// Row alignment for the loads of the binary and column-sum kernels: 2 when
+// every row is 16-byte aligned (vec), 1 when 8-byte aligned, else 0.
+template <typename T>
+static int row_align(const pid_ensemble& e, bool vec) {
+  if (vec) return 2;
+  return ((reinterpret_cast<uintptr_t>(e.data) & 7) == 0 && (e.ld * (int64_t)sizeof(T)) % 8 == 0) ? 1 : 0;
+}
+
 template <typename T, int MODE, int MPW>
 static void launch_bin_t(const MeanPlan& p, const pid_ensemble& e, const Extract& ex, bool vec,
                          const int* sglob, long long* part, hipStream_t st) {
@@ -1076,7 +1098,7 @@ static void launch_bin_t(const MeanPlan& p, const pid_ensemble& e, const Extract
 #define PB_LAUNCH(S)                                                                          \
   hipExtLaunchKernelGGL((pidmean_bin_kernel<T, MODE, MPW, S, 8>), grid, block, (uint32_t)p.lds_bytes, st,    \
                         tm.start(), tm.stop(), 0u, U,                                              \
-                     e.ld, (int)e.n, e.m, ex, p.ntiles, sglob, part, vec ? 1 : 0)
+                     e.ld, (int)e.n, e.m, ex, p.ntiles, sglob, part, row_align<T>(e, vec))
   if (p.two_pass) PB_LAUNCH(true); else PB_LAUNCH(false);
 #undef PB_LAUNCH
 }
@@ -1124,7 +1146,7 @@ static void launch_colsum_g(const pid_ensemble& e, const Extract& ex, int groups
   KernelTimer tm("pidmean_colsum", st);
   void* dst = groups > 1 ? gpart : sout;
   hipLaunchKernelGGL((colsum_part_kernel<T, MODE, BIN, SCALED>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
-                     (const CT*)coef, chunk, dst, vec ? 1 : 0);
+                     (const CT*)coef, chunk, dst, row_align<T>(e, vec));
   if (groups > 1) {
     const int cgrid = (int)std::min<int64_t>((e.m + 255) / 256, device_cu_count() * 8);
     hipLaunchKernelGGL(colsum_combine<AT>, cgrid, 256, 0, st, (const AT*)gpart, groups, e.m, (AT*)sout);
