@@ -726,7 +726,13 @@ __global__ __launch_bounds__(256) void colsum_part_kernel(const T* __restrict__ 
     return full ? load16_nt(r + x0) : (half ? load16_nt8(r + x0) : load16_guarded(r, x0, m));
   };
   auto add = [&](int i, const Vec16<T>& v) {
-    if constexpr (BIN) {
+    if constexpr (BIN && MODE == MODE_NONE && sizeof(T) == 1) {
+      // U8 masks hold 0/1: the byte itself is the count
+      const uint4 q = __builtin_bit_cast(uint4, v);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) t[p] += (int)((w[p >> 2] >> (8 * (p & 3))) & 0xffu);
+    } else if constexpr (BIN) {
 #pragma unroll
       for (int p = 0; p < PPL; ++p) t[p] += extract_bit<MODE>(v.v[p], ex);
     } else {
@@ -738,10 +744,18 @@ __global__ __launch_bounds__(256) void colsum_part_kernel(const T* __restrict__ 
       }
     }
   };
+  // vector loads of four rows in flight; element loads (unaligned rows, the
+  // ragged end of a row) one row at a time
+  auto rowv = [&](int i) -> Vec16<T> {
+    const T* r = U + (int64_t)i * ld;
+    return full ? load16_nt(r + x0) : load16_nt8(r + x0);
+  };
   int i = i0 + q;
-  for (; i + 12 < i1; i += 16) {
-    const Vec16<T> a0 = row(i), a1 = row(i + 4), a2 = row(i + 8), a3 = row(i + 12);
-    add(i, a0); add(i + 4, a1); add(i + 8, a2); add(i + 12, a3);
+  if (full || half) {
+    for (; i + 12 < i1; i += 16) {
+      const Vec16<T> a0 = rowv(i), a1 = rowv(i + 4), a2 = rowv(i + 8), a3 = rowv(i + 12);
+      add(i, a0); add(i + 4, a1); add(i + 8, a2); add(i + 12, a3);
+    }
   }
   for (; i < i1; i += 4) add(i, row(i));
 #pragma unroll
