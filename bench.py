@@ -84,15 +84,32 @@ def kernel_ms(pid, name):
     return (ms / n if n else float("nan")), n
 
 
-def cpu_baseline(U_host, budget_s=12.0):
-    """The FP64 oracle (untuned) on the same step: all-pairs PID + PID-mean."""
-    import numpy as np
-    import oracle
+def host_cpu():
+    """(os.cpu_count(), CPU model name, BLAS libraries with their thread counts)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = []
     try:
         from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        blas = [dict(api=d.get("internal_api"), threads=d.get("num_threads")) for d in threadpool_info()]
     except Exception:
-        threads = os.cpu_count() or 1
+        pass
+    return os.cpu_count(), model, blas
+
+
+def cpu_baseline(U_host, budget_s=12.0):
+    """The FP64 oracle (untuned) on the same step: all-pairs PID + PID-mean,
+    with the BLAS threads it gets by default and with one thread."""
+    import numpy as np
+    import oracle
+    ncpu, model, blas = host_cpu()
+    threads = max([b["threads"] or 1 for b in blas] or [1])
     U64 = U_host.astype(np.float64)
     n, m = U64.shape
     reps, t_tot = 0, 0.0
@@ -104,9 +121,20 @@ def cpu_baseline(U_host, budget_s=12.0):
         t_tot += time.perf_counter() - t0
         reps += 1
     t = t_tot / reps
+    t1 = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle.pid(U64)
+            oracle.pid_mean(U64)
+            t1 = time.perf_counter() - t0
+    except Exception:
+        pass
     return dict(value=n * n * m / t, unit="pair*points/s", cores=int(threads), kind="oracle",
                 sample=f"the full workload ({n} x {m} FP64), all-pairs PID + PID-mean, mean of {reps} runs",
-                seconds_per_step=t), ref, refm
+                value_1thread=(n * n * m / t1) if t1 else None, os_cpu_count=ncpu, cpu_model=model,
+                blas=blas, seconds_per_step=t), ref, refm
 
 
 def ranks_outside_ties(rank_gpu, depth_ref, tol):
@@ -180,6 +208,19 @@ def headline(args):
         step()
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t1) / args.steps
+    # the Gram kernel right after 1 GiB of writes to a scratch buffer, which
+    # evicts the 256 MB Infinity Cache (MALL): the masks come from HBM alone
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    pid.pid_timing_select("gram")
+    pid.pid_timing_enable(True)
+    for _ in range(max(5, args.steps // 4)):
+        scratch.fill_(1.0)
+        step()
+    torch.cuda.synchronize()
+    cold = kernel_ms(pid, "gram")
+    pid.pid_timing_enable(False)
+    pid.pid_timing_select(None)
+    del scratch
     log(f"step {t_step * 1e3:.3f} ms ({t_plain * 1e3:.3f} ms without kernel events); gram "
         f"{kt['gram'][0] * 1e3:.1f} us in the timed region; breakdown " +
         ", ".join(f"{k} {v[0] * 1e3:.1f} us" for k, v in breakdown.items()))
@@ -198,7 +239,9 @@ def headline(args):
     U_host = U.cpu().numpy()
 
     extra = {"kernel_us": {k: round(v[0] * 1e3, 2) for k, v in breakdown.items()},
-             "step_us_without_kernel_events": round(t_plain * 1e6, 2)}
+             "step_us_without_kernel_events": round(t_plain * 1e6, 2),
+             "gram_us_after_mall_flush": round(cold[0] * 1e3, 2),
+             "gram_frac_hbm_after_mall_flush": round(algo_bytes / (cold[0] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
@@ -217,6 +260,7 @@ def headline(args):
 
     if not args.no_extras:
         extra.update(side_measurements(pid, torch, np, synth, U, args, ref if cpu else None))
+        extra["serving"] = serving_leg(pid, torch, synth, args.serve_requests)
 
     line = {
         "metric": METRIC, "value": n * n * m / t_step, "unit": "pair*points/s", "n_gpus": 1,
@@ -350,12 +394,18 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
 
 
-def run_server(pid, torch, pool, reqs, slots, arena_bytes, t_warm):
+def run_server(pid, torch, pool, reqs, slots, arena_bytes):
     """Submit ``reqs`` at their arrival times to a server with ``slots``
-    execution slots; returns per-request latencies (ms) after the warm-up."""
+    execution slots.  Latency = completion - arrival, both on the server's
+    clock (a submitter that falls behind its arrivals counts against the
+    server).  Returns latency percentiles (ms), requests/s over the span from
+    the first arrival to the last completion, and the mean number of requests
+    on the device at once (from the per-request device timestamps)."""
     srv = pid.PidServer(arena_bytes, max_slots=slots)
+    torch.cuda.synchronize()
     tickets = []
     t0 = time.perf_counter()
+    t0s = srv.pid_server_clock()
     for r in reqs:
         now = time.perf_counter() - t0
         if r.arrival_s > now:
@@ -363,20 +413,64 @@ def run_server(pid, torch, pool, reqs, slots, arena_bytes, t_warm):
         U = pool[(r.kind, r.side)][: r.n]
         t, _ = srv.pid_submit(U, variant=r.variant)
         tickets.append((r, t))
-    lat, t_first, t_last = [], None, 0.0
+    lat, done, dev = [], [], []
     for r, t in tickets:
-        srv.pid_wait(t)
-        ts, tb, td = srv.pid_request_times(t)
-        if r.arrival_s >= t_warm:
-            lat.append((td - ts) * 1e3)
-            t_first = ts if t_first is None else min(t_first, ts)
-            t_last = max(t_last, td)
+        st = srv.pid_wait(t)
+        if st != pid.PID_OK:
+            raise RuntimeError(f"request {r} failed: {srv.last_error()}")
+        _, _, td = srv.pid_request_times(t)
+        lat.append((td - (t0s + r.arrival_s)) * 1e3)
+        done.append(td)
+        dev.append(srv.pid_request_device_times(t))
         srv.release(t)
     srv.pid_server_destroy()
     n = len(lat)
-    return dict(requests=n, p50_ms=percentile(lat, 50), p90_ms=percentile(lat, 90),
-                p99_ms=percentile(lat, 99), mean_ms=float(sum(lat) / max(1, n)),
-                req_per_s=n / max(1e-9, t_last - t_first))
+    span = max(done) - (t0s + min(r.arrival_s for r in reqs))
+    busy = sum(e - s for s, e in dev)
+    dev_span = max(e for _, e in dev) - min(s for s, _ in dev)
+    return dict(requests=n, slots=slots, p50_ms=percentile(lat, 50), p90_ms=percentile(lat, 90),
+                p99_ms=percentile(lat, 99), mean_ms=float(sum(lat) / max(1, n)), max_ms=float(max(lat)),
+                req_per_s=n / max(1e-9, span), mean_requests_on_device=busy / max(1e-9, dev_span))
+
+
+def serving_pool_for(synth, torch, reqs, dev):
+    keys = {}
+    for r in reqs:
+        keys[(r.kind, r.side)] = max(keys.get((r.kind, r.side), 0), r.n)
+    pool = {k: synth.serving_pool(k[0], k[1], n_max, device=dev) for k, n_max in sorted(keys.items())}
+    torch.cuda.synchronize()
+    return pool
+
+
+def serving_leg(pid, torch, synth, n_requests, rates=(200.0, None), slot_counts=(4, 1)):
+    """Serving workload: Poisson arrivals of mixed requests (60 % 2D, N 32..512,
+    128^2..1024^2; 40 % 3D, N 16..128, 64^3..192^3; FP16 soft masks; all-pairs
+    or PID-mean 50/50), masks resident on the device, at each rate (req/s;
+    None = every request arrives at once, the saturating case), with 4 slots
+    (continuous batching) and 1 slot (one request at a time)."""
+    dev = "cuda:0"
+    base = synth.serving_requests(n_requests)
+    log(f"serving: generating the request pool for {n_requests} requests")
+    pool = serving_pool_for(synth, torch, base, dev)
+    # every kernel variant of the mix runs once before anything is timed
+    for r in base:
+        U = pool[(r.kind, r.side)][: r.n]
+        (pid.pid_all_pairs(U, inclusion=False) if r.variant == "pairs" else pid.pid_mean(U))
+    torch.cuda.synchronize()
+    arena = 4 << 30
+    out = {}
+    for rate in rates:
+        reqs = synth.serving_requests(n_requests, rate_hz=rate) if rate else \
+            [type(r)(r.rid, 0.0, r.kind, r.n, r.side, r.variant) for r in base]
+        name = f"poisson_{int(rate)}_per_s" if rate else "burst"
+        for slots in slot_counts:
+            res = run_server(pid, torch, pool, reqs, slots, arena)
+            log(f"serving {name}, {slots} slot(s): p50 {res['p50_ms']:.3f} ms, p99 {res['p99_ms']:.3f} ms, "
+                f"{res['req_per_s']:.0f} req/s, {res['mean_requests_on_device']:.2f} requests on the device")
+            out[f"{name}_slots{slots}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items()}
+    del pool
+    torch.cuda.empty_cache()
+    return out
 
 
 def serve(args):
@@ -385,37 +479,16 @@ def serve(args):
     import paper_2512_15187_amd as pid
     import synth
 
-    dev = "cuda:0"
-    warm_s = 1.0
-    total = args.requests + int(200 * warm_s)
-    reqs = synth.serving_requests(total)
-    keys = sorted({(r.kind, r.side) for r in reqs})
-    log(f"generating the request pool: {len(keys)} (kind, side) ensembles")
-    pool = {}
-    for kind, side in keys:
-        pool[(kind, side)] = synth.serving_pool(kind, side, 512 if kind == "2d" else 128, device=dev)
-    torch.cuda.synchronize()
-    arena = 2 << 30
-    # warm the kernels once per (kind, variant)
-    for kind, side in keys[:2] + keys[-2:]:
-        pid.pid_all_pairs(pool[(kind, side)][:32])
-        pid.pid_mean(pool[(kind, side)][:32])
-    torch.cuda.synchronize()
-    log("serving with 4 slots (continuous batching)")
-    mixed = run_server(pid, torch, pool, reqs, 4, arena, warm_s)
-    log(f"  {mixed}")
-    log("serving one request at a time (1 slot)")
-    single = run_server(pid, torch, pool, reqs, 1, arena, warm_s)
-    log(f"  {single}")
+    res = serving_leg(pid, torch, synth, args.requests, rates=(200.0, 1000.0, None))
     line = {
-        "metric": METRIC, "value": mixed["p99_ms"], "unit": "ms (p99 latency)", "n_gpus": 1,
-        "steps": mixed["requests"], "warmup": int(200 * warm_s), "ms_per_step": mixed["mean_ms"],
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
-        "config": {"workload": "serving: Poisson 200 req/s; 60% 2D (N 32..512, 128^2..1024^2), 40% 3D "
-                               "(N 16..128, 64^3..192^3), FP16 soft masks, all-pairs / PID-mean 50/50",
-                   "slots": 4, "arena_bytes": arena},
-        "serving": {"continuous_batching": mixed, "one_at_a_time": single,
-                    "p99_speedup": single["p99_ms"] / mixed["p99_ms"] if mixed["p99_ms"] else None},
+        "metric": METRIC, "value": res["poisson_200_per_s_slots4"]["p99_ms"], "unit": "ms (p99 latency)",
+        "n_gpus": 1, "steps": args.requests, "warmup": 0,
+        "ms_per_step": res["poisson_200_per_s_slots4"]["mean_ms"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "serving: Poisson 200 req/s (and 1000 req/s, and all at once); 60% 2D "
+                               "(N 32..512, 128^2..1024^2), 40% 3D (N 16..128, 64^3..192^3), FP16 soft masks, "
+                               "all-pairs / PID-mean 50/50; latency from arrival", "slots": 4},
+        "serving": res,
     }
     print(json.dumps(line), flush=True)
 
@@ -469,7 +542,8 @@ def main():
     ap.add_argument("--mode", choices=["headline", "serve", "copycal", "sweep"], default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--requests", type=int, default=2000, help="serve mode: timed requests (after 1 s warm-up)")
+    ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per run")
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests per run of the serving leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PID hot path is built and timed on a single "

@@ -214,20 +214,27 @@ pid_status pid_rank(const double* depth, int64_t n, int32_t* rank, int32_t* orde
 
 /* ---------------------------------------------------------------------------
  * Serving: requests of uneven ensemble and grid size, admitted by device-memory
- * footprint and run concurrently (continuous batching).
+ * footprint and run concurrently (continuous batching).  The workload is one
+ * depth call per request (Sec. 3.2 Eq. pid with Sec. 3.4, or Sec. 4.1).
  *
  * The server owns no device memory of its own: `arena` is a caller-allocated
  * device buffer of `arena_bytes` from which each admitted request's workspace
- * is carved; a request waits in the admission queue until its workspace fits
- * and one of `max_slots` execution slots (HIP streams) is free.  The ensemble
- * and output buffers of a request stay owned by the caller and must stay valid
- * until the request completes.  Results of a request are bitwise identical to
- * the same request run alone through pid_all_pairs / pid_mean.
+ * is carved.  A request waits in the admission queue until (a) one of
+ * `max_slots` execution slots (HIP streams) is free, (b) its workspace fits in
+ * the arena (first fit) and (c) its footprint -- the bytes of its stored
+ * ensemble, weights and outputs plus its workspace -- keeps the footprint of
+ * all running requests within the budget set by pid_server_set_budget (no
+ * budget by default).  Queued requests are taken in arrival order; one that
+ * does not fit yet is passed over by later ones until it has waited 50 ms,
+ * after which nothing starts ahead of it.  The ensemble and output buffers
+ * of a request stay owned by the caller and must stay valid until the
+ * request completes.  Results of a request are bitwise identical to the same
+ * request run alone through pid_all_pairs / pid_mean / pid_pairs_depths.
  * ------------------------------------------------------------------------- */
 typedef struct pid_server pid_server;
 
 typedef struct {
-  int32_t variant;   /* 0 = all-pairs, 1 = PID-mean */
+  int32_t variant;   /* 0 = all-pairs, 1 = PID-mean, 3 = all-pairs depths without the matrix */
   int32_t gemm;      /* pid_gemm (all-pairs only)   */
   pid_ensemble ens;
   pid_iso iso;
@@ -242,15 +249,35 @@ typedef struct {
 
 pid_status pid_server_create(int device, void* arena, size_t arena_bytes, int max_slots,
                              pid_server** server);
-/* Non-blocking: validates the request, queues it and returns a ticket. */
+/* Footprint budget in bytes (0 = none).  A request whose footprint alone
+ * exceeds it is refused by pid_submit with PID_ERR_OVER_BUDGET. */
+pid_status pid_server_set_budget(pid_server* server, size_t footprint_bytes);
+/* Non-blocking: validates the request, queues it and returns a ticket.
+ * PID_ERR_OVER_BUDGET when its workspace exceeds the arena or its footprint
+ * the budget; PID_ERR_CANCELLED once the server is stopping. */
 pid_status pid_submit(pid_server* server, const pid_request* req, uint64_t* ticket);
-/* done = 1 once the request finished; result = its status (PID_OK or an error). */
+/* done = 1 once the request finished; result = its status (PID_OK or an
+ * error).  After a failed request, pid_last_error() of the calling thread
+ * holds the request's error text. */
 pid_status pid_poll(pid_server* server, uint64_t ticket, int* done, pid_status* result);
-/* Blocks until the request finished. */
+/* Blocks until the request finished; result and error text as pid_poll. */
 pid_status pid_wait(pid_server* server, uint64_t ticket, pid_status* result);
-/* Times in seconds on the server's clock: submission, start of its launch, completion. */
+/* Seconds on the server's clock (pid_server_clock): submission, admission
+ * (start of its launch) and the moment the scheduler saw it complete. */
 pid_status pid_request_times(pid_server* server, uint64_t ticket, double* t_submit,
                              double* t_start, double* t_done);
+/* Start and end of the request's work on the device, in milliseconds after
+ * the server's creation, from timing events recorded on its slot stream
+ * before its first and after its last kernel.  PID_ERR_INVALID_ARG unless the
+ * request completed with PID_OK. */
+pid_status pid_request_device_times(pid_server* server, uint64_t ticket, double* start_ms,
+                                    double* end_ms);
+/* The server's clock: seconds since creation (a monotonic clock). */
+pid_status pid_server_clock(pid_server* server, double* now_s);
+/* Forget a finished request (its ticket becomes unknown).  A server keeps
+ * every ticket's record until it is released or the server is destroyed.
+ * PID_ERR_INVALID_ARG for unknown or unfinished tickets. */
+pid_status pid_release(pid_server* server, uint64_t ticket);
 /* Stops admitting, lets running requests finish, cancels queued ones
  * (PID_ERR_CANCELLED), joins the scheduler thread and frees host resources. */
 pid_status pid_server_destroy(pid_server* server);
@@ -281,7 +308,7 @@ pid_status pid_timing_sample(int every);
 /* Diagnostics. */
 const char* pid_status_string(pid_status s);
 const char* pid_last_error(void);   /* thread-local text of the last failed call */
-int pid_abi_version(void);          /* 2 */
+int pid_abi_version(void);          /* 3 */
 
 #ifdef __cplusplus
 }

@@ -95,6 +95,10 @@ def load_library(path: str = LIB_PATH):
         "pid_wait": ([V, ctypes.c_uint64, P(I32)], I32),
         "pid_request_times": ([V, ctypes.c_uint64, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double)], I32),
         "pid_server_destroy": ([V], I32),
+        "pid_server_set_budget": ([V, ctypes.c_size_t], I32),
+        "pid_server_clock": ([V, P(ctypes.c_double)], I32),
+        "pid_request_device_times": ([V, ctypes.c_uint64, P(ctypes.c_double), P(ctypes.c_double)], I32),
+        "pid_release": ([V, ctypes.c_uint64], I32),
         "pid_timing_enable": ([I32], I32),
         "pid_timing_get": ([ctypes.c_char_p, P(ctypes.c_double), P(I64)], I32),
         "pid_timing_select": ([ctypes.c_char_p], I32),
@@ -370,11 +374,14 @@ def pid_timing_get(kernel: str):
     return ms.value, n.value
 
 
+_VARIANT = {"pairs": 0, "mean": 1, "depths": 3}
+
+
 class PidServer:
     """Continuous-batching server over ``pid_server_*``.  The arena is a
     device buffer owned by this object."""
 
-    def __init__(self, arena_bytes: int, max_slots: int = 4, device: int = 0):
+    def __init__(self, arena_bytes: int, max_slots: int = 4, device: int = 0, budget: int = 0):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the PID server needs a GPU")
@@ -384,17 +391,31 @@ class PidServer:
                                      int(max_slots), ctypes.byref(h)))
         self.h = h
         self._keep = {}
+        if budget:
+            self.pid_server_set_budget(budget)
 
-    def pid_submit(self, U, variant="pairs", weights=None, iso=None, gemm="auto", inclusion=False):
-        """Queue a request; returns (ticket, outputs dict filled on completion)."""
+    def pid_server_set_budget(self, footprint_bytes: int):
+        """Footprint budget in bytes (0 = none)."""
+        _check(load_library().pid_server_set_budget(self.h, int(footprint_bytes)))
+
+    def pid_server_clock(self) -> float:
+        """Seconds on the server's clock."""
+        t = ctypes.c_double()
+        _check(load_library().pid_server_clock(self.h, ctypes.byref(t)))
+        return t.value
+
+    def pid_submit(self, U, variant="pairs", weights=None, iso=None, gemm="auto", inclusion=False,
+                   validate=False):
+        """Queue a request (variant "pairs", "mean" or "depths"); returns
+        (ticket, outputs dict filled on completion)."""
         lib = load_library()
-        e, i = make_ensemble(U, weights), make_iso(iso)
+        e, i = make_ensemble(U, weights, validate), make_iso(iso)
         d, o = _outputs(U.shape[0], U.device, inclusion and variant == "pairs")
         # the server's streams wait for the work queued so far on the current
         # stream (the inputs and the output allocations)
         ev = torch.cuda.Event()
         ev.record(torch.cuda.current_stream(U.device))
-        req = pid_request(0 if variant == "pairs" else 1, GEMM[gemm], e, i, o, ctypes.c_void_p(ev.cuda_event))
+        req = pid_request(_VARIANT[variant], GEMM[gemm], e, i, o, ctypes.c_void_p(ev.cuda_event))
         t = ctypes.c_uint64(0)
         _check(lib.pid_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = (U, weights, d, ev)
@@ -410,12 +431,25 @@ class PidServer:
         _check(load_library().pid_wait(self.h, ticket, ctypes.byref(res)))
         return res.value
 
+    def last_error(self) -> str:
+        """Error text of the last failed request waited for or polled on
+        this thread."""
+        return load_library().pid_last_error().decode(errors="replace")
+
     def pid_request_times(self, ticket):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(load_library().pid_request_times(self.h, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
+    def pid_request_device_times(self, ticket):
+        """(start, end) of the request on the device, ms after server creation."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(load_library().pid_request_device_times(self.h, ticket, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def release(self, ticket):
+        """Forget a finished request (server record and the tensors kept for it)."""
+        _check(load_library().pid_release(self.h, ticket))
         self._keep.pop(ticket, None)
 
     def pid_server_destroy(self):

@@ -178,9 +178,15 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
     if (!pidk::pairs_supported(ens->dtype, kind, scheme))
       return fail(PID_ERR_UNSUPPORTED, "scheme %d is not built for dtype %d with iso kind %d", gemm, ens->dtype, kind);
     pidk::PairsPlan p = pidk::pairs_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr, scheme);
+    if (p.unsupported)
+      return fail(PID_ERR_UNSUPPORTED, "all-pairs of n = %lld, m = %lld is beyond this library's limits "
+                  "(n <= 32768; pid_pairs_depths and pid_mean take larger ensembles)",
+                  (long long)ens->n, (long long)ens->m);
     kb = pidk::pairs_workspace(p, ens->n);
   } else if (variant == 1) {
     pidk::MeanPlan p = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
+    if (p.unsupported)
+      return fail(PID_ERR_UNSUPPORTED, "n = %lld is beyond the PID-mean launch limits", (long long)ens->n);
     kb = pidk::mean_workspace(p, ens->n, ens->m);
   } else if (variant == 2) {
     size_t kp = 0;
@@ -188,6 +194,9 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
     if (s != PID_OK) return s;
     kb = kp;
   } else if (variant == 3) {
+    if (pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr).unsupported ||
+        pidk::rows_plan(ens->n, ens->m, ens->dtype).unsupported)
+      return fail(PID_ERR_UNSUPPORTED, "n = %lld is beyond the PID-mean launch limits", (long long)ens->n);
     kb = pidk::pairs_linear_workspace(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
   } else {
     return fail(PID_ERR_INVALID_ARG,
@@ -373,7 +382,7 @@ const char* pid_status_string(pid_status s) {
 
 const char* pid_last_error(void) { return g_last_error.c_str(); }
 
-int pid_abi_version(void) { return 2; }
+int pid_abi_version(void) { return 3; }
 
 }  // extern "C"
 

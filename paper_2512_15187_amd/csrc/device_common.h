@@ -8,6 +8,8 @@
 
 #include <type_traits>
 
+#include "pid_internal.h"
+
 namespace pidk {
 
 typedef _Float16 f16;
@@ -21,8 +23,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Stored bf16 is handled as raw 16-bit patterns.
 struct bf16_t { uint16_t bits; };
-
-enum Mode { MODE_NONE = 0, MODE_GAUSS = 1, MODE_STEP = 2 };
 
 // Parameters of the isovalue model, prepared on the host.
 //   GAUSS: u = 0.5 * erfc((f - c) * a) with a = -side / (sigma * sqrt(2)),

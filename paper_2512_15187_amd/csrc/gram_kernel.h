@@ -12,9 +12,6 @@
 
 namespace pidk {
 
-// MFMA input flavours
-enum MType { MT_F16 = 0, MT_BF16 = 1, MT_BF16X3 = 2, MT_I8 = 3, MT_F32 = 4, MT_F64 = 5 };
-
 template <int MT> struct MTraits;
 template <> struct MTraits<MT_F16>   { using E = f16;      static constexpr int EB = 2; static constexpr int KK = 16; static constexpr int PLANES = 1; };
 template <> struct MTraits<MT_BF16>  { using E = uint16_t; static constexpr int EB = 2; static constexpr int KK = 16; static constexpr int PLANES = 1; };
@@ -944,61 +941,34 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
   if constexpr (!((MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) && sizeof(Tin) <= 4 && sizeof(Tin) >= 2)) {
     return false;
   } else {
-    static const bool enabled = [] {
-      const char* v = getenv("PID_TUNE_GRAM_DMA");
-      return v == nullptr || atoi(v) != 0;
-    }();
     constexpr int eb = sizeof(Tin);
-    if (!enabled || !ga0.vec || (ga0.m * eb) % 16 != 0) return false;
+    if (!ga0.vec || (ga0.m * eb) % 16 != 0) return false;
     if (((int64_t)31 * ga0.ld + ga0.m) * eb >= (INT64_C(1) << 31) || ga0.m * 4 >= (INT64_C(1) << 31)) return false;
-    static const int ntiles = [] {
-      const char* v = getenv("PID_TUNE_GRAM_TILES");
-      return (v != nullptr && atoi(v) == 2) ? 2 : 1;
-    }();
     GramArgs ga = ga0;
     ga.slabs = (ga0.m * eb + 127) / 128;   // 128-byte slabs of every row
     const bool w = ga.w != nullptr;
-    static const int nwaves = [] {
-      const char* v = getenv("PID_TUNE_GRAM_WAVES");
-      return (v != nullptr && atoi(v) == 8) ? 8 : 16;
-    }();
     auto go = [&](auto k, size_t lds, int threads) {
       static const bool attr = (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                     163840) == hipSuccess);
       (void)attr;
       hipExtLaunchKernelGGL(k, dim3(grid), dim3(threads), (uint32_t)lds, st, tm.start(), tm.stop(), 0u, ga);
     };
-    // sub-tiles per wave: at most 36 over 8 waves (5) or over 16 waves (3)
-    auto pick = [&](auto ntc) {
-      constexpr int NT = decltype(ntc)::value;
-      constexpr int NB = gram_dma_nb<Tin, MT, NT>();
-      static_assert(NB >= 2, "LDS ring");
-      // eight row blocks in one diagonal super-tile: grouped sub-tiles
-      const bool grp = nwaves == 16 && ga.nsuper == 1 && ga.nbt == 8;
-      const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w);
-      if (nwaves == 16) {
-        if constexpr (NT == 1) {
-          if (grp) {
-            if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true>, lds, 1024);
-            else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true>, lds, 1024);
-            return;
-          }
-        }
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false>, lds, 1024);
-        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false>, lds, 1024);
-      } else if (maxt > 2) {
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 5, true, NB, NT, 8, false>, lds, 512);
-        else go(gram_dma_kernel<Tin, MT, MODE, 5, false, NB, NT, 8, false>, lds, 512);
-      } else {
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 2, true, NB, NT, 8, false>, lds, 512);
-        else go(gram_dma_kernel<Tin, MT, MODE, 2, false, NB, NT, 8, false>, lds, 512);
-      }
-    };
-    // one tile by default (faster with 16 waves); two where asked for and the
-    // ring still holds three slots
-    constexpr bool two_ok = gram_dma_nb<Tin, MT, 2>() >= 3;
-    if (ntiles == 1 || !two_ok) pick(std::integral_constant<int, 1>());
-    else if constexpr (two_ok) pick(std::integral_constant<int, 2>());
+    // 16 waves, one conversion tile, a ring of NB slabs; sub-tiles per wave:
+    // at most 36 over 16 waves (3)
+    constexpr int NT = 1;
+    constexpr int NB = gram_dma_nb<Tin, MT, NT>();
+    static_assert(NB >= 2, "LDS ring");
+    // eight row blocks in one diagonal super-tile: grouped sub-tiles
+    const bool grp = ga.nsuper == 1 && ga.nbt == 8;
+    const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w);
+    (void)maxt;
+    if (grp) {
+      if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true>, lds, 1024);
+      else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true>, lds, 1024);
+    } else {
+      if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false>, lds, 1024);
+      else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false>, lds, 1024);
+    }
     return true;
   }
 }
@@ -1043,6 +1013,4 @@ bool gram_dispatch_f16(int mt, int mode, const GramArgs& ga, int maxt, int rows,
 bool gram_dispatch_bf16(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
 bool gram_dispatch_f64(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
 bool gram_dispatch_u8(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
-bool gram_supported(int dtype, int mt, int mode);
-
 }  // namespace pidk

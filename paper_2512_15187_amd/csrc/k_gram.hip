@@ -235,128 +235,6 @@ __global__ __launch_bounds__(256) void pairs_finish(FinishArgs f) {
 // ---------------------------------------------------------------------------
 // Host side.
 
-static int elem_bytes_g(int dtype) {
-  switch (dtype) {
-    case PID_F64: return 8;
-    case PID_F32: return 4;
-    case PID_F16: case PID_BF16: return 2;
-    default: return 1;
-  }
-}
-
-static int mtype_of(int scheme) {
-  switch (scheme) {
-    case SCH_F16: return MT_F16;
-    case SCH_BF16: return MT_BF16;
-    case SCH_BF16_SPLIT: return MT_BF16X3;
-    case SCH_I8: return MT_I8;
-    case SCH_F32: return MT_F32;
-    default: return MT_F64;
-  }
-}
-
-static int mt_bytes(int mt) {
-  switch (mt) {
-    case MT_F16: case MT_BF16: case MT_BF16X3: return 2;
-    case MT_I8: return 1;
-    case MT_F32: return 4;
-    default: return 8;
-  }
-}
-
-// chunks (16 B of input) per row per slab
-static int cpr_of(int eb_in, int mt) {
-  // slab rows of at most 256 bytes in LDS per plane, and of 256 bytes of input
-  int cpr = 16;
-  const int epc = 16 / eb_in;
-  while (cpr > 1 && cpr * epc * mt_bytes(mt) > 256) cpr >>= 1;
-  return cpr;
-}
-
-// (input dtype, MFMA type, extraction mode) combinations that are built.
-bool gram_supported(int dtype, int mt, int mode) {
-  switch (dtype) {
-    case PID_F32:
-      if (mt == MT_I8) return mode == MODE_STEP;
-      if (mt == MT_F16 || mt == MT_F32) return true;
-      return mode != MODE_STEP;                       // BF16, BF16x3, F64
-    case PID_F16:
-      if (mt == MT_I8) return mode == MODE_STEP;
-      if (mt == MT_F16) return true;
-      if (mt == MT_F32) return mode != MODE_STEP;
-      if (mt == MT_F64) return mode == MODE_NONE;
-      return false;
-    case PID_BF16:
-      return (mt == MT_BF16 || mt == MT_F32) && mode == MODE_NONE;
-    case PID_F64:
-      if (mt == MT_F64) return true;
-      return (mt == MT_F32 || mt == MT_F16) && mode == MODE_NONE;
-    case PID_U8:
-      if (mt == MT_I8) return mode == MODE_NONE || mode == MODE_STEP;
-      return (mt == MT_F16 || mt == MT_F32) && mode == MODE_NONE;
-    default:
-      return false;
-  }
-}
-
-bool pairs_supported(int dtype, int iso_kind, int scheme) {
-  const int mode = iso_kind == PID_ISO_GAUSSIAN ? MODE_GAUSS : (iso_kind == PID_ISO_STEP ? MODE_STEP : MODE_NONE);
-  return gram_supported(dtype, mtype_of(scheme), mode);
-}
-
-PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted, int scheme) {
-  PairsPlan p{};
-  p.scheme = scheme;
-  const int mt = mtype_of(scheme);
-  const int eb = elem_bytes_g(dtype);
-  p.nbt = (int)((n + 31) / 32);
-  // one diagonal super-tile of up to 8 row blocks when N <= 256, else
-  // super-blocks of 4 row blocks (128 rows) and all their pairs I <= J
-  static const int tune_sb = [] {
-    const char* v = getenv("PID_TUNE_GRAM_SB");   // 4: 128-row super-blocks also for N <= 256
-    return v ? atoi(v) : 0;
-  }();
-  p.sb = (p.nbt <= 8 && !(tune_sb == 4 && p.nbt > 4)) ? p.nbt : 4;
-  p.nsuper = (p.nbt + p.sb - 1) / p.sb;
-  p.ntiles_super = p.nsuper * (p.nsuper + 1) / 2;
-  p.np = p.nbt * (p.nbt + 1) / 2;
-  const int tmax = (p.nsuper > 1) ? p.sb * p.sb : p.sb * (p.sb + 1) / 2;
-  p.maxt = ((tmax + 7) / 8 <= 2) ? 2 : 5;
-  const int cpr = cpr_of(eb, mt);
-  p.ks = cpr * (16 / eb);
-  p.slabs = (m + p.ks - 1) / p.ks;
-  // splits: about one workgroup of 8 waves per CU, at least 2 slabs per split
-  // and at most 16384 points of FP32 accumulation per split.
-  const int cus = device_cu_count();
-  int64_t want = std::max<int64_t>(1, (int64_t)cus / p.ntiles_super);
-  want = std::min<int64_t>(want, std::max<int64_t>(1, p.slabs / 2));
-  const int64_t min_splits = (m + 16383) / 16384;
-  if (mt != MT_I8 && mt != MT_F64) want = std::max(want, min_splits);
-  p.nsplit = (int)(((want + 7) / 8) * 8);
-  static const int tune_splits = [] {
-    const char* v = getenv("PID_TUNE_GRAM_SPLITS");   // a multiple of 8
-    return v ? atoi(v) : 0;
-  }();
-  if (tune_splits > 0 && tune_splits % 8 == 0) p.nsplit = tune_splits;
-  p.slabs_per_split = (p.slabs + p.nsplit - 1) / p.nsplit;
-  const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;
-  const int rowb = p.ks * mt_bytes(mt) + 16;
-  const int planes = (mt == MT_BF16X3) ? 2 : 1;
-  p.lds_bytes = (size_t)2 * planes * rows * rowb + (size_t)rows * 8;   // two slab buffers + row masses
-  p.part_elem = (mt == MT_F64) ? 8 : 4;
-  (void)iso_kind; (void)weighted;
-  return p;
-}
-
-size_t pairs_workspace(const PairsPlan& p, int64_t n) {
-  Carve c(nullptr);
-  c.take<char>((size_t)p.nsplit * p.np * 1024 * p.part_elem);
-  c.take<double>((size_t)p.nsplit * n);   // partial masses
-  c.take<double>((size_t)n * n);          // G
-  c.take<double>((size_t)n);              // masses
-  return c.off + 256;
-}
-
 hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,
                             const ExtractHost& exh, const pid_out& out, void* ws, hipStream_t st,
                             const pid_out* mean_out) {
@@ -379,11 +257,11 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   ga.part_mass = c.take<double>((size_t)p.nsplit * e.n);
   double* G = c.take<double>((size_t)e.n * e.n);
   double* mass = c.take<double>((size_t)e.n);
-  const int eb = elem_bytes_g(e.dtype);
+  const int eb = elem_bytes_of(e.dtype);
   ga.vec = (((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
             (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0)) ? 1 : 0;
   const int mt = mtype_of(p.scheme);
-  const int mode = iso_kind == PID_ISO_GAUSSIAN ? MODE_GAUSS : (iso_kind == PID_ISO_STEP ? MODE_STEP : MODE_NONE);
+  const int mode = iso_mode(iso_kind);
   const int grid = p.nsplit * p.ntiles_super;
   const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;   // most rows a workgroup loads
   bool ok = false;

@@ -892,152 +892,6 @@ __global__ __launch_bounds__(256) void pairs_linear_ratios(const double* __restr
 // ---------------------------------------------------------------------------
 // Host side: plan, workspace and launch.
 
-static int elem_bytes(int dtype) {
-  switch (dtype) {
-    case PID_F64: return 8;
-    case PID_F32: return 4;
-    case PID_F16: case PID_BF16: return 2;
-    default: return 1;
-  }
-}
-
-static bool is_binary(int dtype, int iso_kind, bool weighted) {
-  if (weighted) return false;
-  return iso_kind == PID_ISO_STEP || (dtype == PID_U8 && iso_kind == PID_ISO_NONE);
-}
-
-// Member groups of a column-sum pass: enough blocks of 4 waves to fill the
-// GPU (8 per CU), at least 16 members per group, at most 64 groups.
-static int colsum_groups(int64_t n, int64_t m, int eb) {
-  const int64_t bx = (m + 64 * (16 / eb) - 1) / (64 * (16 / eb));
-  int64_t g = ((int64_t)device_cu_count() * 8 + bx - 1) / bx;
-  g = std::min<int64_t>(g, std::max<int64_t>(1, (n + 15) / 16));
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 64));
-}
-
-
-// Optional tuning overrides, read once: PID_TUNE_MEAN_MPW (members per wave:
-// 4, 8 or 16) and PID_TUNE_MEAN_TPW (tiles per workgroup, 1..64).  They
-// change the launch geometry only, never what is computed.
-static int env_int(const char* name, int dflt) {
-  const char* v = getenv(name);
-  return v ? atoi(v) : dflt;
-}
-
-MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted) {
-  static const int tune_mpw = env_int("PID_TUNE_MEAN_MPW", 0);
-  static const int tune_tpw = env_int("PID_TUNE_MEAN_TPW", 16);
-  static const int tune_pipe = env_int("PID_TUNE_MEAN_PIPE", 1);
-  MeanPlan p{};
-  p.binary = is_binary(dtype, iso_kind, weighted) ? 1 : 0;
-  const int eb = elem_bytes(dtype);
-  const int ppl = 16 / eb;
-  const int tp = 64 * ppl;
-  const int64_t cus = device_cu_count();
-  const int64_t tpw = std::min(64, std::max(1, tune_tpw));
-  p.ntiles = (m + tp - 1) / tp;
-
-  // LDS-staged single pass (soft masks, 128 < N <= 256, no straddling
-  // 16-byte chunk at the end of a row): waves of 32 rows, a ring of four
-  // tile slots.
-  static const int tune_dma = env_int("PID_TUNE_MEAN_DMA", 1);
-  // (For N <= 128 the tiles of eight-row waves are too small per barrier;
-  // the register pipeline below is faster there.)
-  if (tune_dma && !p.binary && iso_kind == PID_ISO_NONE && dtype != PID_U8 && n > 128 && n <= 256 &&
-      (m * eb) % 16 == 0) {
-    const int rpw = 32;
-    const int nw = (int)((n + rpw - 1) / rpw);
-    const int tpp = 128 / eb;
-    const int cb = (dtype == PID_F64) ? 8 : 4;
-    const size_t lds = (size_t)4 * nw * rpw * 128 + (weighted ? (size_t)4 * nw * 256 : 0) +
-                       (size_t)2 * nw * tpp * cb + (size_t)nw * rpw * 16;
-    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(163840 / (int64_t)lds, 32 / nw));
-    const int64_t tiles = (m + tpp - 1) / tpp;
-    p.dma_rpw = rpw;
-    p.dma_nwaves = nw;
-    p.dma_lds = lds;
-    p.dma_grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cus * per_cu));
-  }
-
-  // Pipelined single pass (soft input, N <= 256; FP64 N <= 128).  Each tile
-  // buffer holds MPW members x LB bytes per lane: 4 members x 16 B and
-  // 8 members x 8 B (up to 16 waves, 128 registers per lane), 32 members x
-  // 4 B (8 waves, 256 registers per lane), so that two buffers, the sums
-  // and the addressing fit without spills.  It needs one full tile; rows
-  // that are not aligned take the kernel below.
-  const bool soft = !p.binary && dtype != PID_U8 &&
-                    (iso_kind == PID_ISO_NONE || (iso_kind == PID_ISO_GAUSSIAN && eb != 2));
-  if (soft && tune_pipe) {
-    int mpw = 0;
-    if (n <= 32) mpw = 4;
-    else if (n <= 128) mpw = 8;
-    else if (n <= 256 && eb <= 4) mpw = 32;
-    const int lb = (mpw == 4) ? 16 : (mpw == 8 ? 8 : 4);
-    const int ptp = (mpw && lb >= eb) ? 64 * (lb / eb) : 0;
-    if (ptp == 0) mpw = 0;
-    if (mpw && m >= ptp) {
-      p.mpw = mpw;
-      p.nwaves = (int)((n + mpw - 1) / mpw);
-      p.two_pass = 0;
-      p.groups = 1;
-      p.pipe_lb = lb;
-      const int64_t pt = (m + ptp - 1) / ptp;
-      // the workgroups that fit at once (16 waves per CU, 8 with 32 members
-      // per wave), each streaming its share of the tiles
-      const int64_t resident = cus * std::max(1, (mpw == 32 ? 8 : 16) / p.nwaves);
-      p.pipe_grid = (int)std::max<int64_t>(1, std::min<int64_t>(pt, resident));
-      const int cb = (dtype == PID_F64) ? 8 : 4;
-      p.lds_bytes = (size_t)2 * p.nwaves * ptp * cb + (size_t)2 * p.nwaves * mpw * 8 +
-                    (weighted ? (size_t)2 * ptp * 4 : 0);   // column sums, FP64 sums, tile weights
-      // the unpipelined kernel for rows that are not aligned: at most 16
-      // members per wave, at most tpw tiles per workgroup
-      p.fb_mpw = (n <= 32) ? 4 : (n <= 64 ? 8 : 16);
-      p.fb_nwaves = (int)((n + p.fb_mpw - 1) / p.fb_mpw);
-      p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, std::max<int64_t>((p.ntiles + tpw - 1) / tpw, cus * 2)));
-      return p;
-    }
-  }
-
-  // members per wave: the smallest slice that covers N with at most 8 waves;
-  // FP32 soft input may use 16 waves of 16 members (N <= 256) within the
-  // 128 registers a 1024-thread workgroup allows; beyond: two passes.
-  int mpw = 4;
-  if (n > 32) mpw = 8;
-  if (n > 64) mpw = 16;
-  if (tune_mpw == 4 || tune_mpw == 8 || tune_mpw == 16) mpw = tune_mpw;
-  int nw = (int)((n + mpw - 1) / mpw);
-  const int max_waves = (eb == 4 && !p.binary) ? 16 : 8;
-  p.two_pass = 0;
-  p.groups = 1;
-  if (nw > max_waves) {
-    p.two_pass = 1;
-    nw = 8;
-    p.groups = (int)((n + (int64_t)nw * mpw - 1) / ((int64_t)nw * mpw));
-    p.colsum_groups = colsum_groups(n, m, eb);
-  }
-  p.mpw = mpw;
-  p.nwaves = nw;
-  // at most tpw tiles per workgroup (short FP32 / INT32 lane sums), and at
-  // least two workgroups per CU when there are enough tiles
-  int64_t g = std::max<int64_t>((p.ntiles + tpw - 1) / tpw, cus * 2);
-  if (p.two_pass) g = std::max<int64_t>((p.ntiles + tpw - 1) / tpw, std::max<int64_t>(1, cus * 2 / p.groups));
-  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, g));
-  const int cb = p.binary ? 4 : (dtype == PID_F64 ? 8 : 4);
-  p.lds_bytes = p.two_pass ? 0 : (size_t)2 * nw * tp * cb;
-  return p;
-}
-
-size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m) {
-  Carve c(nullptr);
-  c.take<double>((size_t)std::max(std::max(p.grid, p.pipe_grid), p.dma_grid) * 2 * n);   // partials
-  c.take<double>((size_t)2 * n);            // reduced A and m
-  if (p.two_pass) {
-    c.take<double>((size_t)m);              // column sums
-    c.take<double>((size_t)m * (size_t)p.colsum_groups);   // their member-group partials
-  }
-  return c.off + 256;
-}
-
 template <typename T, int MODE, int MPW, bool W, int NWMAX>
 static void launch_soft_one(const MeanPlan& p, const pid_ensemble& e, const Extract& ex, bool vec,
                             int nwaves, const void* sglob, double* part, hipStream_t st, const KernelTimer& tm) {
@@ -1229,7 +1083,7 @@ hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_
   void* red = c.take<double>((size_t)2 * e.n);
   void* sbuf = plan.two_pass ? (void*)c.take<double>((size_t)e.m) : nullptr;
   void* gpart = plan.two_pass ? (void*)c.take<double>((size_t)e.m * (size_t)plan.colsum_groups) : nullptr;
-  const int eb = elem_bytes(e.dtype);
+  const int eb = elem_bytes_of(e.dtype);
   const bool vec = ((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
                    (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0);
   // the pipelined kernel needs aligned rows and buffer offsets (one wave's
@@ -1283,37 +1137,6 @@ hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_
 // All-pairs depths without the inclusion matrix: the PID-mean pass (masses,
 // IN_in), then t = sum_j u_j / m_j into memory, then B_i = sum_x w u_i t with
 // the two-pass row kernel (soft arithmetic, also for binary input).
-static MeanPlan rows_plan(int64_t n, int64_t m, int dtype) {
-  // the two-pass configuration of mean_plan, soft arithmetic
-  MeanPlan p{};
-  const int eb = elem_bytes(dtype);
-  const int64_t cus = device_cu_count();
-  p.ntiles = (m + 64 * (16 / eb) - 1) / (64 * (16 / eb));
-  p.mpw = (n <= 32) ? 4 : (n <= 64 ? 8 : 16);
-  p.nwaves = (int)std::min<int64_t>(8, (n + p.mpw - 1) / p.mpw);
-  p.two_pass = 1;
-  p.groups = (int)((n + (int64_t)p.nwaves * p.mpw - 1) / ((int64_t)p.nwaves * p.mpw));
-  const int64_t g = std::max<int64_t>((p.ntiles + 15) / 16, std::max<int64_t>(1, cus * 2 / p.groups));
-  p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, g));
-  return p;
-}
-
-size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted) {
-  const MeanPlan p1 = mean_plan(n, m, dtype, iso_kind, weighted);
-  const MeanPlan p3 = rows_plan(n, m, dtype);
-  // the same pieces, in the same order, as launch_pairs_linear carves
-  Carve c(nullptr);
-  c.take<char>(mean_workspace(p1, n, m));
-  c.take<double>((size_t)n);                     // masses
-  c.take<double>((size_t)n);                     // IN_in
-  c.take<double>((size_t)n);                     // coefficients 1 / m_j
-  c.take<double>((size_t)m);                     // t(x)
-  c.take<double>((size_t)m * (size_t)colsum_groups(n, m, elem_bytes(dtype)));   // member-group partials of t
-  c.take<double>((size_t)p3.grid * 2 * n);       // row partials
-  c.take<double>((size_t)2 * n);                 // reduced m, B
-  return c.off + 256;
-}
-
 template <typename T>
 static void launch_linear_t(const pid_ensemble& e, int iso_kind, const Extract& ex, bool vec, const MeanPlan& p3,
                             void* coef, int tg, void* tpart, void* tbuf, double* part, hipStream_t st) {
@@ -1335,7 +1158,7 @@ hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const Extrac
   double* inin = c.take<double>((size_t)e.n);
   void* coef = c.take<double>((size_t)e.n);
   void* tbuf = c.take<double>((size_t)e.m);
-  const int tg = colsum_groups(e.n, e.m, elem_bytes(e.dtype));
+  const int tg = colsum_groups(e.n, e.m, elem_bytes_of(e.dtype));
   void* tpart = c.take<double>((size_t)e.m * (size_t)tg);
   double* part = c.take<double>((size_t)p3.grid * 2 * e.n);
   double* red = c.take<double>((size_t)2 * e.n);
@@ -1353,7 +1176,7 @@ hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const Extrac
     hipLaunchKernelGGL(inv_mass_kernel<float>, (int)((e.n + 255) / 256), 256, 0, st, mass, (int)e.n, (float*)coef);
   // passes 2 and 3: t, then B
   Extract ex = __builtin_bit_cast(Extract, exh);
-  const int eb = elem_bytes(e.dtype);
+  const int eb = elem_bytes_of(e.dtype);
   const bool vec = ((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
                    (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0);
   switch (e.dtype) {

@@ -11,6 +11,12 @@ namespace pidk {
 
 struct Extract;  // device_common.h
 
+// How a stored value becomes a membership probability (compile-time mode of
+// every loader; Sec. 3.5).
+enum Mode { MODE_NONE = 0, MODE_GAUSS = 1, MODE_STEP = 2 };
+int iso_mode(int iso_kind);
+int elem_bytes_of(int dtype);
+
 // Host copy of the isovalue model, converted once per call.
 struct ExtractHost {
   int side;
@@ -50,11 +56,16 @@ struct MeanPlan {
   int dma_rpw;      // >0: LDS-staged single pass, rows per wave (soft masks)
   int dma_nwaves, dma_grid;
   size_t dma_lds;
+  int unsupported;  // 1: no launch geometry keeps the exact integer sums in range
 };
 MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted);
 size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m);
 hipError_t launch_pid_mean(const MeanPlan& p, const pid_ensemble& e, int iso_kind,
                            const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st);
+// Member groups of a column-sum pass; the two-pass row plan of the all-pairs
+// depths without the matrix.
+int colsum_groups(int64_t n, int64_t m, int eb);
+MeanPlan rows_plan(int64_t n, int64_t m, int dtype);
 
 // All-pairs depths (no inclusion matrix) in three streaming passes.
 size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted);
@@ -63,6 +74,9 @@ hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const Extrac
 
 // ---------------------------------------------------------------- all-pairs
 enum Scheme { SCH_F64 = 1, SCH_F32 = 2, SCH_F16 = 3, SCH_BF16 = 4, SCH_BF16_SPLIT = 5, SCH_I8 = 6 };
+// Element type the Gram product multiplies in.
+enum MType { MT_F16 = 0, MT_BF16 = 1, MT_BF16X3 = 2, MT_I8 = 3, MT_F32 = 4, MT_F64 = 5 };
+int mtype_of(int scheme);
 
 struct PairsPlan {
   int scheme;
@@ -78,11 +92,13 @@ struct PairsPlan {
   int ks;           // points per slab
   size_t lds_bytes;
   int part_elem;    // bytes per partial element (4 or 8)
+  int unsupported;  // 1: N or the launch grid beyond what the kernels address
 };
 PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted, int scheme);
 size_t pairs_workspace(const PairsPlan& p, int64_t n);
 // True when the Gram kernel is built for this input dtype, scheme and iso kind.
 bool pairs_supported(int dtype, int iso_kind, int scheme);
+bool gram_supported(int dtype, int mt, int mode);
 // mean_out non-null: also write the PID-mean outputs, from the Gram row sums
 // (A_i = sum_j G_ij) and the masses of the same pass.
 hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_kind,

@@ -23,11 +23,12 @@ def test_exports_every_declared_symbol():
                 "pid_server_create", "pid_submit", "pid_poll", "pid_wait", "pid_request_times",
                 "pid_server_destroy", "pid_status_string", "pid_last_error", "pid_abi_version",
                 "pid_timing_enable", "pid_timing_get", "pid_timing_select",
-                "pid_timing_sample", "pid_bands"}
+                "pid_timing_sample", "pid_bands", "pid_server_set_budget", "pid_server_clock",
+                "pid_request_device_times", "pid_release"}
     assert expected <= set(names), set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pid_abi_version() == 2
+    assert lib.pid_abi_version() == 3
     assert lib.pid_status_string(5) == b"PID_ERR_VALUE_RANGE"
 
 
