@@ -182,6 +182,21 @@ pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* 
 pid_status pid_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* pairs_out,
                     const pid_out* mean_out, void* workspace, size_t ws_bytes, void* stream);
 
+/* pid_both without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  The workspace is a fixed array of
+ * PID_STATIC_SCRATCH_BYTES in the library's device code: one copy per GPU,
+ * allocated when the library's code is loaded on that GPU and held until the
+ * process ends; the call itself allocates nothing.  Outputs, results and
+ * errors as pid_both; PID_ERR_UNSUPPORTED when the call's workspace
+ * (pid_workspace_size, variant 2) exceeds the array.  Every call on one GPU
+ * uses the same array, so calls on one GPU must not overlap: two calls on
+ * different streams, or from different threads, without an ordering between
+ * them race on it. */
+#define PID_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+pid_status pid_both_static(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* pairs_out,
+                           const pid_out* mean_out, void* stream);
+
 /* Fuzzy-contour extraction alone (Sec. 3.5): writes u = model(value) for the
  * N x M ensemble into `u_out` (dense N x M, row stride M) as float (out_dtype
  * PID_F32) or double (PID_F64); Phi by erfcf for float output and erfc for
