@@ -14,6 +14,10 @@ integers.  Each function names the passage of the paper it follows:
 * PID: IN_in, IN_out = means over j of the inclusions; min  -- Sec. 3.2, Eq. pid
 * PID-mean against the mean contour ``ubar``               -- Sec. 4.1
 * fuzzy extraction ``p = P(inside | isovalue ~ N(c, s^2))`` -- Sec. 3.5 (isovalue distribution)
+* further probability models: a uniform isovalue distribution (Sec. 3.5),
+  the level-centred map with linear fall-off (Sec. 3.6, weather example) and
+  the normalised density (Sec. 6.3)
+* PID-mean against a reliability-weighted mean contour   -- Sec. 4.1 (properties of PID-mean)
 * binary reduction to the eID subset operator              -- Sec. 3.1 Eq. 1 and Sec. 3.2 Eq. binary_reduction
 * ranking: deepest first                                   -- Sec. 5.1
 * contour-boxplot bands: median, unions and intersections
@@ -29,7 +33,14 @@ design notes of the repository):
   ``side = -1`` is the sublevel set ``f < c`` of Sec. 3.1 Eq. 2;
 * binary threshold is strict: ``side*(f - c) > 0`` is inside;
 * ranks: rank 0 is the deepest member, ties broken by the lower index;
-* boxplot binarisation: a point is inside a member when ``u >= threshold``.
+* boxplot binarisation: a point is inside a member when ``u >= threshold``;
+* uniform isovalue distribution: the isovalue is uniform on ``[c - h, c + h]``
+  (``h`` = ``width``), so ``p = P(q < f)`` rises linearly from 0 to 1 there;
+* level-centred map: ``p = max(0, 1 - |f - c| / h)``, 1 at the target level and
+  0 from a distance ``h`` (``width``) on (the paper gives no fall-off width);
+* normalised density: ``p = clip(f / c, 0, 1)`` with ``c`` the normalising
+  density, e.g. the ensemble's largest density (the paper does not say which);
+* reliability weights ``r_j >= 0`` (sum > 0): ``ubar = sum_j r_j u_j / sum_j r_j``.
 
 Pinned by ``tests/test_oracle_pins.py`` against exact-rational brute force,
 eID set counting, closed forms for nested chains, a hand-worked fixture, the
@@ -47,7 +58,7 @@ __all__ = [
     "extract", "mass", "incl", "gram", "inclusion_matrix", "pid", "pid_mean",
     "pid_mean_literal", "pid_linear", "rank_order", "eid_sets",
     "binary_pid", "binary_pid_mean", "pid_large", "pid_mean_large",
-    "exact_pid", "exact_pid_mean", "boxplot_bands",
+    "exact_pid", "exact_pid_mean", "boxplot_bands", "pid_mean_weighted",
 ]
 
 
@@ -62,17 +73,34 @@ def extract(data, iso=None):
     ``iso`` is None / ``{"kind": "none"}`` (the values already are soft masks,
     Sec. 3.5 explicit soft masks), ``{"kind": "gaussian", "c", "sigma", "side"}``
     (isovalue ~ N(c, sigma^2): inside probability
-    ``Phi(side*(f - c)/sigma)``), or ``{"kind": "step", "c", "side"}`` (a sharp
-    isovalue: inside iff ``side*(f - c) > 0``, compared exactly in float64)."""
+    ``Phi(side*(f - c)/sigma)``), ``{"kind": "step", "c", "side"}`` (a sharp
+    isovalue: inside iff ``side*(f - c) > 0``, compared exactly in float64),
+    ``{"kind": "ramp", "c", "width", "side"}`` (isovalue uniform on
+    ``[c - width, c + width]``: inside probability ``P(q < f)`` for side +1,
+    ``P(q > f)`` for side -1), ``{"kind": "tent", "c", "width"}`` (the
+    level-centred map of Sec. 3.6: 1 at ``f = c``, falling linearly to 0 at
+    ``|f - c| = width``) or ``{"kind": "density", "c"}`` (the normalised
+    density of Sec. 6.3: ``f / c`` clipped to [0, 1])."""
     f = _f64(data)
     if iso is None or iso.get("kind", "none") == "none":
         return f
     side = float(iso.get("side", 1))
     c = float(iso["c"])
-    if iso["kind"] == "gaussian":
+    kind = iso["kind"]
+    if kind == "gaussian":
         return ndtr(side * (f - c) / float(iso["sigma"]))
-    if iso["kind"] == "step":
+    if kind == "step":
         return (side * (f - c) > 0).astype(np.float64)
+    if kind == "ramp":
+        h = float(iso["width"])
+        lo = c - h                          # support of the isovalue: [c - h, c + h]
+        below = np.clip((f - lo) / (2.0 * h), 0.0, 1.0)   # P(q < f)
+        return below if side > 0 else 1.0 - below
+    if kind == "tent":
+        h = float(iso["width"])
+        return np.maximum(0.0, 1.0 - np.abs(f - c) / h)
+    if kind == "density":
+        return np.clip(f / c, 0.0, 1.0)
     raise ValueError(iso)
 
 
@@ -151,6 +179,21 @@ def pid_mean_literal(U, w=None):
     in_in = np.array([incl(u, ubar, w) for u in U])
     in_out = np.array([incl(ubar, u, w) for u in U])
     return dict(in_in=in_in, in_out=in_out, depth=np.minimum(in_in, in_out))
+
+
+def pid_mean_weighted(U, r, w=None):
+    """PID-mean against a reliability-weighted mean contour (Sec. 4.1, the
+    optional weighting of the point-wise mean): ``ubar = sum_j r_j u_j /
+    sum_j r_j`` with member weights ``r_j >= 0`` (not all 0); then
+    ``IN_in = u_i <_p ubar``, ``IN_out = ubar <_p u_i``, depth = min, each
+    evaluated by the inclusion operator on the materialised ``ubar``."""
+    U = _f64(U)
+    r = _f64(r)
+    ubar = (r[:, None] * U).sum(axis=0) / r.sum()
+    in_in = np.array([incl(u, ubar, w) for u in U])
+    in_out = np.array([incl(ubar, u, w) for u in U])
+    return dict(mass=mass(U, w), mbar=float(mass(ubar, w)), in_in=in_in, in_out=in_out,
+                depth=np.minimum(in_in, in_out))
 
 
 def pid_linear(U, w=None):

@@ -460,3 +460,97 @@ def test_boxplot_bands_de_morgan():
     assert np.array_equal(c["union_inner"], ~a["inter_inner"])
     assert np.array_equal(c["inter_outer"], ~a["union_outer"])
     assert np.array_equal(c["median"], ~a["median"])
+
+
+# ------------------------------------------ Sec. 3.5, 3.6, 6.3: further models
+def test_golden_probability_models():
+    g = golden.load("weighted_mean_and_models.txt")
+    f = np.array([float(v) for v in g["f"]])
+    cases = {"ramp_up": dict(kind="ramp", c=0.5, width=0.125, side=1),
+             "ramp_down": dict(kind="ramp", c=0.5, width=0.125, side=-1),
+             "tent": dict(kind="tent", c=0.5, width=0.125),
+             "density": dict(kind="density", c=0.5)}
+    for key, iso in cases.items():
+        assert oracle.extract(f, iso).tolist() == [float(v) for v in g[key]], key
+
+
+def test_models_reduce_to_library_distributions():
+    """The ramp is the CDF of the uniform isovalue distribution, the tent the
+    width-scaled density of the symmetric triangular distribution."""
+    from scipy import stats
+    rng = _rng(77)
+    for c, h in ((0.5, 0.05), (-2.0, 1.5), (10.0, 1e-3)):
+        f = c + h * rng.uniform(-3, 3, size=2000)
+        up = oracle.extract(f, dict(kind="ramp", c=c, width=h, side=1))
+        np.testing.assert_allclose(up, stats.uniform(loc=c - h, scale=2 * h).cdf(f), atol=1e-12, rtol=0)
+        down = oracle.extract(f, dict(kind="ramp", c=c, width=h, side=-1))
+        np.testing.assert_allclose(down, stats.uniform(loc=c - h, scale=2 * h).sf(f), atol=1e-12, rtol=0)
+        tent = oracle.extract(f, dict(kind="tent", c=c, width=h))
+        np.testing.assert_allclose(tent, h * stats.triang(0.5, loc=c - h, scale=2 * h).pdf(f), atol=1e-9, rtol=0)
+        # the tent is twice the distance of the ramp to the nearer of 0 and 1
+        np.testing.assert_allclose(tent, 2 * np.minimum(up, 1 - up), atol=1e-12, rtol=0)
+        dens = oracle.extract(f, dict(kind="density", c=abs(c) + h))
+        assert dens.min() >= 0.0 and dens.max() <= 1.0
+        inside = (f > 0) & (f < abs(c) + h)
+        np.testing.assert_allclose(dens[inside] * (abs(c) + h), f[inside], rtol=1e-15)
+    # a vanishing width gives the sharp isovalue away from the level itself
+    f = rng.uniform(0, 1, size=5000)
+    f = f[np.abs(f - 0.5) > 1e-6]
+    for side in (1, -1):
+        ramp = oracle.extract(f, dict(kind="ramp", c=0.5, width=1e-9, side=side))
+        assert (ramp == oracle.extract(f, dict(kind="step", c=0.5, side=side))).all()
+
+
+# ------------------------------------------ Sec. 4.1: reliability-weighted mean
+def test_golden_weighted_mean():
+    g = golden.load("weighted_mean_and_models.txt")
+    U = np.array([[float(v) for v in g[k]] for k in ("wu1", "wu2", "wu3")])
+    r = np.array([float(v) for v in g["wr"]])
+    res = oracle.pid_mean_weighted(U, r)
+    assert abs(res["mbar"] - float(g["w_mbar"][0])) < 1e-15
+    for key in ("in_in", "in_out", "depth"):
+        np.testing.assert_allclose(res[key], [float(v) for v in g["w_" + key]], rtol=0, atol=1e-15)
+    assert oracle.rank_order(res["depth"])[0].tolist() == [int(v) for v in g["w_rank"]]
+
+
+@pytest.mark.parametrize("seed,weighted", [(1, False), (2, True), (3, True)])
+def test_weighted_mean_pins(seed, weighted):
+    rng = _rng(seed)
+    n, m = 7, 40
+    U = _dyadic(n, m, seed + 50, zero_rows=(4,))
+    w = rng.integers(1, 4, size=m).astype(np.float64) if weighted else None
+    # unit weights: the plain PID-mean
+    a, b = oracle.pid_mean_weighted(U, np.ones(n), w), oracle.pid_mean(U, w)
+    for key in ("in_in", "in_out", "depth"):
+        np.testing.assert_allclose(a[key], b[key], rtol=0, atol=1e-15)
+    # integer weights: the plain PID-mean of the ensemble with member j
+    # repeated r_j times (members of weight 0 compared against that mean too)
+    r = rng.integers(0, 4, size=n)
+    r[0] = 2
+    rep = np.repeat(U, r, axis=0)
+    plain = oracle.pid_mean(rep, w)
+    wm = oracle.pid_mean_weighted(U, r.astype(np.float64), w)
+    first = np.concatenate([[0], np.cumsum(r)[:-1]])
+    for j in range(n):
+        if r[j] > 0:
+            for key in ("in_in", "in_out"):
+                assert abs(wm[key][j] - plain[key][first[j]]) < 1e-14, (key, j)
+    # one-hot weights: the mean contour is that member
+    for k in (0, 3):
+        e = np.zeros(n)
+        e[k] = 5.0
+        res = oracle.pid_mean_weighted(U, e, w)
+        for i in range(n):
+            assert abs(res["in_in"][i] - oracle.incl(U[i], U[k], w)) < 1e-15
+            assert abs(res["in_out"][i] - oracle.incl(U[k], U[i], w)) < 1e-15
+    # scale invariance in r; weighted recall identity through the Gram numerators
+    rr = rng.uniform(0.1, 2.0, size=n)
+    x, y = oracle.pid_mean_weighted(U, rr, w), oracle.pid_mean_weighted(U, 3.7 * rr, w)
+    np.testing.assert_allclose(x["depth"], y["depth"], rtol=0, atol=1e-15)
+    G, mm = oracle.gram(U, w), oracle.mass(U, w)
+    for i in range(n):
+        exp = (G[i] @ rr) / (rr.sum() * mm[i]) if mm[i] > 0 else 0.0
+        assert abs(x["in_in"][i] - exp) < 1e-14
+    # a planted mistake (ubar normalised by N instead of sum r) fails the pin
+    bad_ubar = (rr[:, None] * U).sum(axis=0) / n
+    assert abs(oracle.incl(U[0], bad_ubar, w) - x["in_in"][0]) > 1e-3
