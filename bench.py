@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "all-pairs PID pair·points/s (MFMA vs FP32) at ≤1e-4 err; PID-mean GB/s; p99 ms"
 HBM_PEAK_GBPS = 8000.0
 TIME_EVERY = 4   # the Gram kernel is bracketed by events on every 4th timed launch
+ROTATE = 4       # resident copies of the headline batch the timed steps cycle over
 KERNEL_SOURCES = ["paper_2512_15187_amd/csrc/gram_kernel.h", "paper_2512_15187_amd/csrc/device_common.h",
                   "paper_2512_15187_amd/csrc/k_gram.hip", "paper_2512_15187_amd/csrc/k_gram_f32.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_f16_2d_n256_m262144_traffic.txt")
@@ -167,14 +168,24 @@ def headline(args):
     log("generating the 2D soft-mask ensemble N=256 on 512x512 (FP32)")
     U, _ = synth.config1(device=dev)
     n, m = U.shape
-    # one call computes both: PID-mean from the Gram row sums of the same pass
-    both = pid.PreparedCall("both", U, gemm="f16", inclusion=True)
+    # The timed steps cycle over ROTATE resident copies of the batch (1.07 GB
+    # in all, four times the 256 MB Infinity Cache), so that every step reads
+    # its masks from HBM, as a stream of different batches would; one call
+    # computes both depth kinds (PID-mean from the Gram row sums of the pass).
+    copies = [U] + [U.clone() for _ in range(ROTATE - 1)]
+    calls = [pid.PreparedCall("both", c, gemm="f16", inclusion=True) for c in copies]
+    both = calls[0]
+    k_step = [0]
 
     def step():
+        calls[k_step[0] % ROTATE].run()
+        k_step[0] += 1
+
+    def same():
         both.run()
 
     log("timing the step")
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, ROTATE)):
         step()
     torch.cuda.synchronize()
     # timed region: events bracket the dominant kernel only, on every
@@ -201,29 +212,29 @@ def headline(args):
                                                  "pidmean_finalize", "rank")
                  if kernel_ms(pid, k)[1] > 0}
     pid.pid_timing_enable(False)
-    # for context, outside the timed region: the same steps with no events
+    # for context, outside the timed region: the same steps with no events,
+    # and the step repeated on one batch (most of which then stays in the
+    # Infinity Cache between steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t1) / args.steps
-    # the Gram kernel right after 1 GiB of writes to a scratch buffer, which
-    # evicts the 256 MB Infinity Cache (MALL): the masks come from HBM alone
-    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)
     pid.pid_timing_select("gram")
     pid.pid_timing_enable(True)
-    for _ in range(max(5, args.steps // 4)):
-        scratch.fill_(1.0)
-        step()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        same()
     torch.cuda.synchronize()
-    cold = kernel_ms(pid, "gram")
+    t_same = (time.perf_counter() - t2) / args.steps
+    warm = kernel_ms(pid, "gram")
     pid.pid_timing_enable(False)
     pid.pid_timing_select(None)
-    del scratch
     log(f"step {t_step * 1e3:.3f} ms ({t_plain * 1e3:.3f} ms without kernel events); gram "
         f"{kt['gram'][0] * 1e3:.1f} us in the timed region; breakdown " +
-        ", ".join(f"{k} {v[0] * 1e3:.1f} us" for k, v in breakdown.items()))
+        ", ".join(f"{k} {v[0] * 1e3:.1f} us" for k, v in breakdown.items()) +
+        f"; one batch repeated: step {t_same * 1e3:.3f} ms, gram {warm[0] * 1e3:.1f} us")
 
     gram_ms = kt["gram"][0]
     algo_bytes = n * m * 4
@@ -232,7 +243,8 @@ def headline(args):
                 frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=read_traffic(), kernel="gram (FP16 MFMA)",
                 kernel_avg_us=round(gram_ms * 1e3, 2), algorithmic_bytes=algo_bytes,
                 kernel_timed_launches=kt["gram"][1],
-                timed_as=f"HIP events on every {TIME_EVERY}th launch of the timed steps")
+                timed_as=f"HIP events on every {TIME_EVERY}th launch of the timed steps, which cycle over "
+                         f"{ROTATE} resident copies of the batch (no Infinity Cache reuse)")
 
     res_pairs = {k: v.clone() for k, v in both.out.items()}
     res_mean = {k: v.clone() for k, v in both.out_mean.items()}
@@ -240,8 +252,9 @@ def headline(args):
 
     extra = {"kernel_us": {k: round(v[0] * 1e3, 2) for k, v in breakdown.items()},
              "step_us_without_kernel_events": round(t_plain * 1e6, 2),
-             "gram_us_after_mall_flush": round(cold[0] * 1e3, 2),
-             "gram_frac_hbm_after_mall_flush": round(algo_bytes / (cold[0] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+             "one_batch_repeated_step_us": round(t_same * 1e6, 2),
+             "one_batch_repeated_gram_us": round(warm[0] * 1e3, 2),
+             "one_batch_repeated_gram_frac_hbm": round(algo_bytes / (warm[0] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
@@ -268,7 +281,8 @@ def headline(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
         "config": {"workload": "2D soft masks, N=256 on 512x512 (M=262144), FP32 masks; all-pairs PID "
                                "(FP16 MFMA Gram, FP64 normalisation) and PID-mean (from the Gram row sums) "
-                               "from one call (pid_both: one pass over the masks), with both rankings",
+                               "from one call (pid_both: one pass over the masks), with both rankings; steps "
+                               "cycle over 4 resident copies of the batch so that each reads HBM",
                    "n": n, "m": m, "scheme": "f16", "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "extra": extra,
     }
@@ -329,7 +343,13 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
     kmu, _ = kernel_ms(pid, "pidmean")
     pid.pid_timing_enable(False)
     out["mean3d_unweighted_GBps"] = n3 * m3 * 2 / (kmu * 1e-3) / 1e9
-    del U3, w3, call, callu
+    # against a reliability-weighted mean contour: two streaming passes
+    r3 = torch.linspace(0.5, 1.5, n3, dtype=torch.float64, device=dev)
+    callw = pid.PreparedCall("weighted", U3, w3, member_weights=r3)
+    tw = timed(callw.run, max(5, args.steps // 2), 2, torch)
+    out["mean3d_reliability_weighted_call_ms"] = tw * 1e3
+    out["mean3d_reliability_weighted_GBps_2_reads"] = 2 * b3 / tw / 1e9
+    del U3, w3, call, callu, callw
 
     # scalar fields -> fuzzy contours, N=128 on 128^3, fused extraction
     log("scalar-field workload N=128 on 128^3 (FP32 fields, fused Phi)")
@@ -350,6 +370,22 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
         out[f"{name}_kernel_GBps"] = nf * mf * 4 / (kk * 1e-3) / 1e9
         if "pairs" in name:
             out[f"{name}_pp_per_s"] = nf * nf * mf / t
+    # the further probability models on the same fields: ramp (uniform
+    # isovalue), tent (level-centred map), normalised density; PID-mean and
+    # the FP16 all-pairs call
+    fmax = pid.pid_field_max(F).item()
+    models = {"ramp": dict(kind="ramp", c=iso["c"], width=iso["sigma"] * 3 ** 0.5, side=iso["side"]),
+              "tent": dict(kind="tent", c=iso["c"], width=2 * iso["sigma"]),
+              "density": dict(kind="density", c=fmax)}
+    for mname, miso in models.items():
+        for variant, kn in (("mean", "pidmean"), ("pairs", "gram")):
+            call = pid.PreparedCall(variant, F, iso=miso, gemm="f16")
+            pid.pid_timing_enable(True)
+            t = timed(call.run, k, 2, torch)
+            kk, _ = kernel_ms(pid, kn)
+            pid.pid_timing_enable(False)
+            out[f"fields_{variant}_{mname}_call_ms"] = t * 1e3
+            out[f"fields_{variant}_{mname}_kernel_GBps"] = nf * mf * 4 / (kk * 1e-3) / 1e9
     del F
 
     # all-pairs depths without the matrix (three streaming passes) against

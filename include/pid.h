@@ -62,11 +62,18 @@ typedef enum {
   PID_U8 = 4   /* binary masks: every value must be 0 or 1 */
 } pid_dtype;
 
-/* How stored values become membership probabilities (Sec. 3.5). */
+/* How stored values become membership probabilities (Sec. 3.5, 3.6, 6.3). */
 typedef enum {
   PID_ISO_NONE = 0,      /* values already are probabilities in [0,1] (soft masks)          */
   PID_ISO_GAUSSIAN = 1,  /* scalar field, isovalue ~ N(c, sigma^2): u = Phi(side*(f-c)/sigma) */
-  PID_ISO_STEP = 2       /* scalar field, sharp isovalue: u = 1 iff side*(f-c) > 0, else 0   */
+  PID_ISO_STEP = 2,      /* scalar field, sharp isovalue: u = 1 iff side*(f-c) > 0, else 0   */
+  PID_ISO_RAMP = 3,      /* scalar field, isovalue uniform on [c - sigma, c + sigma] (Sec. 3.5):
+                            u = P(isovalue < f) = clamp(1/2 + side*(f-c)/(2 sigma), 0, 1)     */
+  PID_ISO_TENT = 4,      /* level-centred map (Sec. 3.6): u = max(0, 1 - |f - c| / sigma):
+                            1 at the level c, falling linearly to 0 at distance sigma      */
+  PID_ISO_DENSITY = 5    /* normalised density (Sec. 6.3): u = clamp(f / c, 0, 1), c > 0 the
+                            normalising density (e.g. the ensemble's largest density,
+                            pid_field_max)                                                  */
 } pid_iso_kind;
 
 /* Arithmetic of the all-pairs numerators G_ij = sum_x w u_i u_j. */
@@ -101,8 +108,12 @@ typedef struct {
 } pid_ensemble;
 
 /* Isovalue model.  side = +1: f > c is inside (p = Phi((f - c)/sigma));
- * side = -1: f < c is inside (the sublevel set of Sec. 3.1 Eq. 2).
- * sigma is used by PID_ISO_GAUSSIAN only and must be > 0 there. */
+ * side = -1: f < c is inside (the sublevel set of Sec. 3.1 Eq. 2).  side
+ * must be +1 or -1 for GAUSSIAN, STEP and RAMP and is ignored by TENT and
+ * DENSITY.  sigma (GAUSSIAN: standard deviation; RAMP: half-width of the
+ * isovalue interval; TENT: fall-off width) must be finite and > 0 there;
+ * c must be finite, and > 0 for DENSITY.  RAMP, TENT and DENSITY take
+ * F64, F32 or F16 fields (PID_ERR_UNSUPPORTED otherwise). */
 typedef struct {
   int32_t kind;     /* pid_iso_kind */
   int32_t side;     /* +1 or -1 */
@@ -125,8 +136,9 @@ typedef struct {
 } pid_out;
 
 /* Bytes of device workspace needed by pid_all_pairs (variant 0), pid_mean
- * (variant 1), pid_both (variant 2) or pid_pairs_depths (variant 3; gemm is
- * ignored) for this ensemble, isovalue model and
+ * (variant 1), pid_both (variant 2), pid_pairs_depths (variant 3; gemm is
+ * ignored) or pid_mean_weighted (variant 4; gemm is ignored) for this
+ * ensemble, isovalue model and
  * scheme.  The size depends on n, m, dtype, iso kind, weights (NULL or not)
  * and scheme only.  iso may be NULL (= PID_ISO_NONE). */
 pid_status pid_workspace_size(const pid_ensemble* ens, const pid_iso* iso, int variant,
@@ -165,6 +177,27 @@ pid_status pid_pairs_depths(const pid_ensemble* ens, const pid_iso* iso, const p
  * out->inclusion is ignored. */
 pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out,
                     void* workspace, size_t ws_bytes, void* stream);
+
+/* PID-mean against a reliability-weighted mean contour (Sec. 4.1, the
+ * optional weighting of the point-wise mean): with member weights r_j >= 0
+ * (member_w: N device doubles, not all 0; the library reads them, the caller
+ * owns them), ubar = sum_j r_j u_j / R with R = sum_j r_j, IN_in = u_i <_p ubar
+ * = A_i / (R m_i) and IN_out = ubar <_p u_i = A_i / sum_j r_j m_j, where
+ * A_i = sum_x w u_i(x) sum_j r_j u_j(x).  Two streaming passes: the weighted
+ * column sums into the workspace, then m_i and A_i.  FP32 sums inside a tile
+ * (FP64 for FP64 input), FP64 across tiles; binary input takes the same soft
+ * arithmetic.  R <= 0 gives zero depths.  out->inclusion is ignored; the
+ * other outputs as pid_mean.  Workspace: pid_workspace_size(variant 4).
+ * Unit weights give the values of pid_mean within its tolerance. */
+pid_status pid_mean_weighted(const pid_ensemble* ens, const pid_iso* iso, const double* member_w,
+                             const pid_out* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Largest stored value of the ensemble (values that are NaN are skipped; NaN
+ * if every value is), written as one double to the device pointer max_out
+ * (8-byte aligned): e.g. the normalising density c of PID_ISO_DENSITY (Sec.
+ * 6.3), read back by the caller before the depth call.  Exact; one streaming
+ * pass, asynchronous on `stream`.  Weights and flags are ignored. */
+pid_status pid_field_max(const pid_ensemble* ens, double* max_out, void* stream);
 
 /* All-pairs PID and PID-mean of one ensemble (Sec. 3.2 with the weighted
  * sums of Sec. 3.4, and Sec. 4.1) from one all-pairs pass.  pairs_out as

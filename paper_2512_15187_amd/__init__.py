@@ -26,7 +26,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pid.h")
 PID_OK, PID_ERR_INVALID_ARG, PID_ERR_UNSUPPORTED, PID_ERR_WORKSPACE_TOO_SMALL = 0, 1, 2, 3
 PID_ERR_DEVICE, PID_ERR_VALUE_RANGE, PID_ERR_OVER_BUDGET, PID_ERR_CANCELLED, PID_ERR_INTERNAL = 4, 5, 6, 7, 8
 PID_F64, PID_F32, PID_F16, PID_BF16, PID_U8 = 0, 1, 2, 3, 4
-PID_ISO_NONE, PID_ISO_GAUSSIAN, PID_ISO_STEP = 0, 1, 2
+PID_ISO_NONE, PID_ISO_GAUSSIAN, PID_ISO_STEP, PID_ISO_RAMP, PID_ISO_TENT, PID_ISO_DENSITY = 0, 1, 2, 3, 4, 5
 GEMM = {"auto": 0, "f64": 1, "f32": 2, "f16": 3, "bf16": 4, "bf16_split": 5, "i8": 6}
 PID_FLAG_VALIDATE = 1
 
@@ -85,6 +85,9 @@ def load_library(path: str = LIB_PATH):
         "pid_all_pairs": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_mean": ([P(pid_ensemble), P(pid_iso), P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_pairs_depths": ([P(pid_ensemble), P(pid_iso), P(pid_out), V, ctypes.c_size_t, V], I32),
+        "pid_mean_weighted": ([P(pid_ensemble), P(pid_iso), V, P(pid_out), V, ctypes.c_size_t, V], I32),
+        "pid_field_max": ([P(pid_ensemble), V, V], I32),
+        "pid_both_static": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), P(pid_out), V], I32),
         "pid_both": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_extract": ([P(pid_ensemble), P(pid_iso), V, I32, V], I32),
         "pid_rank": ([V, I64, V, V, V], I32),
@@ -156,11 +159,15 @@ def make_ensemble(U: torch.Tensor, weights: torch.Tensor | None = None, validate
 
 def make_iso(iso: dict | None):
     """``None`` / {"kind": "none"}; {"kind": "gaussian", "c", "sigma", "side"};
-    {"kind": "step", "c", "side"}."""
+    {"kind": "step", "c", "side"}; {"kind": "ramp", "c", "width", "side"};
+    {"kind": "tent", "c", "width"}; {"kind": "density", "c"} (the width goes
+    into the C struct's ``sigma``)."""
     if iso is None or iso.get("kind", "none") == "none":
         return pid_iso(PID_ISO_NONE, 1, 0.0, 0.0)
-    kind = {"gaussian": PID_ISO_GAUSSIAN, "step": PID_ISO_STEP}[iso["kind"]]
-    return pid_iso(kind, int(iso.get("side", 1)), float(iso["c"]), float(iso.get("sigma", 0.0)))
+    kind = {"gaussian": PID_ISO_GAUSSIAN, "step": PID_ISO_STEP, "ramp": PID_ISO_RAMP, "tent": PID_ISO_TENT,
+            "density": PID_ISO_DENSITY}[iso["kind"]]
+    width = iso.get("width", iso.get("sigma", 0.0))
+    return pid_iso(kind, int(iso.get("side", 1)), float(iso["c"]), float(width))
 
 
 def _stream_ptr(stream):
@@ -244,6 +251,36 @@ def pid_pairs_depths(U, weights=None, iso=None, workspace=None, stream=None, val
     return d
 
 
+def pid_mean_weighted(U, member_weights, weights=None, iso=None, workspace=None, stream=None, validate=False):
+    """PID-mean against the mean contour weighted by ``member_weights`` (a
+    float64 device vector of N reliabilities).  Returns mass, in_in, in_out,
+    depth (float64), rank, order."""
+    lib = load_library()
+    e, i = make_ensemble(U, weights, validate), make_iso(iso)
+    _require_gpu(member_weights, "member_weights")
+    if member_weights.dtype != torch.float64 or member_weights.numel() != U.shape[0] \
+            or not member_weights.is_contiguous():
+        raise ValueError("member_weights must be a contiguous float64 vector of length N")
+    ws_n = ctypes.c_size_t(0)
+    _check(lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 4, 0, ctypes.byref(ws_n)))
+    ws = _workspace(ws_n.value, U.device, workspace)
+    d, o = _outputs(U.shape[0], U.device, False)
+    _check(lib.pid_mean_weighted(ctypes.byref(e), ctypes.byref(i), ctypes.c_void_p(member_weights.data_ptr()),
+                                 ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws_n.value, _stream_ptr(stream)))
+    d["_workspace"] = ws
+    return d
+
+
+def pid_field_max(U, stream=None):
+    """Largest stored value of the ensemble as a one-element float64 device
+    tensor (NaN values skipped)."""
+    lib = load_library()
+    e = make_ensemble(U)
+    out = torch.empty(1, dtype=torch.float64, device=U.device)
+    _check(lib.pid_field_max(ctypes.byref(e), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
 def pid_both(U, weights=None, iso=None, gemm="auto", inclusion=True, workspace=None, stream=None,
              validate=False):
     """All-pairs PID and PID-mean in one call, from one all-pairs pass (the
@@ -315,9 +352,12 @@ class PreparedCall:
     the all-pairs results and ``out_mean`` the PID-mean ones) or "depths"
     (all-pairs depths without the inclusion matrix)."""
 
-    def __init__(self, variant, U, weights=None, iso=None, gemm="auto", inclusion=False):
+    def __init__(self, variant, U, weights=None, iso=None, gemm="auto", inclusion=False, member_weights=None):
         lib = load_library()
-        self.variant = {"pairs": 0, "mean": 1, "both": 2, "depths": 3}[variant]
+        self.variant = {"pairs": 0, "mean": 1, "both": 2, "depths": 3, "weighted": 4}[variant]
+        if self.variant == 4 and (member_weights is None or member_weights.dtype != torch.float64):
+            raise ValueError("variant 'weighted' needs float64 member_weights")
+        self.member_weights = member_weights
         self.gemm = GEMM[gemm]
         self.e, self.i = make_ensemble(U, weights), make_iso(iso)
         n = ctypes.c_size_t(0)
@@ -343,6 +383,10 @@ class PreparedCall:
         elif self.variant == 3:
             _check(lib.pid_pairs_depths(ctypes.byref(self.e), ctypes.byref(self.i), ctypes.byref(self.o), ws,
                                         self.ws_bytes, st))
+        elif self.variant == 4:
+            _check(lib.pid_mean_weighted(ctypes.byref(self.e), ctypes.byref(self.i),
+                                         ctypes.c_void_p(self.member_weights.data_ptr()), ctypes.byref(self.o), ws,
+                                         self.ws_bytes, st))
         else:
             _check(lib.pid_both(ctypes.byref(self.e), ctypes.byref(self.i), self.gemm, ctypes.byref(self.o),
                                 ctypes.byref(self.om), ws, self.ws_bytes, st))

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -52,13 +53,18 @@ pid_status check_ensemble(const pid_ensemble* e, const pid_iso* iso, int* iso_ki
   if (!e->data) return fail(PID_ERR_INVALID_ARG, "data is NULL");
   if (e->flags & ~PID_FLAG_VALIDATE) return fail(PID_ERR_INVALID_ARG, "unknown flags 0x%x", e->flags);
   int kind = iso ? iso->kind : PID_ISO_NONE;
-  if (kind != PID_ISO_NONE && kind != PID_ISO_GAUSSIAN && kind != PID_ISO_STEP)
-    return fail(PID_ERR_INVALID_ARG, "unknown iso kind %d", kind);
+  if (kind < PID_ISO_NONE || kind > PID_ISO_DENSITY) return fail(PID_ERR_INVALID_ARG, "unknown iso kind %d", kind);
   if (kind != PID_ISO_NONE) {
-    if (iso->side != 1 && iso->side != -1) return fail(PID_ERR_INVALID_ARG, "iso side must be +1 or -1");
+    const bool sided = kind == PID_ISO_GAUSSIAN || kind == PID_ISO_STEP || kind == PID_ISO_RAMP;
+    if (sided && iso->side != 1 && iso->side != -1) return fail(PID_ERR_INVALID_ARG, "iso side must be +1 or -1");
     if (!std::isfinite(iso->c)) return fail(PID_ERR_INVALID_ARG, "iso c must be finite");
-    if (kind == PID_ISO_GAUSSIAN && !(iso->sigma > 0.0 && std::isfinite(iso->sigma)))
+    const bool widthed = kind == PID_ISO_GAUSSIAN || kind == PID_ISO_RAMP || kind == PID_ISO_TENT;
+    if (widthed && !(iso->sigma > 0.0 && std::isfinite(iso->sigma)))
       return fail(PID_ERR_INVALID_ARG, "iso sigma must be finite and > 0");
+    if (kind == PID_ISO_DENSITY && !(iso->c > 0.0))
+      return fail(PID_ERR_INVALID_ARG, "iso c (the normalising density) must be > 0");
+    if (kind >= PID_ISO_RAMP && e->dtype != PID_F64 && e->dtype != PID_F32 && e->dtype != PID_F16)
+      return fail(PID_ERR_UNSUPPORTED, "iso kind %d takes F64, F32 or F16 fields", kind);
   }
   *iso_kind = kind;
   return PID_OK;
@@ -72,6 +78,13 @@ pidk::ExtractHost make_extract(const pid_iso* iso) {
   x.cf = (float)iso->c;
   if (iso->kind == PID_ISO_GAUSSIAN) {
     x.ad = -(double)iso->side / (iso->sigma * std::sqrt(2.0));
+    x.af = (float)x.ad;
+  } else if (iso->kind >= PID_ISO_RAMP) {
+    // t = (f - c) * a: RAMP a = side / (2 h), TENT a = 1 / h, DENSITY c = 0, a = 1 / c
+    x.model = iso->kind;
+    if (iso->kind == PID_ISO_RAMP) x.ad = (double)iso->side / (2.0 * iso->sigma);
+    else if (iso->kind == PID_ISO_TENT) x.ad = 1.0 / iso->sigma;
+    else { x.ad = 1.0 / iso->c; x.cd = 0.0; x.cf = 0.0f; }
     x.af = (float)x.ad;
   }
   // largest float <= c and smallest float >= c (exact comparisons of float fields)
@@ -193,14 +206,18 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
     s = workspace_size(ens, iso, 0, gemm, &kp);   // the all-pairs pass serves both
     if (s != PID_OK) return s;
     kb = kp;
+  } else if (variant == 4) {
+    if (pidk::rows_plan(ens->n, ens->m, ens->dtype).unsupported)
+      return fail(PID_ERR_UNSUPPORTED, "n = %lld is beyond the PID-mean launch limits", (long long)ens->n);
+    kb = pidk::mean_weighted_workspace(ens->n, ens->m, ens->dtype);
   } else if (variant == 3) {
     if (pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr).unsupported ||
         pidk::rows_plan(ens->n, ens->m, ens->dtype).unsupported)
       return fail(PID_ERR_UNSUPPORTED, "n = %lld is beyond the PID-mean launch limits", (long long)ens->n);
     kb = pidk::pairs_linear_workspace(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
   } else {
-    return fail(PID_ERR_INVALID_ARG,
-                "variant must be 0 (all-pairs), 1 (PID-mean), 2 (both) or 3 (all-pairs depths)");
+    return fail(PID_ERR_INVALID_ARG, "variant must be 0 (all-pairs), 1 (PID-mean), 2 (both), 3 (all-pairs "
+                "depths) or 4 (PID-mean with member weights)");
   }
   *bytes = ((kb + 255) / 256) * 256 + extra_bytes(ens->n, variant == 2 ? 2 : 1);
   return PID_OK;
@@ -320,6 +337,49 @@ pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* 
 pid_status pid_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const pid_out* pairs_out,
                     const pid_out* mean_out, void* workspace, size_t ws_bytes, void* stream) {
   return pidapi::run_both(ens, iso, gemm, pairs_out, mean_out, workspace, ws_bytes, stream);
+}
+
+pid_status pid_mean_weighted(const pid_ensemble* ens, const pid_iso* iso, const double* member_w, const pid_out* out,
+                             void* workspace, size_t ws_bytes, void* stream) {
+  int kind = 0;
+  pid_status s = check_ensemble(ens, iso, &kind);
+  if (s != PID_OK) return s;
+  if (!member_w) return fail(PID_ERR_INVALID_ARG, "member_w is NULL");
+  if (!out) return fail(PID_ERR_INVALID_ARG, "out is NULL");
+  if (!workspace) return fail(PID_ERR_INVALID_ARG, "workspace is NULL");
+  size_t need = 0;
+  s = pidapi::workspace_size(ens, iso, 4, PID_GEMM_AUTO, &need);
+  if (s != PID_OK) return s;
+  if (ws_bytes < need)
+    return fail(PID_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Extras x = carve_extras(workspace, need - extra_bytes(ens->n), ens->n);
+  if (ens->flags & PID_FLAG_VALIDATE) {
+    s = run_validate(ens, kind, x.flag, st);
+    if (s != PID_OK) return s;
+  }
+  pid_out o = *out;
+  o.inclusion = nullptr;
+  const bool want_rank = o.rank || o.order;
+  if (want_rank && !o.depth) o.depth = x.depth;
+  hipError_t err = pidk::launch_pid_mean_weighted(*ens, kind, make_extract(iso), member_w, o, workspace, st);
+  if (err != hipSuccess) return hip_fail(err, "pid_mean_weighted launch");
+  if (want_rank) {
+    err = pidk::launch_rank(o.depth, ens->n, o.rank, o.order, st);
+    if (err != hipSuccess) return hip_fail(err, "rank launch");
+  }
+  return PID_OK;
+}
+
+pid_status pid_field_max(const pid_ensemble* ens, double* max_out, void* stream) {
+  int kind = 0;
+  pid_status s = check_ensemble(ens, nullptr, &kind);
+  if (s != PID_OK) return s;
+  if (!max_out) return fail(PID_ERR_INVALID_ARG, "max_out is NULL");
+  if ((reinterpret_cast<uintptr_t>(max_out) & 7) != 0) return fail(PID_ERR_INVALID_ARG, "max_out must be 8-byte aligned");
+  hipError_t err = pidk::launch_field_max(*ens, max_out, reinterpret_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "pid_field_max launch");
+  return PID_OK;
 }
 
 pid_status pid_extract(const pid_ensemble* ens, const pid_iso* iso, void* u_out, int out_dtype,

@@ -30,11 +30,16 @@ struct bf16_t { uint16_t bits; };
 //   STEP:  u = [side * (f - c) > 0].  For values that widen exactly to float,
 //          f > c  <=>  f > c_dn  (c_dn = largest float <= c) and
 //          f < c  <=>  f < c_up  (c_up = smallest float >= c).
+//   MODEL: with t = (f - c) * a,
+//          RAMP    (isovalue uniform on [c - h, c + h], a = side / (2h)):  clamp(t + 1/2, 0, 1)
+//          TENT    (level-centred map of width h, a = 1 / h):              max(0, 1 - |t|)
+//          DENSITY (normalised density, c = 0 here, a = 1 / normaliser):   clamp(t, 0, 1)
 struct Extract {
   int side;
   float cf, af;
   float c_dn, c_up;
   double cd, ad;
+  int model;
 };
 
 __device__ __forceinline__ float to_float(float v) { return v; }
@@ -76,6 +81,10 @@ __device__ __forceinline__ float extract_f(T raw, const Extract& e) {
   } else if constexpr (MODE == MODE_GAUSS) {
     if constexpr (FAST) return half_erfc_fast((f - e.cf) * e.af);
     else return 0.5f * erfcf((f - e.cf) * e.af);
+  } else if constexpr (MODE == MODE_MODEL) {
+    const float t = (f - e.cf) * e.af;
+    if (e.model == PID_ISO_TENT) return fmaxf(0.0f, 1.0f - fabsf(t));
+    return fminf(fmaxf(e.model == PID_ISO_RAMP ? t + 0.5f : t, 0.0f), 1.0f);
   } else {
     return (e.side > 0) ? (f > e.c_dn ? 1.0f : 0.0f) : (f < e.c_up ? 1.0f : 0.0f);
   }
@@ -88,6 +97,10 @@ __device__ __forceinline__ double extract_d(T raw, const Extract& e) {
     return f;
   } else if constexpr (MODE == MODE_GAUSS) {
     return 0.5 * erfc((f - e.cd) * e.ad);
+  } else if constexpr (MODE == MODE_MODEL) {
+    const double t = (f - e.cd) * e.ad;
+    if (e.model == PID_ISO_TENT) return fmax(0.0, 1.0 - fabs(t));
+    return fmin(fmax(e.model == PID_ISO_RAMP ? t + 0.5 : t, 0.0), 1.0);
   } else {
     return (e.side > 0) ? (f > e.cd ? 1.0 : 0.0) : (f < e.cd ? 1.0 : 0.0);
   }

@@ -418,7 +418,13 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
             else u = (AccE)extract_f<MODE, Tin, MT != MT_F32>(pv.v[g + e], a.ex);
             if (!rvalid) u = AccE(0);
             if (!full) u = (x0 + g + e < a.m) ? u : AccE(0);
-            if constexpr (WEIGHTED) { msum += (AccE)wv[g + e] * u; uv[e] = (AccE)sqrtf(wv[g + e]) * u; }
+            if constexpr (WEIGHTED) {
+              msum += (AccE)wv[g + e] * u;
+              // sqrt(w) in the accumulation precision: an FP32 root would
+              // carry its rounding into every FP64 product
+              if constexpr (sizeof(AccE) == 8) uv[e] = sqrt((double)wv[g + e]) * u;
+              else uv[e] = sqrtf(wv[g + e]) * u;
+            }
             else { msum += u; uv[e] = u; }
           }
           unsigned char* d4 = dst + (size_t)g * TR::EB;
@@ -1013,4 +1019,6 @@ bool gram_dispatch_f16(int mt, int mode, const GramArgs& ga, int maxt, int rows,
 bool gram_dispatch_bf16(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
 bool gram_dispatch_f64(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
 bool gram_dispatch_u8(int mt, int mode, const GramArgs& ga, int maxt, int rows, int grid, size_t lds, hipStream_t st);
+bool gram_dispatch_model(int dtype, int mt, const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
+                         hipStream_t st);
 }  // namespace pidk

@@ -12,6 +12,8 @@
 #include "pid_internal.h"
 #include "pid_timing.h"
 
+#include <type_traits>
+
 namespace pidk {
 
 struct BandArgs {
@@ -112,6 +114,10 @@ static void launch_bands_t(const BandArgs& a, int kind, const Extract& ex, hipSt
   switch (kind) {
     case PID_ISO_GAUSSIAN: hipLaunchKernelGGL((bands_kernel<T, MODE_GAUSS>), grid, 256, 0, st, a, ex); break;
     case PID_ISO_STEP: hipLaunchKernelGGL((bands_kernel<T, MODE_STEP>), grid, 256, 0, st, a, ex); break;
+    case PID_ISO_RAMP: case PID_ISO_TENT: case PID_ISO_DENSITY:
+      if constexpr (sizeof(T) >= 2 && !std::is_same<T, bf16_t>::value)
+        hipLaunchKernelGGL((bands_kernel<T, MODE_MODEL>), grid, 256, 0, st, a, ex);
+      break;
     default: hipLaunchKernelGGL((bands_kernel<T, MODE_NONE>), grid, 256, 0, st, a, ex); break;
   }
 }

@@ -265,7 +265,8 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
   const int grid = p.nsplit * p.ntiles_super;
   const int rows = (p.nsuper > 1) ? 64 * p.sb : 32 * p.sb;   // most rows a workgroup loads
   bool ok = false;
-  switch (e.dtype) {
+  if (mode == MODE_MODEL) ok = gram_dispatch_model(e.dtype, mt, ga, p.maxt, rows, grid, p.lds_bytes, st);
+  else switch (e.dtype) {
     case PID_F64: ok = gram_dispatch_f64(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
     case PID_F32: ok = gram_dispatch_f32(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;
     case PID_F16: ok = gram_dispatch_f16(mt, mode, ga, p.maxt, rows, grid, p.lds_bytes, st); break;

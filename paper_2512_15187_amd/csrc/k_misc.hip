@@ -5,6 +5,7 @@
 #include "pid_timing.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace pidk {
 
@@ -38,6 +39,9 @@ static void launch_extract_m(const pid_ensemble& e, int kind, const Extract& ex,
   switch (kind) {
     case PID_ISO_GAUSSIAN: launch_extract_t<T, MODE_GAUSS>(e, ex, out, odt, st); break;
     case PID_ISO_STEP: launch_extract_t<T, MODE_STEP>(e, ex, out, odt, st); break;
+    case PID_ISO_RAMP: case PID_ISO_TENT: case PID_ISO_DENSITY:
+      if constexpr (sizeof(T) >= 2 && !std::is_same<T, bf16_t>::value) launch_extract_t<T, MODE_MODEL>(e, ex, out, odt, st);
+      break;
     default: launch_extract_t<T, MODE_NONE>(e, ex, out, odt, st); break;
   }
 }
@@ -53,6 +57,56 @@ hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost
     case PID_BF16: launch_extract_m<bf16_t>(e, iso_kind, ex, u_out, out_dtype, st); break;
     default: launch_extract_m<uint8_t>(e, iso_kind, ex, u_out, out_dtype, st); break;
   }
+  return hipGetLastError();
+}
+
+// Largest stored value of the ensemble (NaN values skipped), e.g. the
+// normalising density of PID_ISO_DENSITY.  Doubles are mapped to unsigned
+// keys that order like the values, so one integer atomicMax per wave finds
+// the maximum (an order-independent, exact result); the key is decoded in
+// place at the end.
+__device__ __forceinline__ unsigned long long max_key(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ void field_max_init(unsigned long long* key) { *key = 0ull; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void field_max_kernel(const T* __restrict__ U, int64_t ld, int64_t n, int64_t m,
+                                                        unsigned long long* __restrict__ key) {
+  const int64_t tot = n * m;
+  unsigned long long k = 0ull;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / m, x = e - i * m;
+    const double v = to_double(U[i * ld + x]);
+    if (v == v) k = max(k, max_key(v));
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) k = max(k, (unsigned long long)__shfl_xor(k, o, 64));
+  if ((threadIdx.x & 63) == 0 && k) atomicMax(key, k);
+}
+
+__global__ void field_max_final(unsigned long long* key) {
+  const unsigned long long k = *key;
+  double v = __longlong_as_double(0x7ff8000000000000ll);   // NaN: no value that is not NaN
+  if (k) v = __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
+  *reinterpret_cast<double*>(key) = v;
+}
+
+hipError_t launch_field_max(const pid_ensemble& e, double* out, hipStream_t st) {
+  unsigned long long* key = reinterpret_cast<unsigned long long*>(out);
+  hipLaunchKernelGGL(field_max_init, 1, 1, 0, st, key);
+  const int64_t tot = e.n * e.m;
+  const int grid = (int)std::min<int64_t>((tot + 255) / 256, (int64_t)device_cu_count() * 16);
+  switch (e.dtype) {
+    case PID_F64: hipLaunchKernelGGL(field_max_kernel<double>, grid, 256, 0, st, (const double*)e.data, e.ld, e.n, e.m, key); break;
+    case PID_F32: hipLaunchKernelGGL(field_max_kernel<float>, grid, 256, 0, st, (const float*)e.data, e.ld, e.n, e.m, key); break;
+    case PID_F16: hipLaunchKernelGGL(field_max_kernel<f16>, grid, 256, 0, st, (const f16*)e.data, e.ld, e.n, e.m, key); break;
+    case PID_BF16: hipLaunchKernelGGL(field_max_kernel<bf16_t>, grid, 256, 0, st, (const bf16_t*)e.data, e.ld, e.n, e.m, key); break;
+    default: hipLaunchKernelGGL(field_max_kernel<uint8_t>, grid, 256, 0, st, (const uint8_t*)e.data, e.ld, e.n, e.m, key); break;
+  }
+  hipLaunchKernelGGL(field_max_final, 1, 1, 0, st, key);
   return hipGetLastError();
 }
 

@@ -26,6 +26,13 @@ namespace pidk {
 template <typename T>
 using ComputeT = typename std::conditional<sizeof(T) == 8, double, float>::type;
 
+// The piecewise-linear models (ramp, tent, density) are built for FP64, FP32
+// and FP16 fields.
+template <typename T>
+constexpr bool has_models() {
+  return std::is_same<T, double>::value || std::is_same<T, float>::value || std::is_same<T, f16>::value;
+}
+
 template <typename CT, typename T>
 __device__ __forceinline__ CT to_ct(T raw) {
   if constexpr (std::is_same<CT, double>::value) return to_double(raw);
@@ -909,7 +916,7 @@ static void launch_soft_t(const MeanPlan& p, const pid_ensemble& e, const Extrac
   KernelTimer tm("pidmean", st, /*by_launch=*/true);   // one kernel per call
   if (p.pipe_lb) {   // the plan picks the pipelined kernel only where it is instantiated
     if constexpr (MODE != MODE_STEP && !std::is_same<T, uint8_t>::value && !(sizeof(T) == 8 && MPW == 32) &&
-                  !(sizeof(T) == 2 && MODE == MODE_GAUSS) && MPW != 16) {
+                  !(sizeof(T) == 2 && (MODE == MODE_GAUSS || MODE == MODE_MODEL)) && MPW != 16) {
       constexpr int LB = (MPW == 4) ? 16 : (MPW == 8 ? 8 : 4);
       constexpr int NWM = (MPW == 32) ? 8 : 16;
       if (wtd)
@@ -975,7 +982,7 @@ template <typename T, int MODE>
 static void dispatch_mpw(const MeanPlan& p, const pid_ensemble& e, const Extract& ex, bool vec,
                          const void* sglob, void* part, hipStream_t st) {
   if (p.binary) {
-    if constexpr (MODE != MODE_GAUSS) {
+    if constexpr (MODE == MODE_NONE || MODE == MODE_STEP) {
       switch (p.mpw) {
         case 4: launch_bin_t<T, MODE, 4>(p, e, ex, vec, (const int*)sglob, (long long*)part, st); break;
         case 8: launch_bin_t<T, MODE, 8>(p, e, ex, vec, (const int*)sglob, (long long*)part, st); break;
@@ -998,6 +1005,9 @@ static void dispatch_mode(const MeanPlan& p, const pid_ensemble& e, int iso_kind
   switch (iso_kind) {
     case PID_ISO_GAUSSIAN: dispatch_mpw<T, MODE_GAUSS>(p, e, ex, vec, sglob, part, st); break;
     case PID_ISO_STEP: dispatch_mpw<T, MODE_STEP>(p, e, ex, vec, sglob, part, st); break;
+    case PID_ISO_RAMP: case PID_ISO_TENT: case PID_ISO_DENSITY:
+      if constexpr (has_models<T>()) dispatch_mpw<T, MODE_MODEL>(p, e, ex, vec, sglob, part, st);
+      break;
     default: dispatch_mpw<T, MODE_NONE>(p, e, ex, vec, sglob, part, st); break;
   }
 }
@@ -1034,6 +1044,8 @@ static void launch_colsum(const MeanPlan& p, const pid_ensemble& e, int iso_kind
     }
   } else if (iso_kind == PID_ISO_GAUSSIAN) {
     launch_colsum_g<T, MODE_GAUSS, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
+  } else if (iso_mode(iso_kind) == MODE_MODEL) {
+    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   } else if (iso_kind == PID_ISO_STEP) {
     launch_colsum_g<T, MODE_STEP, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   } else {
@@ -1142,10 +1154,14 @@ static void launch_linear_t(const pid_ensemble& e, int iso_kind, const Extract& 
                             void* coef, int tg, void* tpart, void* tbuf, double* part, hipStream_t st) {
   if (iso_kind == PID_ISO_GAUSSIAN) launch_colsum_g<T, MODE_GAUSS, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
   else if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
-  else launch_colsum_g<T, MODE_NONE, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
+  else if (iso_mode(iso_kind) == MODE_MODEL) {
+    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
+  } else launch_colsum_g<T, MODE_NONE, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
   if (iso_kind == PID_ISO_GAUSSIAN) dispatch_mpw<T, MODE_GAUSS>(p3, e, ex, vec, tbuf, part, st);
   else if (iso_kind == PID_ISO_STEP) dispatch_mpw<T, MODE_STEP>(p3, e, ex, vec, tbuf, part, st);
-  else dispatch_mpw<T, MODE_NONE>(p3, e, ex, vec, tbuf, part, st);
+  else if (iso_mode(iso_kind) == MODE_MODEL) {
+    if constexpr (has_models<T>()) dispatch_mpw<T, MODE_MODEL>(p3, e, ex, vec, tbuf, part, st);
+  } else dispatch_mpw<T, MODE_NONE>(p3, e, ex, vec, tbuf, part, st);
 }
 
 hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const ExtractHost& exh, const pid_out& out,
@@ -1193,6 +1209,109 @@ hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const Extrac
   hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, p3.grid, (int)e.n, red);
   hipLaunchKernelGGL(pairs_linear_ratios, (int)((e.n + 255) / 256), 256, 0, st, red, inin, (int)e.n, out.mass,
                      out.in_in, out.in_out, out.depth);
+  return hipGetLastError();
+}
+
+}  // namespace pidk
+
+namespace pidk {
+
+// ---------------------------------------------------------------------------
+// PID-mean against a reliability-weighted mean contour (Sec. 4.1, the
+// optional weighting of the point-wise mean):
+//   ubar = s_r / R,  s_r(x) = sum_j r_j u_j(x),  R = sum_j r_j,
+//   A_i = sum_x w u_i(x) s_r(x)  =>  u_i <_p ubar = A_i / (R m_i),
+//   m(ubar) = sum_j r_j m_j / R  =>  ubar <_p u_i = A_i / sum_j r_j m_j.
+// Two streaming passes: s_r into the workspace (the column-sum kernel with
+// the weights as coefficients), then m_i and A_i by the two-pass row kernel.
+
+template <typename CT>
+__global__ __launch_bounds__(256) void member_coef_kernel(const double* __restrict__ r, int n, CT* __restrict__ q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) q[i] = (CT)r[i];
+}
+
+// One block: R and sum_j r_j m_j by a fixed tree, then the ratios.  R <= 0
+// (no positive weight) gives zero depths.
+__global__ __launch_bounds__(256) void pidmean_weighted_ratios(const double* __restrict__ red,
+                                                               const double* __restrict__ r, int n,
+                                                               double* __restrict__ m_out,
+                                                               double* __restrict__ in_in,
+                                                               double* __restrict__ in_out,
+                                                               double* __restrict__ depth) {
+#pragma clang fp contract(off)
+  __shared__ double sr[256], sm[256];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int i = t; i < n; i += 256) {
+    a += r[i];
+    b += r[i] * red[i];
+  }
+  sr[t] = a;
+  sm[t] = b;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (t < o) { sr[t] += sr[t + o]; sm[t] += sm[t + o]; }
+    __syncthreads();
+  }
+  const double R = sr[0], Mq = sm[0];
+  for (int i = t; i < n; i += 256) {
+    const double mm = red[i], A = red[n + i];
+    const double ii = (mm > 0.0 && R > 0.0) ? A / (R * mm) : 0.0;
+    const double oo = (Mq > 0.0 && R > 0.0) ? A / Mq : 0.0;
+    if (m_out) m_out[i] = mm;
+    if (in_in) in_in[i] = ii;
+    if (in_out) in_out[i] = oo;
+    if (depth) depth[i] = ii < oo ? ii : oo;
+  }
+}
+
+template <typename T>
+static void launch_weighted_t(const pid_ensemble& e, int iso_kind, const Extract& ex, bool vec, const MeanPlan& p3,
+                              const void* coef, int tg, void* tpart, void* sbuf, double* part, hipStream_t st) {
+  if (iso_kind == PID_ISO_GAUSSIAN) launch_colsum_g<T, MODE_GAUSS, false, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
+  else if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, false, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
+  else if (iso_mode(iso_kind) == MODE_MODEL) {
+    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, false, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
+  } else launch_colsum_g<T, MODE_NONE, false, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
+  if (iso_kind == PID_ISO_GAUSSIAN) dispatch_mpw<T, MODE_GAUSS>(p3, e, ex, vec, sbuf, part, st);
+  else if (iso_kind == PID_ISO_STEP) dispatch_mpw<T, MODE_STEP>(p3, e, ex, vec, sbuf, part, st);
+  else if (iso_mode(iso_kind) == MODE_MODEL) {
+    if constexpr (has_models<T>()) dispatch_mpw<T, MODE_MODEL>(p3, e, ex, vec, sbuf, part, st);
+  } else dispatch_mpw<T, MODE_NONE>(p3, e, ex, vec, sbuf, part, st);
+}
+
+hipError_t launch_pid_mean_weighted(const pid_ensemble& e, int iso_kind, const ExtractHost& exh,
+                                    const double* member_w, const pid_out& out, void* ws, hipStream_t st) {
+  const MeanPlan p3 = rows_plan(e.n, e.m, e.dtype);
+  Carve c(ws);
+  void* coef = c.take<double>((size_t)e.n);
+  void* sbuf = c.take<double>((size_t)e.m);
+  const int tg = colsum_groups(e.n, e.m, elem_bytes_of(e.dtype));
+  void* tpart = c.take<double>((size_t)e.m * (size_t)tg);
+  double* part = c.take<double>((size_t)p3.grid * 2 * e.n);
+  double* red = c.take<double>((size_t)2 * e.n);
+  const int cg = (int)((e.n + 255) / 256);
+  if (e.dtype == PID_F64) hipLaunchKernelGGL(member_coef_kernel<double>, cg, 256, 0, st, member_w, (int)e.n, (double*)coef);
+  else hipLaunchKernelGGL(member_coef_kernel<float>, cg, 256, 0, st, member_w, (int)e.n, (float*)coef);
+  Extract ex = __builtin_bit_cast(Extract, exh);
+  const int eb = elem_bytes_of(e.dtype);
+  const bool vec = ((reinterpret_cast<uintptr_t>(e.data) & 15) == 0) && ((e.ld * eb) % 16 == 0) &&
+                   (e.weights == nullptr || (reinterpret_cast<uintptr_t>(e.weights) & 15) == 0);
+  switch (e.dtype) {
+    case PID_F64: launch_weighted_t<double>(e, iso_kind, ex, vec, p3, coef, tg, tpart, sbuf, part, st); break;
+    case PID_F32: launch_weighted_t<float>(e, iso_kind, ex, vec, p3, coef, tg, tpart, sbuf, part, st); break;
+    case PID_F16: launch_weighted_t<f16>(e, iso_kind, ex, vec, p3, coef, tg, tpart, sbuf, part, st); break;
+    case PID_BF16: launch_weighted_t<bf16_t>(e, iso_kind, ex, vec, p3, coef, tg, tpart, sbuf, part, st); break;
+    default: launch_weighted_t<uint8_t>(e, iso_kind, ex, vec, p3, coef, tg, tpart, sbuf, part, st); break;
+  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  KernelTimer tm("pidmean_finalize", st);
+  dim3 rgrid((unsigned)e.n, 2);
+  hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, p3.grid, (int)e.n, red);
+  hipLaunchKernelGGL(pidmean_weighted_ratios, 1, 256, 0, st, red, member_w, (int)e.n, out.mass, out.in_in,
+                     out.in_out, out.depth);
   return hipGetLastError();
 }
 

@@ -1,9 +1,16 @@
 // Stand-alone driver for hardware-counter runs (rocprofv3 --pmc), without
 // torch: it fills its inputs on the device and runs one of
-//   copy [R]   a plain copy of 1 GiB (reads 1 GiB, writes 1 GiB), R times:
-//              the calibration of the byte counters;
-//   both [R]   pid_both on N = 256 members x M = 262144 points (FP32 masks,
-//              FP16 MFMA Gram, inclusion matrix and both rankings), R times.
+//   copy [R]          a plain copy of 1 GiB (reads 1 GiB, writes 1 GiB), R times:
+//                     the calibration of the byte counters;
+//   both [R] [C]      pid_both on N = 256 members x M = 262144 points (FP32 masks,
+//                     FP16 MFMA Gram, inclusion matrix and both rankings), R times,
+//                     cycling over C resident copies of the masks (default 4, so
+//                     that every call reads them from HBM, not from the cache);
+//   fields [R]        the scalar-field workload, N = 128 FP32 fields on 128^3,
+//                     isovalue ~ N(0.5, 0.05^2): pid_all_pairs (FP16 MFMA), the
+//                     thresholded pid_all_pairs (INT8 MFMA) and pid_mean, R times each;
+//   mean3d [R]        pid_mean on N = 64 FP16 masks on 256^3 with FP32 point
+//                     weights, R times.
 // It prints one line per mode with the bytes or the status.
 #include <hip/hip_runtime.h>
 
@@ -26,6 +33,26 @@ __global__ void fill_kernel(float* u, size_t count) {
   h *= 2246822519u;
   h ^= h >> 13;
   u[i] = (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
+// Field-like values in [0.3, 0.7) (around the isovalue 0.5).
+__global__ void fill_field_kernel(float* u, size_t count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint32_t h = (uint32_t)i * 2654435761u + 12345u;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  u[i] = 0.3f + 0.4f * (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
+__global__ void fill_half_kernel(_Float16* u, size_t count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint32_t h = (uint32_t)i * 2654435761u + 777u;
+  h ^= h >> 16;
+  h *= 2246822519u;
+  u[i] = (_Float16)((float)(h >> 8) * (1.0f / 16777216.0f));
 }
 
 __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, size_t n4) {
@@ -56,61 +83,155 @@ int run_copy(int reps) {
   return 0;
 }
 
-int run_both(int reps) {
-  const int64_t n = 256, m = 262144;
-  float* U = nullptr;
-  if (!ok(hipMalloc(&U, (size_t)(n * m) * 4), "hipMalloc")) return 1;
-  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n * m + 255) / 256)), dim3(256), 0, 0, U, (size_t)(n * m));
+pid_ensemble ensemble(int64_t n, int64_t m, int dtype, const void* data, const float* w) {
   pid_ensemble e{};
   e.n = n;
   e.m = m;
   e.ld = m;
-  e.dtype = PID_F32;
-  e.data = U;
-  e.weights = nullptr;
+  e.dtype = dtype;
+  e.data = data;
+  e.weights = w;
+  return e;
+}
+
+struct Outs {
+  double* d = nullptr;
+  int32_t* r = nullptr;
+  pid_out pairs{}, mean{};
+  bool alloc(int64_t n) {
+    if (!ok(hipMalloc(&d, (size_t)(n * n + 8 * n) * 8), "hipMalloc") || !ok(hipMalloc(&r, (size_t)4 * n * 4), "hipMalloc"))
+      return false;
+    pairs = pid_out{d, d + n * n, d + n * n + n, d + n * n + 2 * n, d + n * n + 3 * n, r, r + n};
+    mean = pid_out{nullptr, d + n * n + 4 * n, d + n * n + 5 * n, d + n * n + 6 * n, d + n * n + 7 * n, r + 2 * n,
+                   r + 3 * n};
+    return true;
+  }
+  ~Outs() {
+    if (d) hipFree(d);
+    if (r) hipFree(r);
+  }
+};
+
+int run_both(int reps, int copies) {
+  const int64_t n = 256, m = 262144;
+  float* U = nullptr;
+  if (!ok(hipMalloc(&U, (size_t)(n * m) * 4 * copies), "hipMalloc")) return 1;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n * m * copies + 255) / 256)), dim3(256), 0, 0, U,
+                     (size_t)(n * m * copies));
   pid_iso iso{};
   iso.kind = PID_ISO_NONE;
   iso.side = 1;
+  pid_ensemble e0 = ensemble(n, m, PID_F32, U, nullptr);
   size_t wsb = 0;
-  if (pid_workspace_size(&e, &iso, 2, PID_GEMM_F16, &wsb) != PID_OK) {
+  if (pid_workspace_size(&e0, &iso, 2, PID_GEMM_F16, &wsb) != PID_OK) {
     fprintf(stderr, "workspace size: %s\n", pid_last_error());
     return 1;
   }
   void* ws = nullptr;
-  double* d = nullptr;
-  int32_t* r32 = nullptr;
-  if (!ok(hipMalloc(&ws, wsb), "hipMalloc") || !ok(hipMalloc(&d, (size_t)(n * n + 8 * n) * 8), "hipMalloc") ||
-      !ok(hipMalloc(&r32, (size_t)4 * n * 4), "hipMalloc"))
-    return 1;
-  pid_out po{d, d + n * n, d + n * n + n, d + n * n + 2 * n, d + n * n + 3 * n, r32, r32 + n};
-  pid_out mo{nullptr, d + n * n + 4 * n, d + n * n + 5 * n, d + n * n + 6 * n, d + n * n + 7 * n, r32 + 2 * n,
-             r32 + 3 * n};
+  Outs o;
+  if (!ok(hipMalloc(&ws, wsb), "hipMalloc") || !o.alloc(n)) return 1;
   for (int r = 0; r < reps; ++r) {
-    if (pid_both(&e, &iso, PID_GEMM_F16, &po, &mo, ws, wsb, nullptr) != PID_OK) {
+    pid_ensemble e = ensemble(n, m, PID_F32, U + (size_t)(r % copies) * n * m, nullptr);
+    if (pid_both(&e, &iso, PID_GEMM_F16, &o.pairs, &o.mean, ws, wsb, nullptr) != PID_OK) {
       fprintf(stderr, "pid_both: %s\n", pid_last_error());
       return 1;
     }
   }
   if (!ok(hipDeviceSynchronize(), "pid_both")) return 1;
-  printf("both: %d calls of pid_both, N=%lld M=%lld FP32, FP16 Gram\n", reps, (long long)n, (long long)m);
+  printf("both: %d calls of pid_both, N=%lld M=%lld FP32, FP16 Gram, %d copies of the masks\n", reps, (long long)n,
+         (long long)m, copies);
   hipFree(U);
   hipFree(ws);
-  hipFree(d);
-  hipFree(r32);
+  return 0;
+}
+
+int run_fields(int reps) {
+  const int64_t n = 128, m = 128 * 128 * 128;
+  float* F = nullptr;
+  if (!ok(hipMalloc(&F, (size_t)(n * m) * 4), "hipMalloc")) return 1;
+  hipLaunchKernelGGL(fill_field_kernel, dim3((unsigned)((n * m + 255) / 256)), dim3(256), 0, 0, F, (size_t)(n * m));
+  pid_ensemble e = ensemble(n, m, PID_F32, F, nullptr);
+  pid_iso gauss{PID_ISO_GAUSSIAN, 1, 0.5, 0.05};
+  pid_iso step{PID_ISO_STEP, 1, 0.5, 0.0};
+  size_t w1 = 0, w2 = 0, w3 = 0;
+  if (pid_workspace_size(&e, &gauss, 0, PID_GEMM_F16, &w1) != PID_OK ||
+      pid_workspace_size(&e, &step, 0, PID_GEMM_I8, &w2) != PID_OK ||
+      pid_workspace_size(&e, &gauss, 1, 0, &w3) != PID_OK) {
+    fprintf(stderr, "workspace size: %s\n", pid_last_error());
+    return 1;
+  }
+  const size_t wsb = w1 > w2 ? (w1 > w3 ? w1 : w3) : (w2 > w3 ? w2 : w3);
+  void* ws = nullptr;
+  Outs o;
+  if (!ok(hipMalloc(&ws, wsb), "hipMalloc") || !o.alloc(n)) return 1;
+  for (int r = 0; r < reps; ++r) {
+    if (pid_all_pairs(&e, &gauss, PID_GEMM_F16, &o.pairs, ws, wsb, nullptr) != PID_OK ||
+        pid_all_pairs(&e, &step, PID_GEMM_I8, &o.pairs, ws, wsb, nullptr) != PID_OK ||
+        pid_mean(&e, &gauss, &o.mean, ws, wsb, nullptr) != PID_OK) {
+      fprintf(stderr, "fields: %s\n", pid_last_error());
+      return 1;
+    }
+  }
+  if (!ok(hipDeviceSynchronize(), "fields")) return 1;
+  printf("fields: %d x (FP16 all-pairs, INT8 all-pairs, PID-mean), N=%lld M=%lld FP32 fields\n", reps,
+         (long long)n, (long long)m);
+  hipFree(F);
+  hipFree(ws);
+  return 0;
+}
+
+int run_mean3d(int reps) {
+  const int64_t n = 64, m = (int64_t)256 * 256 * 256;
+  _Float16* U = nullptr;
+  float* w = nullptr;
+  if (!ok(hipMalloc(&U, (size_t)(n * m) * 2), "hipMalloc") || !ok(hipMalloc(&w, (size_t)m * 4), "hipMalloc")) return 1;
+  hipLaunchKernelGGL(fill_half_kernel, dim3((unsigned)((n * m + 255) / 256)), dim3(256), 0, 0, U, (size_t)(n * m));
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, 0, w, (size_t)m);
+  pid_ensemble e = ensemble(n, m, PID_F16, U, w);
+  pid_iso iso{PID_ISO_NONE, 1, 0.0, 0.0};
+  size_t wsb = 0;
+  if (pid_workspace_size(&e, &iso, 1, 0, &wsb) != PID_OK) {
+    fprintf(stderr, "workspace size: %s\n", pid_last_error());
+    return 1;
+  }
+  void* ws = nullptr;
+  Outs o;
+  if (!ok(hipMalloc(&ws, wsb), "hipMalloc") || !o.alloc(n)) return 1;
+  for (int r = 0; r < reps; ++r) {
+    if (pid_mean(&e, &iso, &o.mean, ws, wsb, nullptr) != PID_OK) {
+      fprintf(stderr, "pid_mean: %s\n", pid_last_error());
+      return 1;
+    }
+  }
+  if (!ok(hipDeviceSynchronize(), "mean3d")) return 1;
+  printf("mean3d: %d calls of pid_mean, N=%lld M=%lld FP16 + FP32 weights\n", reps, (long long)n, (long long)m);
+  hipFree(U);
+  hipFree(w);
+  hipFree(ws);
   return 0;
 }
 
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc < 2 || (strcmp(argv[1], "copy") != 0 && strcmp(argv[1], "both") != 0)) {
-    fprintf(stderr, "usage: %s copy|both [reps]\n", argv[0]);
+  const char* modes[] = {"copy", "both", "fields", "mean3d"};
+  int mode = -1;
+  for (int k = 0; k < 4; ++k)
+    if (argc >= 2 && strcmp(argv[1], modes[k]) == 0) mode = k;
+  if (mode < 0) {
+    fprintf(stderr, "usage: %s copy|both|fields|mean3d [reps] [copies]\n", argv[0]);
     return 2;
   }
   const int reps = argc > 2 ? atoi(argv[2]) : 3;
-  if (reps < 1 || reps > 1000) {
-    fprintf(stderr, "reps must be 1..1000\n");
+  const int copies = argc > 3 ? atoi(argv[3]) : 4;
+  if (reps < 1 || reps > 1000 || copies < 1 || copies > 8) {
+    fprintf(stderr, "reps must be 1..1000, copies 1..8\n");
     return 2;
   }
-  return strcmp(argv[1], "copy") == 0 ? run_copy(reps) : run_both(reps);
+  switch (mode) {
+    case 0: return run_copy(reps);
+    case 1: return run_both(reps, copies);
+    case 2: return run_fields(reps);
+    default: return run_mean3d(reps);
+  }
 }

@@ -13,7 +13,8 @@ struct Extract;  // device_common.h
 
 // How a stored value becomes a membership probability (compile-time mode of
 // every loader; Sec. 3.5).
-enum Mode { MODE_NONE = 0, MODE_GAUSS = 1, MODE_STEP = 2 };
+enum Mode { MODE_NONE = 0, MODE_GAUSS = 1, MODE_STEP = 2,
+            MODE_MODEL = 3 };   // MODEL: the piecewise-linear models (ramp, tent, density)
 int iso_mode(int iso_kind);
 int elem_bytes_of(int dtype);
 
@@ -23,6 +24,7 @@ struct ExtractHost {
   float cf, af;
   float c_dn, c_up;
   double cd, ad;
+  int model;   // PID_ISO_RAMP / TENT / DENSITY under MODE_MODEL
 };
 
 // Bump allocator over the caller's workspace (256-byte aligned pieces).
@@ -62,6 +64,10 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
 size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m);
 hipError_t launch_pid_mean(const MeanPlan& p, const pid_ensemble& e, int iso_kind,
                            const ExtractHost& ex, const pid_out& out, void* ws, hipStream_t st);
+// PID-mean against a mean contour weighted by member_w (N device doubles).
+size_t mean_weighted_workspace(int64_t n, int64_t m, int dtype);
+hipError_t launch_pid_mean_weighted(const pid_ensemble& e, int iso_kind, const ExtractHost& ex,
+                                    const double* member_w, const pid_out& out, void* ws, hipStream_t st);
 // Member groups of a column-sum pass; the two-pass row plan of the all-pairs
 // depths without the matrix.
 int colsum_groups(int64_t n, int64_t m, int eb);
@@ -115,6 +121,8 @@ hipError_t launch_rank2(const double* d0, int32_t* rank0, int32_t* order0, const
 // Contour-boxplot bands: one byte per point (pid_bands).
 hipError_t launch_bands(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, const int32_t* order,
                         int64_t k_inner, int64_t k_outer, double threshold, uint8_t* out, hipStream_t st);
+// Largest stored value (NaN skipped) into *out (device).
+hipError_t launch_field_max(const pid_ensemble& e, double* out, hipStream_t st);
 // Writes 0 to *flag_dev when all values pass, else a nonzero code.
 hipError_t launch_validate(const pid_ensemble& e, int iso_kind, unsigned int* flag_dev, hipStream_t st);
 

@@ -60,12 +60,19 @@ int iso_mode(int iso_kind) {
   switch (iso_kind) {
     case PID_ISO_GAUSSIAN: return MODE_GAUSS;
     case PID_ISO_STEP: return MODE_STEP;
+    case PID_ISO_RAMP: case PID_ISO_TENT: case PID_ISO_DENSITY: return MODE_MODEL;
     default: return MODE_NONE;
   }
 }
 
 // (input dtype, MFMA type, extraction mode) combinations that are built.
 bool gram_supported(int dtype, int mt, int mode) {
+  if (mode == MODE_MODEL) {   // fields: FP16 MFMA, the accurate BF16 split, the VALU comparators
+    if (dtype == PID_F32) return mt == MT_F16 || mt == MT_BF16X3 || mt == MT_F32;
+    if (dtype == PID_F16) return mt == MT_F16 || mt == MT_F32;
+    if (dtype == PID_F64) return mt == MT_F64;
+    return false;
+  }
   switch (dtype) {
     case PID_F32:
       if (mt == MT_I8) return mode == MODE_STEP;
@@ -198,7 +205,7 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   // and the addressing fit without spills.  It needs one full tile; rows
   // that are not aligned take the kernel below.
   const bool soft = !p.binary && dtype != PID_U8 &&
-                    (iso_kind == PID_ISO_NONE || (iso_kind == PID_ISO_GAUSSIAN && eb != 2));
+                    (iso_kind == PID_ISO_NONE || (iso_kind != PID_ISO_STEP && eb != 2));
   if (soft) {
     int mpw = 0;
     if (n <= 32) mpw = 4;
@@ -312,6 +319,19 @@ size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, boo
   c.take<double>((size_t)m * (size_t)colsum_groups(n, m, elem_bytes_of(dtype)));   // member-group partials of t
   c.take<double>((size_t)p3.grid * 2 * n);       // row partials
   c.take<double>((size_t)2 * n);                 // reduced m, B
+  return c.off + 256;
+}
+
+// Reliability-weighted PID-mean: the same pieces, in the same order, as
+// launch_pid_mean_weighted carves.
+size_t mean_weighted_workspace(int64_t n, int64_t m, int dtype) {
+  const MeanPlan p = rows_plan(n, m, dtype);
+  Carve c(nullptr);
+  c.take<double>((size_t)n);                                          // coefficients
+  c.take<double>((size_t)m);                                          // s_r(x)
+  c.take<double>((size_t)m * (size_t)colsum_groups(n, m, elem_bytes_of(dtype)));   // its member-group partials
+  c.take<double>((size_t)p.grid * 2 * n);                             // row partials
+  c.take<double>((size_t)2 * n);                                      // reduced m, A
   return c.off + 256;
 }
 

@@ -63,13 +63,13 @@ static void rejects() {
   bad([](pid_ensemble&) {}, pid_iso{PID_ISO_STEP, 1, std::nan(""), 0.0}, "finite");
   bad([](pid_ensemble&) {}, pid_iso{PID_ISO_STEP, 1, INFINITY, 0.0}, "finite");
   for (const Case& c : cases) {
-    for (int variant = 0; variant < 4; ++variant) {
+    for (int variant = 0; variant < 5; ++variant) {
       const pid_status s = pid_workspace_size(&c.e, &c.iso, variant, PID_GEMM_AUTO, &b);
       CHECK(s == PID_ERR_INVALID_ARG);
       CHECK(std::strstr(pid_last_error(), c.msg) != nullptr);
     }
   }
-  CHECK(pid_workspace_size(&e, &none, 4, 0, &b) == PID_ERR_INVALID_ARG);
+  CHECK(pid_workspace_size(&e, &none, 5, 0, &b) == PID_ERR_INVALID_ARG);
   CHECK(pid_workspace_size(&e, &none, -1, 0, &b) == PID_ERR_INVALID_ARG);
   CHECK(pid_workspace_size(&e, &none, 0, 42, &b) == PID_ERR_INVALID_ARG);
   CHECK(pid_workspace_size(&e, &none, 0, PID_GEMM_I8, &b) == PID_ERR_INVALID_ARG);   // not binary
@@ -111,7 +111,8 @@ static void plans() {
                         32768, 32769, 100000, INT64_C(1) << 22, INT64_C(1) << 30};
   const int64_t ms[] = {1, 2, 7, 16, 1000, 4096, 65537, INT64_C(1) << 20, INT64_C(1) << 24,
                         INT64_C(1) << 28, (INT64_C(1) << 31) + 5, INT64_C(1) << 40};
-  const pid_iso isos[] = {{PID_ISO_NONE, 1, 0, 0}, {PID_ISO_GAUSSIAN, 1, 0.5, 0.05}, {PID_ISO_STEP, -1, 0.5, 0}};
+  const pid_iso isos[] = {{PID_ISO_NONE, 1, 0, 0}, {PID_ISO_GAUSSIAN, 1, 0.5, 0.05}, {PID_ISO_STEP, -1, 0.5, 0},
+                          {PID_ISO_RAMP, 1, 0.5, 0.1}, {PID_ISO_TENT, 0, 0.5, 0.1}, {PID_ISO_DENSITY, 0, 2.0, 0}};
   int ok = 0, refused = 0;
   for (int64_t n : ns)
     for (int64_t m : ms)
@@ -119,7 +120,7 @@ static void plans() {
         for (const pid_iso& iso : isos)
           for (int wtd = 0; wtd < 2; ++wtd) {
             pid_ensemble e = ens(n, m, dt, (const void*)0x1000, wtd ? (const float*)0x2000 : nullptr);
-            for (int variant = 0; variant < 4; ++variant)
+            for (int variant = 0; variant < 5; ++variant)
               for (int g = 0; g <= 6; ++g) {
                 if (variant != 0 && variant != 2 && g) continue;
                 size_t b = 0;

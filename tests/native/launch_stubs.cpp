@@ -23,4 +23,7 @@ hipError_t launch_rank2(const double*, int32_t*, int32_t*, const double*, int32_
 hipError_t launch_bands(const pid_ensemble&, int, const ExtractHost&, const int32_t*, int64_t, int64_t, double,
                         uint8_t*, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_validate(const pid_ensemble&, int, unsigned int*, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_pid_mean_weighted(const pid_ensemble&, int, const ExtractHost&, const double*, const pid_out&,
+                                    void*, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_field_max(const pid_ensemble&, double*, hipStream_t) { return hipErrorNotSupported; }
 }  // namespace pidk

@@ -24,7 +24,8 @@ def test_exports_every_declared_symbol():
                 "pid_server_destroy", "pid_status_string", "pid_last_error", "pid_abi_version",
                 "pid_timing_enable", "pid_timing_get", "pid_timing_select",
                 "pid_timing_sample", "pid_bands", "pid_server_set_budget", "pid_server_clock",
-                "pid_request_device_times", "pid_release"}
+                "pid_request_device_times", "pid_release", "pid_mean_weighted", "pid_field_max",
+                "pid_both_static"}
     assert expected <= set(names), set(names)
     for n in names:
         assert hasattr(lib, n), n
@@ -76,7 +77,7 @@ def test_scheme_checks_on_host():
     # unknown scheme / variant
     assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 0, 42, ctypes.byref(nbytes)) \
         == pid.PID_ERR_INVALID_ARG
-    assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 4, 0, ctypes.byref(nbytes)) \
+    assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 5, 0, ctypes.byref(nbytes)) \
         == pid.PID_ERR_INVALID_ARG
     # variant 3 (all-pairs depths without the matrix) is sized on the host
     assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(i), 3, 0, ctypes.byref(nbytes)) == pid.PID_OK
@@ -113,3 +114,40 @@ def test_bands_rejects_bad_arguments():
         assert lib.pid_bands(ctypes.byref(e), None, order, ki, ko, thr, out, None) == pid.PID_ERR_INVALID_ARG
     assert lib.pid_bands(ctypes.byref(e), None, None, 1, 4, 0.5, out, None) == pid.PID_ERR_INVALID_ARG
     assert lib.pid_bands(ctypes.byref(e), None, order, 1, 4, 0.5, None, None) == pid.PID_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("dtype,iso,status,msg", [
+    (pid.PID_F32, pid.pid_iso(pid.PID_ISO_RAMP, 1, 0.5, 0.0), pid.PID_ERR_INVALID_ARG, "sigma"),
+    (pid.PID_F32, pid.pid_iso(pid.PID_ISO_RAMP, 0, 0.5, 0.1), pid.PID_ERR_INVALID_ARG, "side"),
+    (pid.PID_F32, pid.pid_iso(pid.PID_ISO_TENT, 1, 0.5, float("inf")), pid.PID_ERR_INVALID_ARG, "sigma"),
+    (pid.PID_F32, pid.pid_iso(pid.PID_ISO_DENSITY, 1, 0.0, 0.0), pid.PID_ERR_INVALID_ARG, "normalising"),
+    (pid.PID_F32, pid.pid_iso(pid.PID_ISO_DENSITY, 1, -2.0, 0.0), pid.PID_ERR_INVALID_ARG, "normalising"),
+    (pid.PID_U8, pid.pid_iso(pid.PID_ISO_TENT, 1, 0.5, 0.1), pid.PID_ERR_UNSUPPORTED, "F64, F32 or F16"),
+    (pid.PID_BF16, pid.pid_iso(pid.PID_ISO_RAMP, 1, 0.5, 0.1), pid.PID_ERR_UNSUPPORTED, "F64, F32 or F16"),
+    (pid.PID_F32, pid.pid_iso(6, 1, 0.5, 0.1), pid.PID_ERR_INVALID_ARG, "unknown iso kind"),
+])
+def test_model_arguments_rejected_on_host(dtype, iso, status, msg):
+    lib = _lib()
+    e = _ens(dtype=dtype)
+    nbytes = ctypes.c_size_t(0)
+    for variant in (0, 1, 3, 4):
+        assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(iso), variant, 0, ctypes.byref(nbytes)) == status
+        assert msg in lib.pid_last_error().decode()
+
+
+def test_model_and_weighted_variants_sized_on_host():
+    lib = _lib()
+    nbytes = ctypes.c_size_t(0)
+    for kind, side, sigma in ((pid.PID_ISO_RAMP, -1, 0.1), (pid.PID_ISO_TENT, 0, 0.1), (pid.PID_ISO_DENSITY, 0, 0.0)):
+        iso = pid.pid_iso(kind, side, 0.5, sigma)
+        for dtype in (pid.PID_F32, pid.PID_F16, pid.PID_F64):
+            e = _ens(dtype=dtype)
+            for variant in (0, 1, 2, 3, 4):
+                assert lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(iso), variant, 0,
+                                              ctypes.byref(nbytes)) == pid.PID_OK
+    # the weighted call checks its pointers before anything is launched
+    e, i, o = _ens(), pid.pid_iso(0, 1, 0.0, 0.0), pid.pid_out()
+    assert lib.pid_mean_weighted(ctypes.byref(e), ctypes.byref(i), None, ctypes.byref(o), ctypes.c_void_p(0x10),
+                                 1 << 20, None) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_field_max(ctypes.byref(e), None, None) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_field_max(ctypes.byref(e), ctypes.c_void_p(0x1004), None) == pid.PID_ERR_INVALID_ARG

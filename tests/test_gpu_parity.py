@@ -136,6 +136,7 @@ PAIR_CASES = [
     (70, 2049, torch.float32, True, "f32"),
     (100, 3000, torch.float32, False, "bf16"),
     (130, 1000, torch.float64, False, "f64"),
+    (40, 1500, torch.float64, True, "f64"),
     (256, 4096, torch.float16, False, "f16"),
     (230, 3333, torch.float16, True, "f16"),
     (300, 2000, torch.float32, False, "f16"),
