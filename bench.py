@@ -274,6 +274,7 @@ def headline(args):
     if not args.no_extras:
         extra.update(side_measurements(pid, torch, np, synth, U, args, ref if cpu else None))
         extra["serving"] = serving_leg(pid, torch, synth, args.serve_requests)
+        extra["sweep_sec52"] = sweep_rows(pid, torch, synth, SWEEP_SHAPES)
 
     line = {
         "metric": METRIC, "value": n * n * m / t_step, "unit": "pair*points/s", "n_gpus": 1,
@@ -540,34 +541,68 @@ def copy_calibration(args):
                       "copy_GBps_read_plus_write": 2 * (1 << 30) / t / 1e9}), flush=True)
 
 
+# The paper's own GPU PID-mean timings on the same shapes (RTX 4080 Super; the
+# paper does not say what they include), seconds, Sec. 5.2.
+PAPER_SWEEP_GPU_S = {(10000, 50): 1.23, (20000, 50): 2.00, (50, 256): 2.36, (50, 352): 5.50}
+
+
+def sweep_rows(pid, torch, synth, shapes, reps=5):
+    """PID-mean of binary 3D ellipsoid ensembles (Sec. 5.2: 80 % normal, 20 %
+    outlying members) as U8 masks and bit-packed (one bit per voxel), inputs
+    resident in HBM; the results of the two layouts are compared bit for bit."""
+    rows = []
+    for n, res in shapes:
+        U = synth.ellipsoids_3d(n, res, synth.BASE_SEED + 7 + n + res, device="cuda:0")
+        m = res ** 3
+        row = {"n": n, "res": res}
+        for layout in ("u8", "packed"):
+            if layout == "packed":
+                P = pid.pid_pack_bits(U)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pid.pid_pack_bits(U, out=P.words)
+                torch.cuda.synchronize()
+                row["pack_ms"] = round((time.perf_counter() - t0) * 1e3, 4)
+                src = P
+            else:
+                src = U
+            call = pid.PreparedCall("mean", src)
+            t = timed(call.run, reps, 2, torch)
+            pid.pid_timing_enable(True)
+            timed(call.run, reps, 0, torch)
+            kern = sum(kernel_ms(pid, k)[0] if kernel_ms(pid, k)[1] else 0.0
+                       for k in ("pidmean_colsum", "pidmean", "pidmean_finalize"))
+            pid.pid_timing_enable(False)
+            nbytes = n * m if layout == "u8" else n * ((m + 31) // 32) * 4
+            row[layout] = {"call_ms": round(t * 1e3, 4), "kernels_ms": round(kern, 4),
+                           "member_voxels_per_s": n * m / t, "mask_GBps": nbytes / t / 1e9}
+            row[layout + "_depth"] = call.out["depth"].clone()
+            del call
+        row["bitwise_equal"] = bool(torch.equal(row.pop("u8_depth"), row.pop("packed_depth")))
+        if (n, res) in PAPER_SWEEP_GPU_S:
+            row["paper_gpu_s"] = PAPER_SWEEP_GPU_S[(n, res)]
+        log(f"sweep N={n} {res}^3: U8 {row['u8']['call_ms']:.3f} ms, packed {row['packed']['call_ms']:.3f} ms "
+            f"(pack {row['pack_ms']:.3f} ms), equal={row['bitwise_equal']}")
+        rows.append(row)
+        del U, P, src
+        torch.cuda.empty_cache()
+    return rows
+
+
+SWEEP_SHAPES = [(n, 50) for n in (100, 1000, 10000, 20000, 40000)] + \
+               [(50, r) for r in (128, 192, 256, 352, 512)]
+
+
 def sweep(args):
-    """The shapes of the paper's scalability study (Sec. 5.2): binary 3D
-    ellipsoid ensembles (80 % normal, 20 % outliers) as U8 masks, PID-mean by
-    the exact integer path; N from 100 to 40,000 at 50^3 voxels, and 128^3 to
-    512^3 voxels at N = 50.  Inputs resident in HBM; one JSON line."""
+    """The shapes of the paper's scalability study (Sec. 5.2): N from 100 to
+    40,000 at 50^3 voxels, and 128^3 to 512^3 voxels at N = 50; one JSON line."""
     import torch
     import paper_2512_15187_amd as pid
     import synth
-    dev = "cuda:0"
-    rows = []
-    shapes = [(n, 50) for n in (100, 1000, 10000, 20000, 40000)] + \
-             [(50, r) for r in (128, 192, 256, 352, 512)]
-    for n, res in shapes:
-        U = synth.ellipsoids_3d(n, res, synth.BASE_SEED + 7 + n + res, device=dev)
-        m = res ** 3
-        call = pid.PreparedCall("mean", U)
-        t = timed(call.run, 5, 2, torch)
-        pid.pid_timing_enable(True)
-        timed(call.run, 5, 0, torch)
-        kern = kernel_ms(pid, "pidmean")[0] + kernel_ms(pid, "pidmean_finalize")[0]
-        pid.pid_timing_enable(False)
-        rows.append({"n": n, "res": res, "call_ms": round(t * 1e3, 4), "kernels_ms": round(kern, 4),
-                     "member_voxels_per_s": n * m / t, "GBps_u8_masks": n * m / t / 1e9})
-        log(f"sweep N={n} {res}^3: {t * 1e3:.3f} ms per call ({n * m / t / 1e9:.0f} GB/s of U8 masks)")
-        del call, U
-        torch.cuda.empty_cache()
+    rows = sweep_rows(pid, torch, synth, SWEEP_SHAPES)
     print(json.dumps({"metric": "PID-mean on binary 3D ellipsoid ensembles (Sec. 5.2 shapes)",
-                      "unit": "ms per call", "dtype": "u8", "data": "synthetic", "rows": rows}), flush=True)
+                      "unit": "ms per call", "dtype": "u8 / packed bits", "data": "synthetic", "rows": rows}),
+          flush=True)
 
 
 def main():

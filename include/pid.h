@@ -59,7 +59,13 @@ typedef enum {
 /* Element type of the stored ensemble. */
 typedef enum {
   PID_F64 = 0, PID_F32 = 1, PID_F16 = 2, PID_BF16 = 3,
-  PID_U8 = 4   /* binary masks: every value must be 0 or 1 */
+  PID_U8 = 4,  /* binary masks: every value must be 0 or 1 */
+  PID_B1 = 5   /* bit-packed binary masks: point x of row i is bit (i*ld + x) mod 32 of
+                  32-bit word (i*ld + x) / 32 (little-endian, so bit x mod 8 of byte x / 8 of
+                  the row); ld (in points) a multiple of 32, data 4-byte aligned; bits past m
+                  are ignored.  Taken by pid_mean (exact integers, no weights, PID_ISO_NONE)
+                  and produced from U8 masks by pid_pack_bits; the other calls return
+                  PID_ERR_UNSUPPORTED for it */
 } pid_dtype;
 
 /* How stored values become membership probabilities (Sec. 3.5, 3.6, 6.3). */
@@ -191,6 +197,14 @@ pid_status pid_mean(const pid_ensemble* ens, const pid_iso* iso, const pid_out* 
  * Unit weights give the values of pid_mean within its tolerance. */
 pid_status pid_mean_weighted(const pid_ensemble* ens, const pid_iso* iso, const double* member_w,
                              const pid_out* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Packs U8 0/1 masks (ens: dtype PID_U8, any row stride) into PID_B1 rows:
+ * row i of `out` (device, 4-byte aligned) starts at 32-bit word i * out_ld / 32,
+ * out_ld (in points) a multiple of 32 and >= m; the words past the last one
+ * that holds points are left untouched.  A nonzero byte counts as 1.  One
+ * launch, asynchronous on `stream`.  Bit-packed masks hold one bit per point,
+ * an eighth of the U8 bytes, for the binary ensembles of Sec. 5.2 and 6.2. */
+pid_status pid_pack_bits(const pid_ensemble* ens, void* out, int64_t out_ld, void* stream);
 
 /* Largest stored value of the ensemble (values that are NaN are skipped; NaN
  * if every value is), written as one double to the device pointer max_out

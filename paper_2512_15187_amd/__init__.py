@@ -25,7 +25,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pid.h")
 # ---- enums (mirror include/pid.h) ----
 PID_OK, PID_ERR_INVALID_ARG, PID_ERR_UNSUPPORTED, PID_ERR_WORKSPACE_TOO_SMALL = 0, 1, 2, 3
 PID_ERR_DEVICE, PID_ERR_VALUE_RANGE, PID_ERR_OVER_BUDGET, PID_ERR_CANCELLED, PID_ERR_INTERNAL = 4, 5, 6, 7, 8
-PID_F64, PID_F32, PID_F16, PID_BF16, PID_U8 = 0, 1, 2, 3, 4
+PID_F64, PID_F32, PID_F16, PID_BF16, PID_U8, PID_B1 = 0, 1, 2, 3, 4, 5
 PID_ISO_NONE, PID_ISO_GAUSSIAN, PID_ISO_STEP, PID_ISO_RAMP, PID_ISO_TENT, PID_ISO_DENSITY = 0, 1, 2, 3, 4, 5
 GEMM = {"auto": 0, "f64": 1, "f32": 2, "f16": 3, "bf16": 4, "bf16_split": 5, "i8": 6}
 PID_FLAG_VALIDATE = 1
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "pid_pairs_depths": ([P(pid_ensemble), P(pid_iso), P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_mean_weighted": ([P(pid_ensemble), P(pid_iso), V, P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_field_max": ([P(pid_ensemble), V, V], I32),
+        "pid_pack_bits": ([P(pid_ensemble), V, I64, V], I32),
         "pid_both_static": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), P(pid_out), V], I32),
         "pid_both": ([P(pid_ensemble), P(pid_iso), I32, P(pid_out), P(pid_out), V, ctypes.c_size_t, V], I32),
         "pid_extract": ([P(pid_ensemble), P(pid_iso), V, I32, V], I32),
@@ -137,8 +138,29 @@ def _require_gpu(t: torch.Tensor, what: str):
         raise ValueError(f"{what} must be a device tensor")
 
 
-def make_ensemble(U: torch.Tensor, weights: torch.Tensor | None = None, validate: bool = False):
-    """Fill pid_ensemble from an N x M (row-strided) device tensor."""
+class PackedMasks:
+    """Bit-packed binary masks (PID_B1): ``words`` is an N x ldw int32 device
+    tensor (unit stride along a row) whose row i holds the bits of member i,
+    point x in bit x mod 32 of word x / 32; ``m`` is the number of points."""
+
+    def __init__(self, words: torch.Tensor, m: int):
+        if words.dtype != torch.int32 or words.dim() != 2 or words.stride(1) != 1:
+            raise ValueError("words must be a 2-D int32 tensor with unit stride along a row")
+        if not 1 <= m <= 32 * words.shape[1]:
+            raise ValueError("m must be between 1 and 32 * words.shape[1]")
+        self.words, self.m = words, int(m)
+        self.shape = (words.shape[0], self.m)
+        self.device = words.device
+
+
+def make_ensemble(U, weights: torch.Tensor | None = None, validate: bool = False):
+    """Fill pid_ensemble from an N x M (row-strided) device tensor or from
+    PackedMasks."""
+    if isinstance(U, PackedMasks):
+        _require_gpu(U.words, "words")
+        if weights is not None:
+            raise ValueError("bit-packed masks take no point weights")
+        return pid_ensemble(U.words.shape[0], U.m, 32 * U.words.stride(0), PID_B1, 0, U.words.data_ptr(), None)
     _require_gpu(U, "U")
     if U.dim() != 2 or U.stride(1) != 1:
         raise ValueError("U must be 2-D with unit stride along the points")
@@ -269,6 +291,29 @@ def pid_mean_weighted(U, member_weights, weights=None, iso=None, workspace=None,
                                  ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws_n.value, _stream_ptr(stream)))
     d["_workspace"] = ws
     return d
+
+
+def pid_pack_bits(U, out=None, stream=None) -> PackedMasks:
+    """Pack N x M uint8 0/1 device masks into PackedMasks (on the device).
+    ``out``: an N x ldw int32 device tensor to fill (unit stride along a row,
+    32 * ldw >= M; its words past the last one that holds points are left as
+    they are), else a new N x ceil(M / 32) one."""
+    lib = load_library()
+    e = make_ensemble(U)
+    if U.dtype != torch.uint8:
+        raise ValueError("pid_pack_bits packs uint8 0/1 masks")
+    m = U.shape[1]
+    if out is None:
+        words = torch.empty((U.shape[0], (m + 31) // 32), dtype=torch.int32, device=U.device)
+    else:
+        words = out
+        _require_gpu(words, "out")
+        if words.dtype != torch.int32 or words.dim() != 2 or words.stride(1) != 1 or words.shape[0] != U.shape[0] \
+                or 32 * words.shape[1] < m:
+            raise ValueError("out must be an N x ldw int32 tensor with unit row stride and 32 * ldw >= M")
+    ld = 32 * words.stride(0)
+    _check(lib.pid_pack_bits(ctypes.byref(e), ctypes.c_void_p(words.data_ptr()), ld, _stream_ptr(stream)))
+    return PackedMasks(words, m)
 
 
 def pid_field_max(U, stream=None):

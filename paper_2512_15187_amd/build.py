@@ -28,7 +28,7 @@ COMMON = [
     "-Wno-unused-command-line-argument",
 ]
 REPORT = os.path.join(OUT_DIR, "resource_usage.txt")
-SOURCES = ["k_gram_f32.hip", "k_gram_models.hip", "k_gram_f16.hip", "k_gram_f64u8.hip", "k_pidmean.hip", "k_gram.hip", "k_misc.hip", "k_bands.hip", "static_scratch.hip", "api.cpp", "plan.cpp", "server.cpp", "timing.cpp"]
+SOURCES = ["k_gram_f32.hip", "k_gram_models.hip", "k_gram_f16.hip", "k_gram_f64u8.hip", "k_pidmean.hip", "k_gram.hip", "k_misc.hip", "k_bands.hip", "k_bits.hip", "static_scratch.hip", "api.cpp", "plan.cpp", "server.cpp", "timing.cpp"]
 
 
 def _compile(src: str):

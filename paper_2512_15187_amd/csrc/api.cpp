@@ -36,7 +36,7 @@ int elem_bytes(int dtype) {
     case PID_F64: return 8;
     case PID_F32: return 4;
     case PID_F16: case PID_BF16: return 2;
-    case PID_U8: return 1;
+    case PID_U8: case PID_B1: return 1;   // (B1: an upper bound, for the overflow check)
     default: return 0;
   }
 }
@@ -52,6 +52,12 @@ pid_status check_ensemble(const pid_ensemble* e, const pid_iso* iso, int* iso_ki
   if (e->ld > (int64_t(1) << 56) / e->n / eb) return fail(PID_ERR_INVALID_ARG, "n * ld overflows");
   if (!e->data) return fail(PID_ERR_INVALID_ARG, "data is NULL");
   if (e->flags & ~PID_FLAG_VALIDATE) return fail(PID_ERR_INVALID_ARG, "unknown flags 0x%x", e->flags);
+  if (e->dtype == PID_B1) {
+    if (e->ld % 32 != 0) return fail(PID_ERR_INVALID_ARG, "PID_B1 rows: ld (%lld) must be a multiple of 32", (long long)e->ld);
+    if ((reinterpret_cast<uintptr_t>(e->data) & 3) != 0) return fail(PID_ERR_INVALID_ARG, "PID_B1 data must be 4-byte aligned");
+    if (iso && iso->kind != PID_ISO_NONE) return fail(PID_ERR_UNSUPPORTED, "PID_B1 masks take PID_ISO_NONE only");
+    if (e->weights) return fail(PID_ERR_UNSUPPORTED, "PID_B1 masks take no weights (exact integer sums)");
+  }
   int kind = iso ? iso->kind : PID_ISO_NONE;
   if (kind < PID_ISO_NONE || kind > PID_ISO_DENSITY) return fail(PID_ERR_INVALID_ARG, "unknown iso kind %d", kind);
   if (kind != PID_ISO_NONE) {
@@ -184,7 +190,12 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
   if (s != PID_OK) return s;
   if (!bytes) return fail(PID_ERR_INVALID_ARG, "bytes is NULL");
   size_t kb = 0;
-  if (variant == 0) {
+  if (ens->dtype == PID_B1) {
+    if (variant != 1) return fail(PID_ERR_UNSUPPORTED, "PID_B1 masks are taken by pid_mean only");
+    const pidk::B1Plan p = pidk::b1_plan(ens->n, ens->m);
+    if (p.unsupported) return fail(PID_ERR_UNSUPPORTED, "n or m beyond the bit-packed launch limits");
+    kb = pidk::b1_workspace(p, ens->n);
+  } else if (variant == 0) {
     int scheme = 0;
     s = resolve_scheme(ens, kind, gemm, &scheme);
     if (s != PID_OK) return s;
@@ -280,7 +291,7 @@ pid_status run(int variant, const pid_ensemble* ens, const pid_iso* iso, int gem
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   size_t kb = need - extra_bytes(ens->n);
   Extras x = carve_extras(ws, kb, ens->n);
-  if (ens->flags & PID_FLAG_VALIDATE) {
+  if ((ens->flags & PID_FLAG_VALIDATE) && ens->dtype != PID_B1) {   // (every bit is a valid mask value)
     s = run_validate(ens, kind, x.flag, st);
     if (s != PID_OK) return s;
   }
@@ -297,6 +308,8 @@ pid_status run(int variant, const pid_ensemble* ens, const pid_iso* iso, int gem
   } else if (variant == 3) {
     o.inclusion = nullptr;
     err = pidk::launch_pairs_linear(*ens, kind, ex, o, ws, st);
+  } else if (ens->dtype == PID_B1) {
+    err = pidk::launch_b1_mean(*ens, o, ws, st);
   } else {
     pidk::MeanPlan p = pidk::mean_plan(ens->n, ens->m, ens->dtype, kind, ens->weights != nullptr);
     err = pidk::launch_pid_mean(p, *ens, kind, ex, o, ws, st);
@@ -371,11 +384,29 @@ pid_status pid_mean_weighted(const pid_ensemble* ens, const pid_iso* iso, const 
   return PID_OK;
 }
 
+pid_status pid_pack_bits(const pid_ensemble* ens, void* out, int64_t out_ld, void* stream) {
+  int kind = 0;
+  pid_status s = check_ensemble(ens, nullptr, &kind);
+  if (s != PID_OK) return s;
+  if (ens->dtype != PID_U8) return fail(PID_ERR_INVALID_ARG, "pid_pack_bits packs PID_U8 masks");
+  if (!out) return fail(PID_ERR_INVALID_ARG, "out is NULL");
+  if ((reinterpret_cast<uintptr_t>(out) & 3) != 0) return fail(PID_ERR_INVALID_ARG, "out must be 4-byte aligned");
+  if (out_ld < ens->m || out_ld % 32 != 0)
+    return fail(PID_ERR_INVALID_ARG, "out_ld (%lld) must be a multiple of 32 and >= m", (long long)out_ld);
+  if ((ens->m + 31) / 32 > (int64_t)INT32_MAX * 256 / ens->n)
+    return fail(PID_ERR_UNSUPPORTED, "n * m too large for one launch");
+  hipError_t err = pidk::launch_pack_bits(*ens, static_cast<uint32_t*>(out), out_ld / 32,
+                                          reinterpret_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "pid_pack_bits launch");
+  return PID_OK;
+}
+
 pid_status pid_field_max(const pid_ensemble* ens, double* max_out, void* stream) {
   int kind = 0;
   pid_status s = check_ensemble(ens, nullptr, &kind);
   if (s != PID_OK) return s;
   if (!max_out) return fail(PID_ERR_INVALID_ARG, "max_out is NULL");
+  if (ens->dtype == PID_B1) return fail(PID_ERR_UNSUPPORTED, "PID_B1 masks are taken by pid_mean only");
   if ((reinterpret_cast<uintptr_t>(max_out) & 7) != 0) return fail(PID_ERR_INVALID_ARG, "max_out must be 8-byte aligned");
   hipError_t err = pidk::launch_field_max(*ens, max_out, reinterpret_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "pid_field_max launch");
@@ -388,6 +419,7 @@ pid_status pid_extract(const pid_ensemble* ens, const pid_iso* iso, void* u_out,
   pid_status s = check_ensemble(ens, iso, &kind);
   if (s != PID_OK) return s;
   if (!u_out) return fail(PID_ERR_INVALID_ARG, "u_out is NULL");
+  if (ens->dtype == PID_B1) return fail(PID_ERR_UNSUPPORTED, "PID_B1 masks are taken by pid_mean only");
   if (out_dtype != PID_F32 && out_dtype != PID_F64)
     return fail(PID_ERR_INVALID_ARG, "out_dtype must be PID_F32 or PID_F64");
   hipError_t err = pidk::launch_extract(*ens, kind, make_extract(iso), u_out, out_dtype,
@@ -402,6 +434,7 @@ pid_status pid_bands(const pid_ensemble* ens, const pid_iso* iso, const int32_t*
   pid_status s = check_ensemble(ens, iso, &kind);
   if (s != PID_OK) return s;
   if (!order) return fail(PID_ERR_INVALID_ARG, "order is NULL");
+  if (ens->dtype == PID_B1) return fail(PID_ERR_UNSUPPORTED, "PID_B1 masks are taken by pid_mean only");
   if (!out) return fail(PID_ERR_INVALID_ARG, "out is NULL");
   if (k_inner < 1 || k_inner > k_outer || k_outer > ens->n)
     return fail(PID_ERR_INVALID_ARG, "need 1 <= k_inner <= k_outer <= n (got %lld, %lld, n = %lld)",

@@ -322,6 +322,35 @@ size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, boo
   return c.off + 256;
 }
 
+// Bit-packed binary PID-mean (k_bits.hip): groups of 255 members for the
+// column counts, KT planes for counts up to n, row tiles of 64 lanes x WPL
+// words (WPL = 4 up to 16 planes, 2 beyond), 64 members per block.
+B1Plan b1_plan(int64_t n, int64_t m) {
+  B1Plan p{};
+  p.W = (m + 31) / 32;
+  p.groups = (int)((n + 254) / 255);
+  p.chunk = (int)((n + p.groups - 1) / p.groups);
+  int bits = 1;
+  while (bits < 31 && (INT64_C(1) << bits) <= n) ++bits;   // bits of the largest count, n
+  p.kt = bits <= 8 ? 8 : (bits <= 16 ? 16 : 32);           // the row kernel's plane count
+  const int wpl = p.kt <= 16 ? 4 : 2;
+  p.ntiles = (int)std::min<int64_t>(INT32_MAX, (p.W + 64 * wpl - 1) / (64 * wpl));
+  p.mgroups = (int)((n + 63) / 64);
+  if (p.groups > kMaxGridY || p.mgroups > kMaxGridY || (p.W + 255) / 256 > INT32_MAX ||
+      (p.W + 64 * wpl - 1) / (64 * wpl) > INT32_MAX)
+    p.unsupported = 1;
+  return p;
+}
+
+size_t b1_workspace(const B1Plan& p, int64_t n) {
+  Carve c(nullptr);
+  c.take<uint32_t>((size_t)p.groups * 8 * p.W);                 // group count planes
+  c.take<uint32_t>((size_t)p.kt * p.W);                         // total count planes
+  c.take<long long>((size_t)2 * n * p.ntiles);                  // row partials
+  c.take<long long>((size_t)2 * n);                             // reduced m, S
+  return c.off + 256;
+}
+
 // Reliability-weighted PID-mean: the same pieces, in the same order, as
 // launch_pid_mean_weighted carves.
 size_t mean_weighted_workspace(int64_t n, int64_t m, int dtype) {

@@ -69,7 +69,8 @@ int dtype_bytes(int dtype) {
 // (its rows up to the last valid point), the weights and every output asked for.
 size_t request_bytes(const pid_request& r) {
   const pid_ensemble& e = r.ens;
-  size_t b = (size_t)((e.n - 1) * e.ld + e.m) * (size_t)dtype_bytes(e.dtype);
+  size_t b = e.dtype == PID_B1 ? (size_t)((e.n - 1) * e.ld + e.m + 7) / 8
+                               : (size_t)((e.n - 1) * e.ld + e.m) * (size_t)dtype_bytes(e.dtype);
   if (e.weights) b += (size_t)e.m * 4;
   const size_t n = (size_t)e.n;
   if (r.out.inclusion && r.variant == 0) b += n * n * 8;

@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
                 "pid_timing_enable", "pid_timing_get", "pid_timing_select",
                 "pid_timing_sample", "pid_bands", "pid_server_set_budget", "pid_server_clock",
                 "pid_request_device_times", "pid_release", "pid_mean_weighted", "pid_field_max",
-                "pid_both_static"}
+                "pid_both_static", "pid_pack_bits"}
     assert expected <= set(names), set(names)
     for n in names:
         assert hasattr(lib, n), n
@@ -151,3 +151,32 @@ def test_model_and_weighted_variants_sized_on_host():
                                  1 << 20, None) == pid.PID_ERR_INVALID_ARG
     assert lib.pid_field_max(ctypes.byref(e), None, None) == pid.PID_ERR_INVALID_ARG
     assert lib.pid_field_max(ctypes.byref(e), ctypes.c_void_p(0x1004), None) == pid.PID_ERR_INVALID_ARG
+
+
+def test_packed_masks_checked_on_host():
+    lib = _lib()
+    nbytes = ctypes.c_size_t(0)
+    none = pid.pid_iso(0, 1, 0.0, 0.0)
+
+    def ws(variant, iso=none, **kw):
+        e = _ens(**{"dtype": pid.PID_B1, "ld": 64, **kw})
+        return lib.pid_workspace_size(ctypes.byref(e), ctypes.byref(iso), variant, 0, ctypes.byref(nbytes))
+
+    assert ws(1) == pid.PID_OK and nbytes.value > 0
+    for variant in (0, 2, 3, 4):          # PID-mean only
+        assert ws(variant) == pid.PID_ERR_UNSUPPORTED
+    assert ws(1, ld=40) == pid.PID_ERR_INVALID_ARG and "multiple of 32" in lib.pid_last_error().decode()
+    assert ws(1, data=0x1002) == pid.PID_ERR_INVALID_ARG and "aligned" in lib.pid_last_error().decode()
+    assert ws(1, iso=pid.pid_iso(pid.PID_ISO_STEP, 1, 0.5, 0.0)) == pid.PID_ERR_UNSUPPORTED
+    assert ws(1, weights=0x2000) == pid.PID_ERR_UNSUPPORTED
+    # the packing call checks its source and destination before any launch
+    src = _ens(dtype=pid.PID_U8, m=100, ld=100)
+    assert lib.pid_pack_bits(ctypes.byref(src), None, 128, None) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_pack_bits(ctypes.byref(src), ctypes.c_void_p(0x1000), 96, None) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_pack_bits(ctypes.byref(src), ctypes.c_void_p(0x1000), 120, None) == pid.PID_ERR_INVALID_ARG
+    assert lib.pid_pack_bits(ctypes.byref(src), ctypes.c_void_p(0x1001), 128, None) == pid.PID_ERR_INVALID_ARG
+    f32 = _ens(m=100, ld=100)
+    assert lib.pid_pack_bits(ctypes.byref(f32), ctypes.c_void_p(0x1000), 128, None) == pid.PID_ERR_INVALID_ARG
+    # the other calls refuse packed masks
+    e = _ens(dtype=pid.PID_B1, ld=64)
+    assert lib.pid_field_max(ctypes.byref(e), ctypes.c_void_p(0x1000), None) == pid.PID_ERR_UNSUPPORTED

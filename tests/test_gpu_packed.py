@@ -1,0 +1,137 @@
+"""Bit-packed binary masks (one bit per grid point) on the GPU, through the C
+ABI: the packing layout against numpy's little-endian bit packing, PID-mean
+of packed masks bitwise against the oracle's exact integer form (Sec. 4.1
+with the binary reduction of Sec. 3.2) for every plane count of the column
+counter (8, 16 and 32 planes), several member groups, ragged words and padded
+rows, and, on the scalability shapes of Sec. 5.2 (3D ellipsoids, 80 % normal
+and 20 % outlying members), against the oracle where it fits in host memory
+and against the unpacked masks' path on the largest shapes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2512_15187_amd as pid
+import synth
+from tests.gpu_helpers import assert_bitwise, assert_ranks, np64
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+KEYS = ("mass", "in_in", "in_out", "depth")
+
+
+def _np_pack(B, ldw=None):
+    """N x M uint8 0/1 -> N x ldw int32 words, point x in bit x mod 32 of
+    word x / 32 (numpy's little-endian bit order); padding words are zero."""
+    n, m = B.shape
+    W = (m + 31) // 32
+    ldw = W if ldw is None else ldw
+    padded = np.zeros((n, 32 * ldw), dtype=np.uint8)
+    padded[:, :m] = B
+    return np.packbits(padded, axis=1, bitorder="little").view("<i4").reshape(n, ldw)
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (3, 31), (4, 32), (5, 33), (17, 1000), (9, 4096 + 5)])
+def test_pack_layout(n, m):
+    B = synth.random_binary(n, m, n * 7 + m)
+    P = pid.pid_pack_bits(B.to(DEV))
+    assert P.words.shape == (n, (m + 31) // 32)
+    assert np.array_equal(P.words.cpu().numpy(), _np_pack(B.numpy()))
+    # a strided U8 source and a padded destination: words past the row's last
+    # one are left as they were
+    wide = torch.zeros((n, m + 40), dtype=torch.uint8)
+    wide[:, 3:3 + m] = B
+    src = wide.to(DEV)[:, 3:3 + m]
+    W = (m + 31) // 32
+    dst = torch.full((n, W + 3), -7, dtype=torch.int32, device=DEV)
+    P2 = pid.pid_pack_bits(src, out=dst)
+    got = dst.cpu().numpy()
+    assert np.array_equal(got[:, :W], _np_pack(B.numpy()))
+    assert (got[:, W:] == -7).all()
+    assert P2.m == m
+
+
+MEAN_CASES = [
+    # (n, m): one word and ragged words; one group of 255 members (8 planes);
+    # 256 members (16 planes); several groups; 2^16 + members (32 planes)
+    (1, 1), (2, 31), (3, 33), (6, 64), (64, 1000), (255, 4099), (256, 4096), (300, 777),
+    (600, 10007), (4100, 700), (66000, 37),
+]
+
+
+@pytest.mark.parametrize("n,m", MEAN_CASES, ids=[f"{c[0]}x{c[1]}" for c in MEAN_CASES])
+def test_packed_mean_bitexact(n, m):
+    B = synth.random_binary(n, m, 100 + n)
+    ref = oracle.binary_pid_mean(B.numpy())
+    res = pid.pid_mean(pid.pid_pack_bits(B.to(DEV)))
+    assert_bitwise(res, ref, keys=KEYS, label=f"packed {n}x{m}")
+    assert_ranks(res["rank"], ref["depth"], 0)
+    # the same bits packed on the host into rows padded by two words
+    W = (m + 31) // 32
+    words = torch.from_numpy(_np_pack(B.numpy(), W + 2)).to(DEV)
+    res2 = pid.pid_mean(pid.PackedMasks(words, m))
+    assert_bitwise(res2, ref, keys=KEYS, label=f"host-packed {n}x{m}")
+
+
+def test_packed_degenerate():
+    # empty members and a zero ensemble: IN_in of an empty member is 0, and
+    # with no points set at all every ratio is 0
+    B = synth.random_binary(40, 500, 5)
+    B[[3, 17]] = 0
+    ref = oracle.binary_pid_mean(B.numpy())
+    res = pid.pid_mean(pid.pid_pack_bits(B.to(DEV)))
+    assert_bitwise(res, ref, keys=KEYS, label="empty members")
+    Z = torch.zeros((10, 100), dtype=torch.uint8)
+    z = pid.pid_mean(pid.pid_pack_bits(Z.to(DEV)))
+    assert (np64(z["depth"]) == 0).all() and (np64(z["mass"]) == 0).all()
+    # identical members: every depth is 1
+    O = synth.random_binary(1, 3000, 6).repeat(20, 1)
+    o = pid.pid_mean(pid.pid_pack_bits(O.to(DEV)))
+    assert (np64(o["depth"]) == 1.0).all()
+    # bits past m in the last word are ignored
+    B = synth.random_binary(8, 45, 8)
+    words = _np_pack(B.numpy())
+    words[:, -1] |= np.int32(-(1 << 13))        # set bits 13..31 of the last word
+    res = pid.pid_mean(pid.PackedMasks(torch.from_numpy(words).to(DEV), 45))
+    assert_bitwise(res, oracle.binary_pid_mean(B.numpy()), keys=KEYS, label="garbage tail")
+
+
+def test_packed_rejects():
+    B = synth.random_binary(4, 100, 1).to(DEV)
+    P = pid.pid_pack_bits(B)
+    with pytest.raises(pid.PidError, match="UNSUPPORTED"):
+        pid.pid_mean(P, iso=dict(kind="step", c=0.5, side=1))
+    with pytest.raises(pid.PidError, match="UNSUPPORTED"):
+        pid.pid_all_pairs(P)
+    with pytest.raises(pid.PidError, match="UNSUPPORTED"):
+        pid.pid_mean_weighted(P, torch.ones(4, dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):
+        pid.pid_pack_bits(B.to(torch.float32))
+
+
+def test_packed_ellipsoids_vs_oracle():
+    """N = 2000 ellipsoids at 50^3 (a point of the member sweep), against
+    the oracle."""
+    B = synth.ellipsoids_3d(2000, 50, 11, device=DEV)
+    res = pid.pid_mean(pid.pid_pack_bits(B))
+    ref = oracle.binary_pid_mean(B.cpu().numpy())
+    assert_bitwise(res, ref, keys=KEYS, label="ellipsoids 2000 @ 50^3")
+    assert_ranks(res["rank"], ref["depth"], 0)
+
+
+@pytest.mark.parametrize("n,res", [(40000, 50), (50, 512)])
+def test_packed_sweep_extremes(n, res):
+    """The largest shapes of the two sweeps: packed and unpacked masks give
+    the same bits of every result, the masses equal the oracle's counts on a
+    sample of members, and the depths lie in [0, 1]."""
+    B = synth.ellipsoids_3d(n, res, 12, device=DEV)
+    pk = pid.pid_mean(pid.pid_pack_bits(B))
+    u8 = pid.pid_mean(B)
+    for k in KEYS:
+        assert torch.equal(pk[k], u8[k]), k
+    assert torch.equal(pk["rank"], u8["rank"])
+    rng = np.random.Generator(np.random.PCG64(n))
+    for i in rng.choice(n, size=min(n, 8), replace=False):
+        assert pk["mass"][i].item() == float(oracle.mass(B[i].cpu().numpy()[None].astype(np.float64))[0])
+    d = np64(pk["depth"])
+    assert (d >= 0).all() and (d <= 1).all()
