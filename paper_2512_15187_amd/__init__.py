@@ -297,14 +297,15 @@ def pid_pack_bits(U, out=None, stream=None) -> PackedMasks:
     """Pack N x M uint8 0/1 device masks into PackedMasks (on the device).
     ``out``: an N x ldw int32 device tensor to fill (unit stride along a row,
     32 * ldw >= M; its words past the last one that holds points are left as
-    they are), else a new N x ceil(M / 32) one."""
+    they are), else a new one whose rows are padded to a multiple of four
+    words (16-byte rows, which the PID-mean kernels read as vectors)."""
     lib = load_library()
     e = make_ensemble(U)
     if U.dtype != torch.uint8:
         raise ValueError("pid_pack_bits packs uint8 0/1 masks")
     m = U.shape[1]
     if out is None:
-        words = torch.empty((U.shape[0], (m + 31) // 32), dtype=torch.int32, device=U.device)
+        words = torch.zeros((U.shape[0], (m + 127) // 128 * 4), dtype=torch.int32, device=U.device)
     else:
         words = out
         _require_gpu(words, "out")

@@ -194,7 +194,7 @@ pid_status workspace_size(const pid_ensemble* ens, const pid_iso* iso, int varia
     if (variant != 1) return fail(PID_ERR_UNSUPPORTED, "PID_B1 masks are taken by pid_mean only");
     const pidk::B1Plan p = pidk::b1_plan(ens->n, ens->m);
     if (p.unsupported) return fail(PID_ERR_UNSUPPORTED, "n or m beyond the bit-packed launch limits");
-    kb = pidk::b1_workspace(p, ens->n);
+    kb = pidk::b1_workspace(p, ens->n, false);
   } else if (variant == 0) {
     int scheme = 0;
     s = resolve_scheme(ens, kind, gemm, &scheme);
@@ -393,8 +393,8 @@ pid_status pid_pack_bits(const pid_ensemble* ens, void* out, int64_t out_ld, voi
   if ((reinterpret_cast<uintptr_t>(out) & 3) != 0) return fail(PID_ERR_INVALID_ARG, "out must be 4-byte aligned");
   if (out_ld < ens->m || out_ld % 32 != 0)
     return fail(PID_ERR_INVALID_ARG, "out_ld (%lld) must be a multiple of 32 and >= m", (long long)out_ld);
-  if ((ens->m + 31) / 32 > (int64_t)INT32_MAX * 256 / ens->n)
-    return fail(PID_ERR_UNSUPPORTED, "n * m too large for one launch");
+  if ((ens->n + 15) / 16 > 65535 || (ens->m + 2047) / 2048 / 4 >= INT32_MAX)
+    return fail(PID_ERR_UNSUPPORTED, "n or m beyond the packing launch limits");
   hipError_t err = pidk::launch_pack_bits(*ens, static_cast<uint32_t*>(out), out_ld / 32,
                                           reinterpret_cast<hipStream_t>(stream));
   if (err != hipSuccess) return hip_fail(err, "pid_pack_bits launch");

@@ -111,8 +111,9 @@ hipError_t launch_field_max(const pid_ensemble& e, double* out, hipStream_t st) 
 }
 
 // rank[i] = #{ j : d_j > d_i  or  (d_j == d_i and j < i) };  order[rank[i]] = i.
-// One wave per member: lanes compare strided j, popcounts of the ballots
-// give the count (an exact integer, so the result is order-independent).
+// One wave per MPW members: lanes compare strided j against each of the
+// wave's members, popcounts of the ballots give the counts (exact integers,
+// so the result does not depend on the order of the comparisons).
 // blockIdx.y selects one of two depth arrays (the second may be absent).
 struct RankArgs {
   const double* d[2];
@@ -120,40 +121,111 @@ struct RankArgs {
   int32_t* order[2];
 };
 
+template <int MPW>
 __global__ __launch_bounds__(256) void rank_kernel(RankArgs ra, int n) {
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * MPW;
   const double* __restrict__ d = ra.d[blockIdx.y];
   int32_t* __restrict__ rank = ra.rank[blockIdx.y];
   int32_t* __restrict__ order = ra.order[blockIdx.y];
-  if (i >= n) return;                       // whole wave leaves together
-  const double di = d[i];
-  int r = 0;
+  if (i0 >= n) return;                      // whole wave leaves together
+  double di[MPW];
+  int r[MPW];
+#pragma unroll
+  for (int q = 0; q < MPW; ++q) {
+    di[q] = (i0 + q < n) ? d[i0 + q] : 0.0;
+    r[q] = 0;
+  }
   // four 64-member chunks per round: their loads are issued together
   for (int j0 = 0; j0 < n; j0 += 256) {
     double dj[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + 64 * q + lane;
-      dj[q] = j < n ? d[j] : 0.0;
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + 64 * c + lane;
+      dj[c] = j < n ? d[j] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + 64 * q + lane;
-      const bool before = j < n && ((dj[q] > di) || (dj[q] == di && j < i));
-      r += __popcll(__ballot(before));
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + 64 * c + lane;
+#pragma unroll
+      for (int q = 0; q < MPW; ++q) {
+        const bool before = j < n && ((dj[c] > di[q]) || (dj[c] == di[q] && j < i0 + q));
+        r[q] += __popcll(__ballot(before));
+      }
     }
   }
-  if (lane == 0) {
-    if (rank) rank[i] = r;
-    if (order) order[r] = i;
+#pragma unroll
+  for (int q = 0; q < MPW; ++q) {
+    if (lane == q && i0 + q < n) {
+      if (rank) rank[i0 + q] = r[q];
+      if (order) order[r[q]] = i0 + q;
+    }
   }
+}
+
+// Large ensembles: a block of four waves ranks 64 consecutive members (16
+// per wave) against tiles of 2048 depths staged in LDS.  For a chunk of 64 j
+// entirely below the wave's members, "before" is d_j >= d_i; entirely above,
+// d_j > d_i; only the chunk that holds the members themselves needs the
+// index test.  Padding past n is NaN, which compares false.
+constexpr int kRankTile = 2048;
+
+__global__ __launch_bounds__(256) void rank_lds_kernel(RankArgs ra, int n) {
+  __shared__ double tile[kRankTile];
+  const int lane = threadIdx.x & 63;
+  const int i0 = blockIdx.x * 64 + (threadIdx.x >> 6) * 16;   // the wave's first member
+  const double* __restrict__ d = ra.d[blockIdx.y];
+  double di[16];
+  int r[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    di[q] = (i0 + q < n) ? d[i0 + q] : 0.0;
+    r[q] = 0;
+  }
+  for (int t0 = 0; t0 < n; t0 += kRankTile) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < kRankTile; k += 256)
+      tile[k] = (t0 + k < n) ? d[t0 + k] : __builtin_nan("");
+    __syncthreads();
+    const int tend = min(kRankTile, n - t0);
+    for (int c0 = 0; c0 < tend; c0 += 64) {
+      const int j0 = t0 + c0;
+      const double dj = tile[c0 + lane];
+      const int j = j0 + lane;
+      if (j0 + 64 <= i0) {          // every j before every member of the wave
+#pragma unroll
+        for (int q = 0; q < 16; ++q) r[q] += __popcll(__ballot(dj >= di[q]));
+      } else if (j0 >= i0 + 16) {   // every j after
+#pragma unroll
+        for (int q = 0; q < 16; ++q) r[q] += __popcll(__ballot(dj > di[q]));
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) r[q] += __popcll(__ballot((dj > di[q]) || (dj == di[q] && j < i0 + q)));
+      }
+    }
+  }
+  int32_t* __restrict__ rank = ra.rank[blockIdx.y];
+  int32_t* __restrict__ order = ra.order[blockIdx.y];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (lane == q && i0 + q < n) {
+      if (rank) rank[i0 + q] = r[q];
+      if (order) order[r[q]] = i0 + q;
+    }
+  }
+}
+
+static void launch_rank_kernel(const RankArgs& ra, int64_t n, int arrays, hipStream_t st) {
+  if (n <= 2048)
+    hipLaunchKernelGGL((rank_kernel<1>), dim3((unsigned)((n + 3) / 4), arrays), 256, 0, st, ra, (int)n);
+  else
+    hipLaunchKernelGGL(rank_lds_kernel, dim3((unsigned)((n + 63) / 64), arrays), 256, 0, st, ra, (int)n);
 }
 
 hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st) {
   KernelTimer tm("rank", st);
   RankArgs ra{{depth, nullptr}, {rank, nullptr}, {order, nullptr}};
-  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((n + 3) / 4), 1), 256, 0, st, ra, (int)n);
+  launch_rank_kernel(ra, n, 1, st);
   return hipGetLastError();
 }
 
@@ -161,7 +233,7 @@ hipError_t launch_rank2(const double* d0, int32_t* rank0, int32_t* order0, const
                         int32_t* order1, int64_t n, hipStream_t st) {
   KernelTimer tm("rank", st);
   RankArgs ra{{d0, d1}, {rank0, rank1}, {order0, order1}};
-  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((n + 3) / 4), 2), 256, 0, st, ra, (int)n);
+  launch_rank_kernel(ra, n, 2, st);
   return hipGetLastError();
 }
 

@@ -1087,16 +1087,9 @@ static void launch_dma(const MeanPlan& p, const pid_ensemble& e, double* part, h
   else go(pidmean_dma_kernel<T, false, 32, 4>);
 }
 
-hipError_t launch_binary_finalize(const long long* part, long long* red, int nparts, int64_t n, const pid_out& out,
-                                  hipStream_t st) {
-  KernelTimer tm("pidmean_finalize", st);
-  hipLaunchKernelGGL(pidmean_reduce<true>, dim3((unsigned)n, 2), 256, 0, st, part, nparts, (int)n, red);
-  hipLaunchKernelGGL(pidmean_ratios<true>, 1, 256, 0, st, red, (int)n, out.mass, out.in_in, out.in_out, out.depth);
-  return hipGetLastError();
-}
-
 hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_kind,
                            const ExtractHost& exh, const pid_out& out, void* ws, hipStream_t st) {
+  if (plan.bits) return launch_u8_bits_mean(e, out, ws, st);
   Extract ex = __builtin_bit_cast(Extract, exh);
   Carve c(ws);
   void* part = c.take<double>((size_t)std::max(std::max(plan.grid, plan.pipe_grid), plan.dma_grid) * 2 * e.n);

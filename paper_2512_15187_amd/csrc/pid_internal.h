@@ -59,6 +59,7 @@ struct MeanPlan {
   int dma_nwaves, dma_grid;
   size_t dma_lds;
   int unsupported;  // 1: no launch geometry keeps the exact integer sums in range
+  int bits;         // 1: U8 binary masks, packed in the first pass (launch_u8_bits_mean)
 };
 MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted);
 size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m);
@@ -67,6 +68,7 @@ hipError_t launch_pid_mean(const MeanPlan& p, const pid_ensemble& e, int iso_kin
 // Bit-packed binary masks (PID_B1): exact integer PID-mean from popcounts.
 struct B1Plan {
   int64_t W;        // 32-point words per row
+  int64_t Wp;       // W rounded up to 4: row stride of the count planes and of a packed copy
   int groups;       // member groups of the column counts (<= 255 members each)
   int chunk;        // members per group
   int kt;           // bit planes of the total count: 8, 16 or 32 (counts up to n)
@@ -75,14 +77,11 @@ struct B1Plan {
   int unsupported;
 };
 B1Plan b1_plan(int64_t n, int64_t m);
-size_t b1_workspace(const B1Plan& p, int64_t n);
+size_t b1_workspace(const B1Plan& p, int64_t n, bool packed_copy);
 hipError_t launch_b1_mean(const pid_ensemble& e, const pid_out& out, void* ws, hipStream_t st);
+hipError_t launch_u8_bits_mean(const pid_ensemble& e, const pid_out& out, void* ws, hipStream_t st);
 // U8 0/1 masks -> PID_B1 rows of out_ldw 32-bit words.
 hipError_t launch_pack_bits(const pid_ensemble& e, uint32_t* out, int64_t out_ldw, hipStream_t st);
-// The exact-integer reduction of [2][n][nparts] partials (m, S) and the
-// binary PID-mean ratios.
-hipError_t launch_binary_finalize(const long long* part, long long* red, int nparts, int64_t n, const pid_out& out,
-                                  hipStream_t st);
 
 // PID-mean against a mean contour weighted by member_w (N device doubles).
 size_t mean_weighted_workspace(int64_t n, int64_t m, int dtype);

@@ -172,6 +172,11 @@ constexpr int64_t kTilesPerWorkgroup = 16;
 MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted) {
   MeanPlan p{};
   p.binary = is_binary(dtype, iso_kind, weighted) ? 1 : 0;
+  if (p.binary && dtype == PID_U8) {   // packed on the fly, then the popcount passes
+    p.bits = 1;
+    p.unsupported = b1_plan(n, m).unsupported;
+    return p;
+  }
   const int eb = elem_bytes_of(dtype);
   const int ppl = 16 / eb;
   const int tp = 64 * ppl;
@@ -278,6 +283,7 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
 }
 
 size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m) {
+  if (p.bits) return b1_workspace(b1_plan(n, m), n, true);
   Carve c(nullptr);
   c.take<double>((size_t)std::max(std::max(p.grid, p.pipe_grid), p.dma_grid) * 2 * n);   // partials
   c.take<double>((size_t)2 * n);            // reduced A and m
@@ -328,26 +334,31 @@ size_t pairs_linear_workspace(int64_t n, int64_t m, int dtype, int iso_kind, boo
 B1Plan b1_plan(int64_t n, int64_t m) {
   B1Plan p{};
   p.W = (m + 31) / 32;
-  p.groups = (int)((n + 254) / 255);
+  p.Wp = (p.W + 3) / 4 * 4;
+  // member groups of the first pass: at most 255 members each (8 count
+  // planes), and enough of them that chunks x groups fills the GPU (about
+  // 2048 waves), down to 8 members per group
+  const int64_t chunks = (m + 2047) / 2048;
+  const int64_t want = std::min<int64_t>((n + 7) / 8, (2048 + chunks - 1) / chunks);
+  p.groups = (int)std::min<int64_t>(INT32_MAX, std::max<int64_t>((n + 254) / 255, want));
   p.chunk = (int)((n + p.groups - 1) / p.groups);
-  int bits = 1;
-  while (bits < 31 && (INT64_C(1) << bits) <= n) ++bits;   // bits of the largest count, n
-  p.kt = bits <= 8 ? 8 : (bits <= 16 ? 16 : 32);           // the row kernel's plane count
-  const int wpl = p.kt <= 16 ? 4 : 2;
-  p.ntiles = (int)std::min<int64_t>(INT32_MAX, (p.W + 64 * wpl - 1) / (64 * wpl));
-  p.mgroups = (int)((n + 63) / 64);
-  if (p.groups > kMaxGridY || p.mgroups > kMaxGridY || (p.W + 255) / 256 > INT32_MAX ||
-      (p.W + 64 * wpl - 1) / (64 * wpl) > INT32_MAX)
+  int bits = 1;   // bits of the largest column count, n
+  while (bits < 31 && (INT64_C(1) << bits) <= n) ++bits;
+  p.kt = bits <= 8 ? 8 : (bits <= 16 ? 16 : 32);
+  p.ntiles = (int)std::min<int64_t>(INT32_MAX, (p.W + 63) / 64);   // row tiles of one word per lane (the most)
+  p.mgroups = (int)std::min<int64_t>(INT32_MAX, (n + 63) / 64);
+  if (p.groups > kMaxGridY || p.mgroups > kMaxGridY || (p.W + 63) / 64 > INT32_MAX || (m + 2047) / 2048 > INT32_MAX)
     p.unsupported = 1;
   return p;
 }
 
-size_t b1_workspace(const B1Plan& p, int64_t n) {
+size_t b1_workspace(const B1Plan& p, int64_t n, bool packed_copy) {
   Carve c(nullptr);
-  c.take<uint32_t>((size_t)p.groups * 8 * p.W);                 // group count planes
-  c.take<uint32_t>((size_t)p.kt * p.W);                         // total count planes
+  c.take<uint32_t>((size_t)p.groups * 8 * p.Wp);                // group count planes
+  c.take<uint32_t>((size_t)p.kt * p.Wp);                        // count planes
   c.take<long long>((size_t)2 * n * p.ntiles);                  // row partials
-  c.take<long long>((size_t)2 * n);                             // reduced m, S
+  c.take<long long>((size_t)2 * n + 1);                         // reduced m, S and the total
+  if (packed_copy) c.take<uint32_t>((size_t)n * p.Wp);          // packed copy of U8 masks
   return c.off + 256;
 }
 

@@ -35,8 +35,8 @@ def _np_pack(B, ldw=None):
 def test_pack_layout(n, m):
     B = synth.random_binary(n, m, n * 7 + m)
     P = pid.pid_pack_bits(B.to(DEV))
-    assert P.words.shape == (n, (m + 31) // 32)
-    assert np.array_equal(P.words.cpu().numpy(), _np_pack(B.numpy()))
+    assert P.words.shape == (n, (m + 127) // 128 * 4)   # rows padded to 16 bytes
+    assert np.array_equal(P.words.cpu().numpy(), _np_pack(B.numpy(), (m + 127) // 128 * 4))
     # a strided U8 source and a padded destination: words past the row's last
     # one are left as they were
     wide = torch.zeros((n, m + 40), dtype=torch.uint8)
@@ -135,3 +135,16 @@ def test_packed_sweep_extremes(n, res):
         assert pk["mass"][i].item() == float(oracle.mass(B[i].cpu().numpy()[None].astype(np.float64))[0])
     d = np64(pk["depth"])
     assert (d >= 0).all() and (d <= 1).all()
+
+
+@pytest.mark.parametrize("off", [0, 1, 7, 15])
+@pytest.mark.parametrize("m", [1, 100, 2047, 2048, 2049, 5000])
+def test_u8_mean_any_alignment(off, m):
+    """U8 masks are packed on the fly from 16-byte blocks aligned down from
+    each row's start: rows at every misalignment, chunk-sized and ragged."""
+    n = 37
+    B = synth.random_binary(n, m, off * 100 + m)
+    wide = torch.zeros((n, m + 48), dtype=torch.uint8)
+    wide[:, off:off + m] = B
+    res = pid.pid_mean(wide.to(DEV)[:, off:off + m])
+    assert_bitwise(res, oracle.binary_pid_mean(B.numpy()), keys=KEYS, label=f"u8 off={off} m={m}")

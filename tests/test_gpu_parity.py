@@ -266,6 +266,17 @@ def test_rank_entry_point():
     assert rank.cpu().tolist() == r.tolist() and order.cpu().tolist() == o.tolist()
 
 
+@pytest.mark.parametrize("n", [2048, 2049, 5003, 40000])
+def test_rank_large(n):
+    """Large ensembles (eight members per wave): exact ranks, with ties (depths
+    drawn from 600 values) broken by the member index."""
+    rng = np.random.Generator(np.random.PCG64(n))
+    d = torch.from_numpy(rng.integers(0, 600, size=n) / 600.0)
+    rank, order = pid.pid_rank(_dev(d))
+    r, o = oracle.rank_order(d.numpy())
+    assert np.array_equal(rank.cpu().numpy(), r) and np.array_equal(order.cpu().numpy(), o)
+
+
 # ------------------------------------------------------------------ both in one call
 BOTH_CASES = [
     # (n, m, dtype, weighted, gemm)
