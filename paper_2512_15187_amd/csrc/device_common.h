@@ -70,6 +70,18 @@ __device__ __forceinline__ float half_erfc_fast(float z) {
   return z >= 0.0f ? h : 1.0f - h;
 }
 
+// Lets a kernel take as dynamic LDS all of the CU's 160 KB that its static
+// LDS leaves (call once per kernel before its first launch).  A failure is
+// returned and cleared, so that it does not surface at a later launch.
+inline hipError_t allow_dynamic_lds(const void* k) {
+  hipFuncAttributes fa{};
+  hipError_t e = hipFuncGetAttributes(&fa, k);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(163840 - fa.sharedSizeBytes));
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
 // Membership probability in float from a stored value (all input types but
 // double; doubles use extract_d).  FAST selects half_erfc_fast for the
 // Gaussian model (the 16-bit MFMA Gram and PID-mean loaders); otherwise erfcf.

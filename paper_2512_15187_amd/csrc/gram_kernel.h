@@ -954,8 +954,7 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
     ga.slabs = (ga0.m * eb + 127) / 128;   // 128-byte slabs of every row
     const bool w = ga.w != nullptr;
     auto go = [&](auto k, size_t lds, int threads) {
-      static const bool attr = (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                    163840) == hipSuccess);
+      static const bool attr = (allow_dynamic_lds((const void*)k) == hipSuccess);
       (void)attr;
       hipExtLaunchKernelGGL(k, dim3(grid), dim3(threads), (uint32_t)lds, st, tm.start(), tm.stop(), 0u, ga);
     };
@@ -989,9 +988,8 @@ void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
   constexpr int CH256 = (256 * CPR / 512) > 0 ? 256 * CPR / 512 : 1;   // chunk slots for 256 rows
   constexpr int CH128 = (128 * CPR / 512) > 0 ? 128 * CPR / 512 : 1;   // ... for 128 rows
   auto go = [&](auto k) {
-    // allow up to 160 KB of LDS, once per kernel
-    static const bool attr = (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                  163840) == hipSuccess);
+    // all the LDS the kernel's static LDS leaves, once per kernel
+    static const bool attr = (allow_dynamic_lds((const void*)k) == hipSuccess);
     (void)attr;
     hipExtLaunchKernelGGL(k, dim3(grid), dim3(512), (uint32_t)lds, st, tm.start(), tm.stop(), 0u, ga);
   };

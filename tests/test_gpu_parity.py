@@ -224,15 +224,43 @@ def test_zero_mass_and_identical_members():
     assert (np64(rz["depth"]) == 0).all()
 
 
-def test_deterministic_repeat():
-    U = _dev(_soft(200, 20000, 61, torch.float16))
-    a = pid.pid_all_pairs(U)
-    b = pid.pid_all_pairs(U)
-    for k in ("inclusion", "depth", "in_in", "in_out"):
-        assert torch.equal(a[k], b[k]), k
-    a = pid.pid_mean(U)
-    b = pid.pid_mean(U)
-    assert torch.equal(a["depth"], b["depth"])
+@pytest.mark.parametrize("case", ["f16_pairs_mean", "f32_both_gauss", "weighted_f32", "u8_bits", "fields_models"])
+def test_deterministic_repeat(case):
+    """Ten runs of each call give the same bits (split-K partials, column-sum
+    groups and tile partials are all reduced in a fixed order), with the
+    caller's streams and other work in between."""
+    runs = []
+    for r in range(10):
+        if case == "f16_pairs_mean":
+            U = _dev(_soft(200, 20000, 61, torch.float16))
+            a, b = pid.pid_all_pairs(U), pid.pid_mean(U)
+            out = [a["inclusion"], a["depth"], a["in_in"], a["in_out"], b["depth"], b["in_in"], b["in_out"]]
+        elif case == "f32_both_gauss":
+            F = _dev(_fields(256, 4096 * 3 + 17, 62))
+            p, m = pid.pid_both(F, iso=dict(kind="gaussian", c=0.5, sigma=0.05, side=1))
+            out = [p["inclusion"], p["depth"], m["depth"], m["in_out"]]
+        elif case == "weighted_f32":
+            U = _dev(_soft(300, 9000, 63, torch.float32))
+            w = _dev(_weights(9000, 64))
+            a = pid.pid_mean(U, w)
+            c = pid.pid_pairs_depths(U, w)
+            out = [a["depth"], a["in_in"], c["depth"], c["in_out"]]
+        elif case == "u8_bits":
+            B = _dev(synth.random_binary(3000, 20000, 65))
+            out = [pid.pid_mean(B)["depth"], pid.pid_mean(pid.pid_pack_bits(B))["depth"]]
+        else:
+            F = _dev(_fields(96, 7001, 66))
+            a = pid.pid_all_pairs(F, iso=dict(kind="tent", c=0.5, width=0.1))
+            b = pid.pid_mean_weighted(F, _dev(torch.linspace(0.0, 1.0, 96, dtype=torch.float64)),
+                                      iso=dict(kind="ramp", c=0.5, width=0.1, side=1))
+            out = [a["inclusion"], a["depth"], b["depth"]]
+        torch.cuda.synchronize()
+        runs.append([t.cpu() for t in out])
+        if r % 3 == 1:      # other work on the device between runs
+            torch.randn(1 << 20, device=DEV).sum().item()
+    for r in runs[1:]:
+        for x, y in zip(runs[0], r):
+            assert torch.equal(x, y), case
 
 
 def test_validate_flag():
