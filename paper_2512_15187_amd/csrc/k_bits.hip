@@ -13,10 +13,11 @@
 //   2. row sums: S_i = sum_w sum_k 2^k popcount(b_i(w) & P_k(w)) and
 //      m_i = sum_w popcount(b_i(w)), per lane in registers, per wave by a fixed
 //      butterfly, per tile into int64 partials reduced in a fixed order.
-// U8 0/1 masks take the same path: their first pass reads the bytes once,
-// packs them into a workspace copy (an eighth of the bytes) and counts them,
-// and the row pass reads the packed copy.  The packing kernel writes the
-// packed layout from U8 masks for callers that keep them packed.
+// U8 0/1 masks and thresholded fields (the sharp isovalue, Sec. 3.1 Eq. 2)
+// take the same path: their first pass reads the stored values once, turns
+// them into bits, packs them into a workspace copy and counts them, and the
+// row pass reads the packed copy.  The packing kernel writes the packed
+// layout from U8 masks for callers that keep them packed.
 #include "device_common.h"
 #include "pid_internal.h"
 #include "pid_timing.h"
@@ -99,6 +100,88 @@ __device__ __forceinline__ void count_add(uint32_t (&P)[8], uint32_t c) {
   }
 }
 
+// OR of v over groups of L consecutive lanes (L = 2, 4, 8 or 16) by DPP
+// moves: pairs, quads, half rows, rows.
+template <int L>
+__device__ __forceinline__ uint32_t group_or(uint32_t v) {
+  int x = (int)v;
+  x |= __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);                       // quad_perm [1,0,3,2]
+  if constexpr (L >= 4) x |= __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  if constexpr (L >= 8) x |= __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  if constexpr (L >= 16) x |= __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false); // row_mirror
+  return (uint32_t)x;
+}
+
+// The lane's word of chunk c (2048 points) of a row of stored values of T
+// under the sharp isovalue, rows 16-byte aligned.  A 16-byte block holds
+// P = 16 / sizeof(T) points and a word L = 32 / P blocks; the wave reads the
+// chunk in L fully coalesced loads (lane l takes block 64k + l in load k), so
+// that in load k the L lanes of group j hold the P-bit pieces of word
+// 64k / L + j: an OR over the group (DPP) gives every lane of it that word,
+// and lane l keeps the one of load k = l mod L, i.e. word
+// (64 / L)(l mod L) + l / L of the chunk.  Blocks wholly past m are not
+// loaded; points past m are masked.  Wave-uniform calls.
+template <typename T>
+__device__ __forceinline__ int chunk_word_step_index(int lane) {
+  constexpr int L = 2 * (int)sizeof(T);
+  return (64 / L) * (lane % L) + lane / L;
+}
+
+// The L blocks of a chunk that lane `lane` reads (zeros for blocks wholly
+// past m; a full chunk loads without guards, a wave-uniform branch).
+template <typename T>
+struct StepBlocks {
+  Vec16<T> v[2 * sizeof(T)];
+};
+
+template <typename T>
+__device__ __forceinline__ StepBlocks<T> chunk_load_step(const T* row, int64_t c, int64_t m, int lane) {
+  constexpr int P = 16 / (int)sizeof(T);
+  constexpr int L = 32 / P;
+  const Vec16<T>* cp = reinterpret_cast<const Vec16<T>*>(row + c * 2048);
+  const int64_t rem = m - c * 2048;
+  StepBlocks<T> r;
+  if (rem >= 2048) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) r.v[k] = cp[64 * k + lane];
+  } else {
+#pragma unroll
+    for (int k = 0; k < L; ++k) r.v[k] = ((int64_t)(64 * k + lane) * P < rem) ? cp[64 * k + lane] : Vec16<T>{};
+  }
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t chunk_word_step(const StepBlocks<T>& blk, int64_t c, int64_t m, int lane,
+                                                    const Extract& ex) {
+  constexpr int P = 16 / (int)sizeof(T);
+  constexpr int L = 32 / P;
+  const int64_t rem = m - c * 2048;
+  uint32_t mine = 0u;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const int64_t x0 = (int64_t)(64 * k + lane) * P;
+    uint32_t piece = 0u;
+#pragma unroll
+    for (int p = 0; p < P; ++p) piece |= (uint32_t)(extract_bit<MODE_STEP>(blk.v[k].v[p], ex) != 0) << p;
+    if (rem < 2048) piece &= (x0 >= rem) ? 0u : (rem - x0 >= P ? 0xffffffffu : ((1u << (rem - x0)) - 1u));
+    const uint32_t w = group_or<L>(piece << (P * (lane % L)));
+    if (lane % L == k) mine = w;
+  }
+  return mine;
+}
+
+// Word wi of a row from single values under the sharp isovalue (rows of any
+// alignment; points at or past m read as 0).
+template <typename T>
+__device__ __forceinline__ uint32_t word_elems_step(const T* row, int64_t m, int64_t wi, const Extract& ex) {
+  const int64_t p0 = wi * 32;
+  const int cnt = (int)max((int64_t)0, min((int64_t)32, m - p0));
+  uint32_t b = 0u;
+  for (int k = 0; k < cnt; ++k) b |= (uint32_t)(extract_bit<MODE_STEP>(row[p0 + k], ex) != 0) << k;
+  return b;
+}
+
 // ---------------------------------------------------------------- packing
 // Wave per (chunk of 2048 points, 16 rows): grid.x covers four chunks per
 // block, grid.y 16 rows per block.
@@ -159,6 +242,56 @@ __global__ __launch_bounds__(64) void u8_count_pack_kernel(const uint8_t* __rest
   }
   for (; i < i1; ++i) {
     const uint32_t w0 = chunk_word_u8<false>(U + (int64_t)i * ld, c, m, lane);
+    count_add(P, w0);
+    if (wi < W) pk[(int64_t)i * ldp + wi] = w0;
+  }
+  if (wi < W) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) gpart[((int64_t)g * 8 + k) * Wp + wi] = P[k];
+  }
+}
+
+// Thresholded fields: as u8_count_pack_kernel, with the words formed by
+// chunk_word_step (ALIGNED: rows 16-byte aligned) or element by element.
+template <typename T, bool ALIGNED>
+__global__ __launch_bounds__(64) void step_count_pack_kernel(const T* __restrict__ U, int64_t ld, int n, int64_t m,
+                                                             Extract ex, int chunk, uint32_t* __restrict__ pk,
+                                                             int64_t ldp, int64_t Wp, uint32_t* __restrict__ gpart) {
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  const int g = blockIdx.y;
+  const int64_t W = (m + 31) / 32;
+  const int64_t wi = c * 64 + (ALIGNED ? chunk_word_step_index<T>(lane) : lane);
+  const int i0 = g * chunk, i1 = min(n, i0 + chunk);
+  uint32_t P[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) P[k] = 0u;
+  auto word = [&](int i) -> uint32_t {
+    const T* row = U + (int64_t)i * ld;
+    if constexpr (ALIGNED) return chunk_word_step<T>(chunk_load_step<T>(row, c, m, lane), c, m, lane, ex);
+    else return word_elems_step<T>(row, m, wi, ex);
+  };
+  int i = i0;
+  for (; i + 1 < i1; i += 2) {   // two rows in flight
+    uint32_t w0, w1;
+    if constexpr (ALIGNED) {
+      const StepBlocks<T> b0 = chunk_load_step<T>(U + (int64_t)i * ld, c, m, lane);
+      const StepBlocks<T> b1 = chunk_load_step<T>(U + (int64_t)(i + 1) * ld, c, m, lane);
+      w0 = chunk_word_step<T>(b0, c, m, lane, ex);
+      w1 = chunk_word_step<T>(b1, c, m, lane, ex);
+    } else {
+      w0 = word(i);
+      w1 = word(i + 1);
+    }
+    count_add(P, w0);
+    count_add(P, w1);
+    if (wi < W) {
+      pk[(int64_t)i * ldp + wi] = w0;
+      pk[(int64_t)(i + 1) * ldp + wi] = w1;
+    }
+  }
+  if (i < i1) {
+    const uint32_t w0 = word(i);
     count_add(P, w0);
     if (wi < W) pk[(int64_t)i * ldp + wi] = w0;
   }
@@ -535,7 +668,22 @@ hipError_t launch_b1_mean(const pid_ensemble& e, const pid_out& out, void* ws, h
   return b1_rows_finalize(p, U, ldw, aligned, e.n, e.m, planes, part, red, out, st);
 }
 
-hipError_t launch_u8_bits_mean(const pid_ensemble& e, const pid_out& out, void* ws, hipStream_t st) {
+template <typename T>
+static void launch_step_count(const pid_ensemble& e, const Extract& ex, const B1Plan& p, uint32_t* pk,
+                              uint32_t* gpart, hipStream_t st) {
+  const T* U = reinterpret_cast<const T*>(e.data);
+  const dim3 grid((unsigned)((e.m + 2047) / 2048), (unsigned)p.groups);
+  const bool aligned = (reinterpret_cast<uintptr_t>(e.data) & 15) == 0 && (e.ld * (int64_t)sizeof(T)) % 16 == 0;
+  if (aligned)
+    hipLaunchKernelGGL((step_count_pack_kernel<T, true>), grid, 64, 0, st, U, e.ld, (int)e.n, e.m, ex, p.chunk, pk,
+                       p.Wp, p.Wp, gpart);
+  else
+    hipLaunchKernelGGL((step_count_pack_kernel<T, false>), grid, 64, 0, st, U, e.ld, (int)e.n, e.m, ex, p.chunk, pk,
+                       p.Wp, p.Wp, gpart);
+}
+
+hipError_t launch_mask_bits_mean(const pid_ensemble& e, int iso_kind, const ExtractHost& exh, const pid_out& out,
+                                 void* ws, hipStream_t st) {
   const B1Plan p = b1_plan(e.n, e.m);
   Carve c(ws);
   uint32_t* gpart = c.take<uint32_t>((size_t)p.groups * 8 * p.Wp);
@@ -543,12 +691,22 @@ hipError_t launch_u8_bits_mean(const pid_ensemble& e, const pid_out& out, void* 
   long long* part = c.take<long long>((size_t)2 * e.n * p.ntiles);
   long long* red = c.take<long long>((size_t)2 * e.n + 1);
   uint32_t* pk = c.take<uint32_t>((size_t)e.n * p.Wp);
-  const uint8_t* U = reinterpret_cast<const uint8_t*>(e.data);
   {
     KernelTimer tm("pidmean_colsum", st);
-    const dim3 grid((unsigned)((e.m + 2047) / 2048), (unsigned)p.groups);
-    hipLaunchKernelGGL(u8_count_pack_kernel, grid, 64, 0, st, U, e.ld, (int)e.n, e.m, p.chunk, pk, p.Wp, p.Wp,
-                       gpart);
+    if (iso_kind == PID_ISO_NONE) {   // U8 0/1 masks
+      const dim3 grid((unsigned)((e.m + 2047) / 2048), (unsigned)p.groups);
+      hipLaunchKernelGGL(u8_count_pack_kernel, grid, 64, 0, st, reinterpret_cast<const uint8_t*>(e.data), e.ld,
+                         (int)e.n, e.m, p.chunk, pk, p.Wp, p.Wp, gpart);
+    } else {                          // the sharp isovalue on stored values
+      const Extract ex = __builtin_bit_cast(Extract, exh);
+      switch (e.dtype) {
+        case PID_F64: launch_step_count<double>(e, ex, p, pk, gpart, st); break;
+        case PID_F32: launch_step_count<float>(e, ex, p, pk, gpart, st); break;
+        case PID_F16: launch_step_count<f16>(e, ex, p, pk, gpart, st); break;
+        case PID_BF16: launch_step_count<bf16_t>(e, ex, p, pk, gpart, st); break;
+        default: launch_step_count<uint8_t>(e, ex, p, pk, gpart, st); break;
+      }
+    }
     hipError_t err = b1_combine(p, gpart, planes, st);
     if (err != hipSuccess) return err;
   }

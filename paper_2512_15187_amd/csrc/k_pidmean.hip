@@ -9,9 +9,10 @@
 // of the members with 16-byte loads, applies the isovalue model in registers,
 // and writes its partial column sums to LDS; after one barrier every lane holds
 // s(x) for its points and accumulates m_i and A_i for the members it loaded.
-// Per tile the sums are FP32 (FP64 for FP64 input), across tiles FP64; binary
-// input uses exact integers throughout.  Per-workgroup partials are reduced
-// in a fixed order by pidmean_reduce, and pidmean_ratios forms the depths.
+// Per tile the sums are FP32 (FP64 for FP64 input), across tiles FP64.
+// Per-workgroup partials are reduced in a fixed order by pidmean_reduce, and
+// pidmean_ratios forms the depths.  Binary input (U8 masks, thresholded
+// values) takes the exact popcount passes of k_bits.hip instead.
 #include "device_common.h"
 #include <hip/hip_ext.h>
 #include "pid_internal.h"
@@ -538,8 +539,6 @@ __global__ __launch_bounds__(512) void pidmean_dma_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Binary path (U8 masks, or STEP on fields), exact integers.
-// part layout: [2][n][grid.x] long long (m, S).
 // 16 bytes of stored elements from an address that is 8-byte but not
 // necessarily 16-byte aligned (rows whose byte length is a multiple of 8
 // only): two 8-byte non-temporal loads.
@@ -550,173 +549,20 @@ __device__ __forceinline__ Vec16<T> load16_nt8(const T* p) {
   return __builtin_bit_cast(Vec16<T>, t);
 }
 
-template <typename T, int MODE, int MPW, bool SFROM, int NWMAX>
-__global__ __launch_bounds__(64 * NWMAX) void pidmean_bin_kernel(
-    const T* __restrict__ U, int64_t ld, int n, int64_t m, Extract ex, int64_t ntiles,
-    const int* __restrict__ sglob, long long* __restrict__ part, int vec) {
-  constexpr int PPL = Vec16<T>::N;
-  constexpr int TP = 64 * PPL;
-  constexpr bool PACKED = (sizeof(T) == 1 && MODE == MODE_NONE);
-  const bool VEC = vec == 2;    // rows 16-byte aligned
-  const bool VEC8 = vec == 1;   // rows 8-byte aligned
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  int* sbuf = reinterpret_cast<int*>(smem_raw);
-  const int lane = threadIdx.x & 63;
-  const int wave = wave_id();
-  const int nw = blockDim.x >> 6;
-  const int mbase = (SFROM ? blockIdx.y * nw * MPW : 0) + wave * MPW;
-
-  // per-lane integer sums stay below 2^31: at most (tiles per workgroup) *
-  // PPL * N, and the grid keeps the tiles per workgroup small
-  int accm[MPW], acca[MPW];
-#pragma unroll
-  for (int r = 0; r < MPW; ++r) { accm[r] = 0; acca[r] = 0; }
-
-  int it = 0;
-  if constexpr (PACKED && !SFROM) {
-    // U8 masks (values 0/1) in one pass: byte-parallel arithmetic on the
-    // 16 bytes of a lane, four points per 32-bit word.  Column sums of the
-    // wave's members are packed byte adds (each byte <= MPW), the workgroup's
-    // column sums too (each byte <= nw * MPW <= 128); per member, m adds the
-    // bytes and A the byte products with s, both by v_dot4_u32_u8.
-    static_assert(MPW * 8 <= 255, "byte lanes hold the column sums of a workgroup");
-    uint32_t* sbw = reinterpret_cast<uint32_t*>(smem_raw);
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
-      const int64_t x0 = tile * TP + (int64_t)lane * PPL;
-      const bool full = (x0 + PPL <= m);
-      uint32_t raw[MPW][4];
-      uint32_t spw[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int r = 0; r < MPW; ++r) {
-        const int i = mbase + r;
-        Vec16<T> v{};
-        if (i < n) {
-          const T* row = U + (int64_t)i * ld;
-          if (VEC && full) v = load16_nt(row + x0);
-          else if (VEC8 && full) v = load16_nt8(row + x0);
-          else v = load16_guarded(row, x0, m);
-        }
-        const uint4 q = __builtin_bit_cast(uint4, v);
-        raw[r][0] = q.x; raw[r][1] = q.y; raw[r][2] = q.z; raw[r][3] = q.w;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) spw[w] += raw[r][w];
-      }
-      uint32_t* sb = sbw + (size_t)(it & 1) * nw * 256;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) sb[wave * 256 + lane * 4 + w] = spw[w];
-      lds_barrier();
-      uint32_t sw[4] = {0u, 0u, 0u, 0u};
-      for (int q = 0; q < nw; ++q) {
-#pragma unroll
-        for (int w = 0; w < 4; ++w) sw[w] += sb[q * 256 + lane * 4 + w];
-      }
-#pragma unroll
-      for (int r = 0; r < MPW; ++r) {
-        uint32_t tm = 0u, ta = 0u;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          tm = __builtin_amdgcn_udot4(raw[r][w], 0x01010101u, tm, false);
-          ta = __builtin_amdgcn_udot4(raw[r][w], sw[w], ta, false);
-        }
-        accm[r] += (int)tm;
-        acca[r] += (int)ta;
-      }
-    }
-  } else
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
-    const int64_t x0 = tile * TP + (int64_t)lane * PPL;
-    const bool full = (x0 + PPL <= m);
-    uint32_t raw[PACKED ? MPW : 1][4];
-    int ub[PACKED ? 1 : MPW][PACKED ? 1 : PPL];
-    int sp[PPL];
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) sp[p] = 0;
-#pragma unroll
-    for (int r = 0; r < MPW; ++r) {
-      const int i = mbase + r;
-      Vec16<T> v{};
-      if (i < n) {
-        const T* row = U + (int64_t)i * ld;
-        if (VEC && full) v = load16_nt(row + x0);
-        else if (VEC8 && full) v = load16_nt8(row + x0);
-        else v = load16_guarded(row, x0, m);
-      }
-      if constexpr (PACKED) {
-        uint4 q = __builtin_bit_cast(uint4, v);
-        raw[r][0] = q.x; raw[r][1] = q.y; raw[r][2] = q.z; raw[r][3] = q.w;
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) sp[p] += (raw[r][p >> 2] >> (8 * (p & 3))) & 0xffu;
-      } else {
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-          int b = (i < n) ? extract_bit<MODE>(v.v[p], ex) : 0;
-          if (!full) b = (x0 + p < m) ? b : 0;
-          ub[r][p] = b;
-          sp[p] += b;
-        }
-      }
-    }
-
-    int s[PPL];
-    if constexpr (SFROM) {
-#pragma unroll
-      for (int p = 0; p < PPL; ++p) s[p] = (x0 + p < m) ? sglob[x0 + p] : 0;
-    } else {
-      int* sb = sbuf + (size_t)(it & 1) * nw * TP;
-#pragma unroll
-      for (int p = 0; p < PPL; ++p) sb[wave * TP + lane * PPL + p] = sp[p];
-      lds_barrier();
-#pragma unroll
-      for (int p = 0; p < PPL; ++p) s[p] = 0;
-      for (int q = 0; q < nw; ++q) {
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) s[p] += sb[q * TP + lane * PPL + p];
-      }
-    }
-
-#pragma unroll
-    for (int r = 0; r < MPW; ++r) {
-      int tm = 0, ta = 0;
-#pragma unroll
-      for (int p = 0; p < PPL; ++p) {
-        int b;
-        if constexpr (PACKED) b = (raw[r][p >> 2] >> (8 * (p & 3))) & 0xffu;
-        else b = ub[r][p];
-        tm += b;
-        ta += b * s[p];
-      }
-      accm[r] += tm;
-      acca[r] += ta;
-    }
-  }
-
-  const int ng = gridDim.x;
-#pragma unroll
-  for (int r = 0; r < MPW; ++r) {
-    const long long a = wave_sum((long long)accm[r]);
-    const long long b = wave_sum((long long)acca[r]);
-    const int i = mbase + r;
-    if (lane == 0 && i < n) {
-      part[(size_t)i * ng + blockIdx.x] = a;
-      part[((size_t)n + i) * ng + blockIdx.x] = b;
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Column sums over the members for the two-pass cases: s(x) = sum_j u_j(x)
-// (exact integers for binary input) and, for all-pairs depths without the
-// matrix, t(x) = sum_j coef_j u_j(x).  Block (bx, g) owns 64 * PPL points (16
-// bytes of every row per lane) and the members [g chunk, (g + 1) chunk); its 4
-// waves take the members q, q + 4, ... of that range in ascending order, four
-// rows in flight, and add their sums in order q = 0..3; the member groups'
-// sums are added in order g = 0, 1, ... by colsum_combine.
-template <typename T, int MODE, bool BIN, bool SCALED>
+// and, for all-pairs depths without the matrix, t(x) = sum_j coef_j u_j(x).
+// Block (bx, g) owns 64 * PPL points (16 bytes of every row per lane) and the
+// members [g chunk, (g + 1) chunk); its 4 waves take the members q, q + 4, ...
+// of that range in ascending order, four rows in flight, and add their sums
+// in order q = 0..3; the member groups' sums are added in order g = 0, 1, ...
+// by colsum_combine.
+template <typename T, int MODE, bool SCALED>
 __global__ __launch_bounds__(256) void colsum_part_kernel(const T* __restrict__ U, int64_t ld, int n, int64_t m,
                                                           Extract ex, const ComputeT<T>* __restrict__ coef,
                                                           int chunk, void* __restrict__ part_v, int vec) {
   using CT = ComputeT<T>;
-  using AT = typename std::conditional<BIN, int, CT>::type;
+  using AT = CT;
   constexpr int PPL = Vec16<T>::N;
   __shared__ AT part[4][64 * PPL];
   const int lane = threadIdx.x & 63;
@@ -733,22 +579,11 @@ __global__ __launch_bounds__(256) void colsum_part_kernel(const T* __restrict__ 
     return full ? load16_nt(r + x0) : (half ? load16_nt8(r + x0) : load16_guarded(r, x0, m));
   };
   auto add = [&](int i, const Vec16<T>& v) {
-    if constexpr (BIN && MODE == MODE_NONE && sizeof(T) == 1) {
-      // U8 masks hold 0/1: the byte itself is the count
-      const uint4 q = __builtin_bit_cast(uint4, v);
-      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    const CT c = SCALED ? coef[i] : CT(1);
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) t[p] += (int)((w[p >> 2] >> (8 * (p & 3))) & 0xffu);
-    } else if constexpr (BIN) {
-#pragma unroll
-      for (int p = 0; p < PPL; ++p) t[p] += extract_bit<MODE>(v.v[p], ex);
-    } else {
-      const CT c = SCALED ? coef[i] : CT(1);
-#pragma unroll
-      for (int p = 0; p < PPL; ++p) {
-        const CT u = extract_ct<MODE, T, CT>(v.v[p], ex);
-        t[p] += SCALED ? c * u : u;
-      }
+    for (int p = 0; p < PPL; ++p) {
+      const CT u = extract_ct<MODE, T, CT>(v.v[p], ex);
+      t[p] += SCALED ? c * u : u;
     }
   };
   // vector loads of four rows in flight; element loads (unaligned rows, the
@@ -789,73 +624,42 @@ __global__ __launch_bounds__(256) void colsum_combine(const AT* __restrict__ par
 // Fixed-order reduction of the per-workgroup partials: one block per member
 // and quantity (grid.y = 2: m, then A); thread t sums the partials
 // t, t+256, ... in ascending order, then a fixed tree over the 256 threads.
-template <bool BIN>
-__global__ __launch_bounds__(256) void pidmean_reduce(const void* __restrict__ part_v, int nparts,
-                                                      int n, void* __restrict__ out_v) {
-  __shared__ double red_d[256];
-  __shared__ long long red_i[256];
+__global__ __launch_bounds__(256) void pidmean_reduce(const double* __restrict__ part, int nparts, int n,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
   const int i = blockIdx.x, q = blockIdx.y, t = threadIdx.x;
   const size_t base = ((size_t)q * n + i) * nparts;
-  if constexpr (BIN) {
-    const long long* part = reinterpret_cast<const long long*>(part_v);
-    long long s = 0;
-    for (int b = t; b < nparts; b += 256) s += part[base + b];
-    red_i[t] = s;
-  } else {
-    const double* part = reinterpret_cast<const double*>(part_v);
-    double s = 0.0;
-    for (int b = t; b < nparts; b += 256) s += part[base + b];
-    red_d[t] = s;
-  }
+  double s = 0.0;
+  for (int b = t; b < nparts; b += 256) s += part[base + b];
+  red[t] = s;
   __syncthreads();
   for (int o = 128; o >= 1; o >>= 1) {
-    if (t < o) {
-      if constexpr (BIN) red_i[t] += red_i[t + o];
-      else red_d[t] += red_d[t + o];
-    }
+    if (t < o) red[t] += red[t + o];
     __syncthreads();
   }
-  if (t == 0) {
-    if constexpr (BIN) reinterpret_cast<long long*>(out_v)[(size_t)q * n + i] = red_i[0];
-    else reinterpret_cast<double*>(out_v)[(size_t)q * n + i] = red_d[0];
-  }
+  if (t == 0) out[(size_t)q * n + i] = red[0];
 }
 
-// Depth ratios: IN_in = A_i / (N m_i), IN_out = A_i / sum_k m_k.  One block;
-// sum_k m_k by a fixed tree.  Binary sums are exact integers, so each ratio is
-// one correctly rounded division.
-template <bool BIN>
-__global__ __launch_bounds__(256) void pidmean_ratios(const void* __restrict__ red_v, int n,
+// One block: the total mass (fixed tree), then per member the ratios of
+// Sec. 4.1 and the depth.
+__global__ __launch_bounds__(256) void pidmean_ratios(const double* __restrict__ red_v, int n,
                                                       double* __restrict__ m_out,
                                                       double* __restrict__ in_in,
                                                       double* __restrict__ in_out,
                                                       double* __restrict__ depth) {
 #pragma clang fp contract(off)
-  __shared__ double red_d[256];
-  __shared__ long long red_i[256];
+  __shared__ double red[256];
   const int t = threadIdx.x;
   double md = 0.0;
-  long long mi = 0;
-  for (int i = t; i < n; i += 256) {
-    if constexpr (BIN) mi += reinterpret_cast<const long long*>(red_v)[i];
-    else md += reinterpret_cast<const double*>(red_v)[i];
-  }
-  red_d[t] = md;
-  red_i[t] = mi;
+  for (int i = t; i < n; i += 256) md += red_v[i];
+  red[t] = md;
   __syncthreads();
   for (int o = 128; o >= 1; o >>= 1) {
-    if (t < o) { red_d[t] += red_d[t + o]; red_i[t] += red_i[t + o]; }
+    if (t < o) red[t] += red[t + o];
     __syncthreads();
   }
   for (int i = t; i < n; i += 256) {
-    double mm, a, tot;
-    if constexpr (BIN) {
-      const long long* r = reinterpret_cast<const long long*>(red_v);
-      mm = (double)r[i]; a = (double)r[n + i]; tot = (double)red_i[0];
-    } else {
-      const double* r = reinterpret_cast<const double*>(red_v);
-      mm = r[i]; a = r[n + i]; tot = red_d[0];
-    }
+    const double mm = red_v[i], a = red_v[n + i], tot = red[0];
     const double ii = (mm > 0.0) ? a / ((double)n * mm) : 0.0;
     const double oo = (tot > 0.0) ? a / tot : 0.0;
     if (m_out) m_out[i] = mm;
@@ -955,7 +759,7 @@ static void launch_soft_t(const MeanPlan& p, const pid_ensemble& e, const Extrac
   }
 }
 
-// Row alignment for the loads of the binary and column-sum kernels: 2 when
+// Row alignment for the loads of the column-sum kernel: 2 when
 // every row is 16-byte aligned (vec), 1 when 8-byte aligned, else 0.
 template <typename T>
 static int row_align(const pid_ensemble& e, bool vec) {
@@ -963,39 +767,14 @@ static int row_align(const pid_ensemble& e, bool vec) {
   return ((reinterpret_cast<uintptr_t>(e.data) & 7) == 0 && (e.ld * (int64_t)sizeof(T)) % 8 == 0) ? 1 : 0;
 }
 
-template <typename T, int MODE, int MPW>
-static void launch_bin_t(const MeanPlan& p, const pid_ensemble& e, const Extract& ex, bool vec,
-                         const int* sglob, long long* part, hipStream_t st) {
-  dim3 grid(p.grid, p.two_pass ? p.groups : 1);
-  dim3 block(64 * p.nwaves);
-  const T* U = reinterpret_cast<const T*>(e.data);
-  KernelTimer tm("pidmean", st, /*by_launch=*/true);   // one kernel per call
-#define PB_LAUNCH(S)                                                                          \
-  hipExtLaunchKernelGGL((pidmean_bin_kernel<T, MODE, MPW, S, 8>), grid, block, (uint32_t)p.lds_bytes, st,    \
-                        tm.start(), tm.stop(), 0u, U,                                              \
-                     e.ld, (int)e.n, e.m, ex, p.ntiles, sglob, part, row_align<T>(e, vec))
-  if (p.two_pass) PB_LAUNCH(true); else PB_LAUNCH(false);
-#undef PB_LAUNCH
-}
-
 template <typename T, int MODE>
 static void dispatch_mpw(const MeanPlan& p, const pid_ensemble& e, const Extract& ex, bool vec,
                          const void* sglob, void* part, hipStream_t st) {
-  if (p.binary) {
-    if constexpr (MODE == MODE_NONE || MODE == MODE_STEP) {
-      switch (p.mpw) {
-        case 4: launch_bin_t<T, MODE, 4>(p, e, ex, vec, (const int*)sglob, (long long*)part, st); break;
-        case 8: launch_bin_t<T, MODE, 8>(p, e, ex, vec, (const int*)sglob, (long long*)part, st); break;
-        default: launch_bin_t<T, MODE, 16>(p, e, ex, vec, (const int*)sglob, (long long*)part, st); break;
-      }
-    }
-  } else {
-    switch (p.mpw) {
-      case 4: launch_soft_t<T, MODE, 4>(p, e, ex, vec, sglob, (double*)part, st); break;
-      case 8: launch_soft_t<T, MODE, 8>(p, e, ex, vec, sglob, (double*)part, st); break;
-      case 32: launch_soft_t<T, MODE, 32>(p, e, ex, vec, sglob, (double*)part, st); break;
-      default: launch_soft_t<T, MODE, 16>(p, e, ex, vec, sglob, (double*)part, st); break;
-    }
+  switch (p.mpw) {
+    case 4: launch_soft_t<T, MODE, 4>(p, e, ex, vec, sglob, (double*)part, st); break;
+    case 8: launch_soft_t<T, MODE, 8>(p, e, ex, vec, sglob, (double*)part, st); break;
+    case 32: launch_soft_t<T, MODE, 32>(p, e, ex, vec, sglob, (double*)part, st); break;
+    default: launch_soft_t<T, MODE, 16>(p, e, ex, vec, sglob, (double*)part, st); break;
   }
 }
 
@@ -1012,18 +791,18 @@ static void dispatch_mode(const MeanPlan& p, const pid_ensemble& e, int iso_kind
   }
 }
 
-template <typename T, int MODE, bool BIN, bool SCALED>
+template <typename T, int MODE, bool SCALED>
 static void launch_colsum_g(const pid_ensemble& e, const Extract& ex, int groups, const void* coef, void* gpart,
                             void* sout, bool vec, hipStream_t st) {
   using CT = ComputeT<T>;
-  using AT = typename std::conditional<BIN, int, CT>::type;
+  using AT = CT;
   constexpr int PPL = Vec16<T>::N;
   const T* U = reinterpret_cast<const T*>(e.data);
   const dim3 grid((unsigned)((e.m + 64 * PPL - 1) / (64 * PPL)), (unsigned)groups);
   const int chunk = (int)((e.n + groups - 1) / groups);
   KernelTimer tm("pidmean_colsum", st);
   void* dst = groups > 1 ? gpart : sout;
-  hipLaunchKernelGGL((colsum_part_kernel<T, MODE, BIN, SCALED>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
+  hipLaunchKernelGGL((colsum_part_kernel<T, MODE, SCALED>), grid, 256, 0, st, U, e.ld, (int)e.n, e.m, ex,
                      (const CT*)coef, chunk, dst, row_align<T>(e, vec));
   if (groups > 1) {
     const int cgrid = (int)std::min<int64_t>((e.m + 255) / 256, device_cu_count() * 8);
@@ -1035,21 +814,14 @@ template <typename T>
 static void launch_colsum(const MeanPlan& p, const pid_ensemble& e, int iso_kind, const Extract& ex,
                           void* sout, void* gpart, bool vec, hipStream_t st) {
   const int g = p.colsum_groups;
-  if (p.binary) {
-    if constexpr (!std::is_same<T, double>::value) {
-      if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, true, false>(e, ex, g, nullptr, gpart, sout, vec, st);
-      else launch_colsum_g<T, MODE_NONE, true, false>(e, ex, g, nullptr, gpart, sout, vec, st);
-    } else {
-      launch_colsum_g<T, MODE_STEP, true, false>(e, ex, g, nullptr, gpart, sout, vec, st);
-    }
-  } else if (iso_kind == PID_ISO_GAUSSIAN) {
-    launch_colsum_g<T, MODE_GAUSS, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
+  if (iso_kind == PID_ISO_GAUSSIAN) {
+    launch_colsum_g<T, MODE_GAUSS, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   } else if (iso_mode(iso_kind) == MODE_MODEL) {
-    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
+    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   } else if (iso_kind == PID_ISO_STEP) {
-    launch_colsum_g<T, MODE_STEP, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
+    launch_colsum_g<T, MODE_STEP, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   } else {
-    launch_colsum_g<T, MODE_NONE, false, false>(e, ex, g, nullptr, gpart, sout, vec, st);
+    launch_colsum_g<T, MODE_NONE, false>(e, ex, g, nullptr, gpart, sout, vec, st);
   }
 }
 
@@ -1057,15 +829,9 @@ static hipError_t launch_mean_finalize(const MeanPlan& p, const pid_ensemble& e,
                                        int nparts, const pid_out& out, hipStream_t st) {
   KernelTimer tm("pidmean_finalize", st);
   dim3 rgrid((unsigned)e.n, 2);
-  if (p.binary) {
-    hipLaunchKernelGGL(pidmean_reduce<true>, rgrid, 256, 0, st, part, nparts, (int)e.n, red);
-    hipLaunchKernelGGL(pidmean_ratios<true>, 1, 256, 0, st, red, (int)e.n, out.mass, out.in_in,
-                       out.in_out, out.depth);
-  } else {
-    hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, nparts, (int)e.n, red);
-    hipLaunchKernelGGL(pidmean_ratios<false>, 1, 256, 0, st, red, (int)e.n, out.mass, out.in_in,
-                       out.in_out, out.depth);
-  }
+  hipLaunchKernelGGL(pidmean_reduce, rgrid, 256, 0, st, (const double*)part, nparts, (int)e.n, (double*)red);
+  hipLaunchKernelGGL(pidmean_ratios, 1, 256, 0, st, (const double*)red, (int)e.n, out.mass, out.in_in, out.in_out,
+                     out.depth);
   return hipGetLastError();
 }
 
@@ -1088,7 +854,7 @@ static void launch_dma(const MeanPlan& p, const pid_ensemble& e, double* part, h
 
 hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_kind,
                            const ExtractHost& exh, const pid_out& out, void* ws, hipStream_t st) {
-  if (plan.bits) return launch_u8_bits_mean(e, out, ws, st);
+  if (plan.bits) return launch_mask_bits_mean(e, iso_kind, exh, out, ws, st);
   Extract ex = __builtin_bit_cast(Extract, exh);
   Carve c(ws);
   void* part = c.take<double>((size_t)std::max(std::max(plan.grid, plan.pipe_grid), plan.dma_grid) * 2 * e.n);
@@ -1152,11 +918,11 @@ hipError_t launch_pid_mean(const MeanPlan& plan, const pid_ensemble& e, int iso_
 template <typename T>
 static void launch_linear_t(const pid_ensemble& e, int iso_kind, const Extract& ex, bool vec, const MeanPlan& p3,
                             void* coef, int tg, void* tpart, void* tbuf, double* part, hipStream_t st) {
-  if (iso_kind == PID_ISO_GAUSSIAN) launch_colsum_g<T, MODE_GAUSS, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
-  else if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
+  if (iso_kind == PID_ISO_GAUSSIAN) launch_colsum_g<T, MODE_GAUSS, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
+  else if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
   else if (iso_mode(iso_kind) == MODE_MODEL) {
-    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
-  } else launch_colsum_g<T, MODE_NONE, false, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
+    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
+  } else launch_colsum_g<T, MODE_NONE, true>(e, ex, tg, coef, tpart, tbuf, vec, st);
   if (iso_kind == PID_ISO_GAUSSIAN) dispatch_mpw<T, MODE_GAUSS>(p3, e, ex, vec, tbuf, part, st);
   else if (iso_kind == PID_ISO_STEP) dispatch_mpw<T, MODE_STEP>(p3, e, ex, vec, tbuf, part, st);
   else if (iso_mode(iso_kind) == MODE_MODEL) {
@@ -1206,7 +972,7 @@ hipError_t launch_pairs_linear(const pid_ensemble& e, int iso_kind, const Extrac
   if (err != hipSuccess) return err;
   KernelTimer tm("pidmean_finalize", st);
   dim3 rgrid((unsigned)e.n, 2);
-  hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, p3.grid, (int)e.n, red);
+  hipLaunchKernelGGL(pidmean_reduce, rgrid, 256, 0, st, part, p3.grid, (int)e.n, red);
   hipLaunchKernelGGL(pairs_linear_ratios, (int)((e.n + 255) / 256), 256, 0, st, red, inin, (int)e.n, out.mass,
                      out.in_in, out.in_out, out.depth);
   return hipGetLastError();
@@ -1269,11 +1035,11 @@ __global__ __launch_bounds__(256) void pidmean_weighted_ratios(const double* __r
 template <typename T>
 static void launch_weighted_t(const pid_ensemble& e, int iso_kind, const Extract& ex, bool vec, const MeanPlan& p3,
                               const void* coef, int tg, void* tpart, void* sbuf, double* part, hipStream_t st) {
-  if (iso_kind == PID_ISO_GAUSSIAN) launch_colsum_g<T, MODE_GAUSS, false, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
-  else if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, false, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
+  if (iso_kind == PID_ISO_GAUSSIAN) launch_colsum_g<T, MODE_GAUSS, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
+  else if (iso_kind == PID_ISO_STEP) launch_colsum_g<T, MODE_STEP, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
   else if (iso_mode(iso_kind) == MODE_MODEL) {
-    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, false, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
-  } else launch_colsum_g<T, MODE_NONE, false, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
+    if constexpr (has_models<T>()) launch_colsum_g<T, MODE_MODEL, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
+  } else launch_colsum_g<T, MODE_NONE, true>(e, ex, tg, coef, tpart, sbuf, vec, st);
   if (iso_kind == PID_ISO_GAUSSIAN) dispatch_mpw<T, MODE_GAUSS>(p3, e, ex, vec, sbuf, part, st);
   else if (iso_kind == PID_ISO_STEP) dispatch_mpw<T, MODE_STEP>(p3, e, ex, vec, sbuf, part, st);
   else if (iso_mode(iso_kind) == MODE_MODEL) {
@@ -1309,7 +1075,7 @@ hipError_t launch_pid_mean_weighted(const pid_ensemble& e, int iso_kind, const E
   if (err != hipSuccess) return err;
   KernelTimer tm("pidmean_finalize", st);
   dim3 rgrid((unsigned)e.n, 2);
-  hipLaunchKernelGGL(pidmean_reduce<false>, rgrid, 256, 0, st, part, p3.grid, (int)e.n, red);
+  hipLaunchKernelGGL(pidmean_reduce, rgrid, 256, 0, st, part, p3.grid, (int)e.n, red);
   hipLaunchKernelGGL(pidmean_weighted_ratios, 1, 256, 0, st, red, member_w, (int)e.n, out.mass, out.in_in,
                      out.in_out, out.depth);
   return hipGetLastError();

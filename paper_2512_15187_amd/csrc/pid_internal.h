@@ -59,7 +59,7 @@ struct MeanPlan {
   int dma_nwaves, dma_grid;
   size_t dma_lds;
   int unsupported;  // 1: no launch geometry keeps the exact integer sums in range
-  int bits;         // 1: U8 binary masks, packed in the first pass (launch_u8_bits_mean)
+  int bits;         // 1: binary input (U8 masks, thresholded values), packed in the first pass
 };
 MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted);
 size_t mean_workspace(const MeanPlan& p, int64_t n, int64_t m);
@@ -79,7 +79,10 @@ struct B1Plan {
 B1Plan b1_plan(int64_t n, int64_t m);
 size_t b1_workspace(const B1Plan& p, int64_t n, bool packed_copy);
 hipError_t launch_b1_mean(const pid_ensemble& e, const pid_out& out, void* ws, hipStream_t st);
-hipError_t launch_u8_bits_mean(const pid_ensemble& e, const pid_out& out, void* ws, hipStream_t st);
+// U8 0/1 masks (iso_kind PID_ISO_NONE) or thresholded values (PID_ISO_STEP):
+// packed in the first pass, then the popcount passes.
+hipError_t launch_mask_bits_mean(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, const pid_out& out,
+                                 void* ws, hipStream_t st);
 // U8 0/1 masks -> PID_B1 rows of out_ldw 32-bit words.
 hipError_t launch_pack_bits(const pid_ensemble& e, uint32_t* out, int64_t out_ldw, hipStream_t st);
 

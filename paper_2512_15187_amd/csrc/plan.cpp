@@ -172,7 +172,7 @@ constexpr int64_t kTilesPerWorkgroup = 16;
 MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted) {
   MeanPlan p{};
   p.binary = is_binary(dtype, iso_kind, weighted) ? 1 : 0;
-  if (p.binary && dtype == PID_U8) {   // packed on the fly, then the popcount passes
+  if (p.binary) {   // U8 masks or thresholded values: packed on the fly, then the popcount passes
     p.bits = 1;
     p.unsupported = b1_plan(n, m).unsupported;
     return p;
@@ -188,7 +188,7 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   // 16-byte chunk at the end of a row): waves of 32 rows, a ring of four
   // tile slots.  (For N <= 128 the tiles of eight-row waves are too small
   // per barrier; the register pipeline below is faster there.)
-  if (!p.binary && iso_kind == PID_ISO_NONE && dtype != PID_U8 && n > 128 && n <= 256 && (m * eb) % 16 == 0) {
+  if (iso_kind == PID_ISO_NONE && dtype != PID_U8 && n > 128 && n <= 256 && (m * eb) % 16 == 0) {
     const int rpw = 32;
     const int nw = (int)((n + rpw - 1) / rpw);
     const int tpp = 128 / eb;
@@ -209,7 +209,7 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   // 4 B (8 waves, 256 registers per lane), so that two buffers, the sums
   // and the addressing fit without spills.  It needs one full tile; rows
   // that are not aligned take the kernel below.
-  const bool soft = !p.binary && dtype != PID_U8 &&
+  const bool soft = dtype != PID_U8 &&
                     (iso_kind == PID_ISO_NONE || (iso_kind != PID_ISO_STEP && eb != 2));
   if (soft) {
     int mpw = 0;
@@ -249,7 +249,7 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   if (n > 32) mpw = 8;
   if (n > 64) mpw = 16;
   int nw = (int)((n + mpw - 1) / mpw);
-  const int max_waves = (eb == 4 && !p.binary) ? 16 : 8;
+  const int max_waves = (eb == 4) ? 16 : 8;
   p.two_pass = 0;
   p.groups = 1;
   if (nw > max_waves) {
@@ -265,19 +265,8 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   int64_t g = std::max<int64_t>((p.ntiles + tpw - 1) / tpw, cus * 2);
   if (p.two_pass) g = std::max<int64_t>((p.ntiles + tpw - 1) / tpw, std::max<int64_t>(1, cus * 2 / p.groups));
   if (p.groups > kMaxGridY) p.unsupported = 1;   // member groups are grid.y
-  if (p.binary) {
-    // the binary kernel sums u_i(x) s(x) <= N per point in one int32 per
-    // lane over its workgroup's tiles: tiles * PPL * N must stay below 2^31
-    const int64_t per_tile = (int64_t)ppl * n;
-    const int64_t max_tiles = (INT64_C(0x7fffffff)) / per_tile;
-    if (max_tiles < 1) {
-      p.unsupported = 1;
-    } else {
-      g = std::max<int64_t>(g, (p.ntiles + max_tiles - 1) / max_tiles);
-    }
-  }
   p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, g));
-  const int cb = p.binary ? 4 : (dtype == PID_F64 ? 8 : 4);
+  const int cb = (dtype == PID_F64) ? 8 : 4;
   p.lds_bytes = p.two_pass ? 0 : (size_t)2 * nw * tp * cb;
   return p;
 }

@@ -27,6 +27,6 @@ hipError_t launch_pid_mean_weighted(const pid_ensemble&, int, const ExtractHost&
                                     void*, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_field_max(const pid_ensemble&, double*, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_b1_mean(const pid_ensemble&, const pid_out&, void*, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_u8_bits_mean(const pid_ensemble&, const pid_out&, void*, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_mask_bits_mean(const pid_ensemble&, int, const ExtractHost&, const pid_out&, void*, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_pack_bits(const pid_ensemble&, uint32_t*, int64_t, hipStream_t) { return hipErrorNotSupported; }
 }  // namespace pidk

@@ -148,3 +148,34 @@ def test_u8_mean_any_alignment(off, m):
     wide[:, off:off + m] = B
     res = pid.pid_mean(wide.to(DEV)[:, off:off + m])
     assert_bitwise(res, oracle.binary_pid_mean(B.numpy()), keys=KEYS, label=f"u8 off={off} m={m}")
+
+
+STEP_CASES = [
+    # (n, m, dtype, side): rows 16-byte aligned (the coalesced chunk form) and
+    # not (element loads), several member groups, every stored type
+    (5, 4096, torch.float32, 1), (128, 2048 * 3, torch.float32, -1), (300, 2048 + 512, torch.float32, 1),
+    (40, 3001, torch.float32, 1), (64, 4096, torch.float64, 1), (33, 1000, torch.float64, -1),
+    (70, 8192, torch.float16, 1), (70, 4099, torch.bfloat16, -1), (50, 4096, torch.uint8, 1),
+]
+
+
+@pytest.mark.parametrize("n,m,dtype,side", STEP_CASES,
+                         ids=[f"{c[0]}x{c[1]}-{str(c[2])[6:]}-{c[3]:+d}" for c in STEP_CASES])
+def test_step_fields_mean_bitexact(n, m, dtype, side):
+    """Thresholded fields (the sharp isovalue) through the bit path: bitwise
+    the oracle's integer PID-mean of the same decisions, with values planted
+    exactly at the threshold (outside on both sides)."""
+    rng = np.random.Generator(np.random.PCG64(n * 7 + m))
+    if dtype == torch.uint8:
+        F = torch.from_numpy(rng.integers(0, 4, size=(n, m)).astype(np.uint8))
+        c = 2.0
+    else:
+        F = torch.from_numpy(rng.normal(0.5, 0.1, size=(n, m))).to(dtype)
+        F.view(-1)[:: 97] = 0.5
+        c = 0.5
+    iso = dict(kind="step", c=c, side=side)
+    res = pid.pid_mean(F.to(DEV), iso=iso)
+    B = oracle.extract(F.to(torch.float64).numpy(), iso).astype(np.uint8)
+    ref = oracle.binary_pid_mean(B)
+    assert_bitwise(res, ref, keys=KEYS, label=f"step {n}x{m} {dtype}")
+    assert_ranks(res["rank"], ref["depth"], 0)
