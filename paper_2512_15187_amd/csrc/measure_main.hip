@@ -10,7 +10,11 @@
 //                     isovalue ~ N(0.5, 0.05^2): pid_all_pairs (FP16 MFMA), the
 //                     thresholded pid_all_pairs (INT8 MFMA) and pid_mean, R times each;
 //   mean3d [R]        pid_mean on N = 64 FP16 masks on 256^3 with FP32 point
-//                     weights, R times.
+//                     weights, R times;
+//   bits [R]          binary PID-mean on N = 20000 masks on 50^3 (random 0/1
+//                     bytes), as U8 masks and packed by pid_pack_bits, R times each;
+//   fieldsbin [R]     PID-mean of the scalar-field workload thresholded at 0.5
+//                     (N = 128 FP32 fields on 128^3), R times.
 // It prints one line per mode with the bytes or the status.
 #include <hip/hip_runtime.h>
 
@@ -53,6 +57,17 @@ __global__ void fill_half_kernel(_Float16* u, size_t count) {
   h ^= h >> 16;
   h *= 2246822519u;
   u[i] = (_Float16)((float)(h >> 8) * (1.0f / 16777216.0f));
+}
+
+// 0/1 bytes from a hash of the index.
+__global__ void fill_bits_kernel(uint8_t* u, size_t count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint32_t h = (uint32_t)i * 2654435761u + 99u;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  u[i] = (uint8_t)((h >> 7) & 1u);
 }
 
 __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, size_t n4) {
@@ -211,15 +226,81 @@ int run_mean3d(int reps) {
   return 0;
 }
 
+int run_bits(int reps) {
+  const int64_t n = 20000, m = 125000;
+  const int64_t ldp = (m + 127) / 128 * 128;   // packed rows of 16-byte multiples, in points
+  uint8_t* U = nullptr;
+  uint32_t* P = nullptr;
+  if (!ok(hipMalloc(&U, (size_t)(n * m)), "hipMalloc") || !ok(hipMalloc(&P, (size_t)(n * ldp / 8)), "hipMalloc"))
+    return 1;
+  hipLaunchKernelGGL(fill_bits_kernel, dim3((unsigned)((n * m + 255) / 256)), dim3(256), 0, 0, U, (size_t)(n * m));
+  pid_ensemble e = ensemble(n, m, PID_U8, U, nullptr);
+  if (pid_pack_bits(&e, P, ldp, nullptr) != PID_OK) {
+    fprintf(stderr, "pid_pack_bits: %s\n", pid_last_error());
+    return 1;
+  }
+  pid_ensemble eb = ensemble(n, m, PID_B1, P, nullptr);
+  eb.ld = ldp;
+  pid_iso iso{PID_ISO_NONE, 1, 0.0, 0.0};
+  size_t w1 = 0, w2 = 0;
+  if (pid_workspace_size(&e, &iso, 1, 0, &w1) != PID_OK || pid_workspace_size(&eb, &iso, 1, 0, &w2) != PID_OK) {
+    fprintf(stderr, "workspace size: %s\n", pid_last_error());
+    return 1;
+  }
+  void* ws = nullptr;
+  Outs o;
+  if (!ok(hipMalloc(&ws, w1 > w2 ? w1 : w2), "hipMalloc") || !o.alloc(n)) return 1;
+  for (int r = 0; r < reps; ++r) {
+    if (pid_mean(&e, &iso, &o.mean, ws, w1, nullptr) != PID_OK || pid_mean(&eb, &iso, &o.mean, ws, w2, nullptr) != PID_OK) {
+      fprintf(stderr, "pid_mean: %s\n", pid_last_error());
+      return 1;
+    }
+  }
+  if (!ok(hipDeviceSynchronize(), "bits")) return 1;
+  printf("bits: %d x (U8, packed) pid_mean, N=%lld M=%lld\n", reps, (long long)n, (long long)m);
+  hipFree(U);
+  hipFree(P);
+  hipFree(ws);
+  return 0;
+}
+
+int run_fieldsbin(int reps) {
+  const int64_t n = 128, m = 128 * 128 * 128;
+  float* F = nullptr;
+  if (!ok(hipMalloc(&F, (size_t)(n * m) * 4), "hipMalloc")) return 1;
+  hipLaunchKernelGGL(fill_field_kernel, dim3((unsigned)((n * m + 255) / 256)), dim3(256), 0, 0, F, (size_t)(n * m));
+  pid_ensemble e = ensemble(n, m, PID_F32, F, nullptr);
+  pid_iso step{PID_ISO_STEP, 1, 0.5, 0.0};
+  size_t wsb = 0;
+  if (pid_workspace_size(&e, &step, 1, 0, &wsb) != PID_OK) {
+    fprintf(stderr, "workspace size: %s\n", pid_last_error());
+    return 1;
+  }
+  void* ws = nullptr;
+  Outs o;
+  if (!ok(hipMalloc(&ws, wsb), "hipMalloc") || !o.alloc(n)) return 1;
+  for (int r = 0; r < reps; ++r) {
+    if (pid_mean(&e, &step, &o.mean, ws, wsb, nullptr) != PID_OK) {
+      fprintf(stderr, "pid_mean: %s\n", pid_last_error());
+      return 1;
+    }
+  }
+  if (!ok(hipDeviceSynchronize(), "fieldsbin")) return 1;
+  printf("fieldsbin: %d x pid_mean of thresholded fields, N=%lld M=%lld FP32\n", reps, (long long)n, (long long)m);
+  hipFree(F);
+  hipFree(ws);
+  return 0;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
-  const char* modes[] = {"copy", "both", "fields", "mean3d"};
+  const char* modes[] = {"copy", "both", "fields", "mean3d", "bits", "fieldsbin"};
   int mode = -1;
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 6; ++k)
     if (argc >= 2 && strcmp(argv[1], modes[k]) == 0) mode = k;
   if (mode < 0) {
-    fprintf(stderr, "usage: %s copy|both|fields|mean3d [reps] [copies]\n", argv[0]);
+    fprintf(stderr, "usage: %s copy|both|fields|mean3d|bits|fieldsbin [reps] [copies]\n", argv[0]);
     return 2;
   }
   const int reps = argc > 2 ? atoi(argv[2]) : 3;
@@ -232,6 +313,8 @@ int main(int argc, char** argv) {
     case 0: return run_copy(reps);
     case 1: return run_both(reps, copies);
     case 2: return run_fields(reps);
-    default: return run_mean3d(reps);
+    case 3: return run_mean3d(reps);
+    case 4: return run_bits(reps);
+    default: return run_fieldsbin(reps);
   }
 }
