@@ -68,8 +68,14 @@ __device__ __forceinline__ uint32_t chunk_word_u8(const uint8_t* row, int64_t c,
   const int a = (int)(reinterpret_cast<uintptr_t>(cp) & 15);
   const uint4* bp = reinterpret_cast<const uint4*>(cp - a);
   const int64_t rem = m - c * 2048;   // points of the row from the chunk's first one
-  const uint32_t hA = (16 * lane - a < rem) ? nz16<FOLD>(bp[lane]) : 0u;
-  const uint32_t hB = (16 * (64 + lane) - a < rem) ? nz16<FOLD>(bp[64 + lane]) : 0u;
+  uint32_t hA, hB;
+  if (rem >= 2048) {   // a full chunk (wave-uniform): no guards on the loads
+    hA = nz16<FOLD>(bp[lane]);
+    hB = nz16<FOLD>(bp[64 + lane]);
+  } else {
+    hA = (16 * lane - a < rem) ? nz16<FOLD>(bp[lane]) : 0u;
+    hB = (16 * (64 + lane) - a < rem) ? nz16<FOLD>(bp[64 + lane]) : 0u;
+  }
   uint32_t lo = hA, hi = hB;
   if (a != 0) {   // wave-uniform: shift in the neighbours' low bits
     const uint32_t hC = (lane == 63 && 16 * 128 - a < rem) ? nz16<FOLD>(bp[128]) : 0u;
