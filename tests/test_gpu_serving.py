@@ -181,3 +181,40 @@ def test_over_budget_and_cancel(pool):
     th.start()
     th.join(timeout=60)
     assert not th.is_alive() and srv.h is None
+
+
+def test_binary_requests_served(pool):
+    """Binary PID-mean requests of the three input forms (U8 masks, bit-packed
+    masks, thresholded FP16 masks) served beside soft requests: bitwise the
+    oracle's integer results and the same call run alone."""
+    srv = pid.PidServer(256 << 20, max_slots=3)
+    B = synth.ellipsoids_3d(300, 40, 21, device=DEV)                  # U8 0/1, 64,000 points
+    P = pid.pid_pack_bits(B[:200])
+    F = pool[("2d", 128)][:90]
+    step = dict(kind="step", c=0.5, side=1)
+    reqs = [(B, None), (P, None), (F, step), (B[:37], None), (pool[("3d", 48)][:30], None)]
+    jobs = []
+    for U, iso in reqs:
+        t, out = srv.pid_submit(U, variant="mean", iso=iso)
+        jobs.append((U, iso, t, out))
+    for U, iso, t, out in jobs:
+        assert srv.pid_wait(t) == pid.PID_OK, srv.last_error()
+    torch.cuda.synchronize()
+    for U, iso, t, out in jobs:
+        alone = pid.pid_mean(U, iso=iso)
+        for key in KEYS:
+            assert torch.equal(out[key], alone[key]), key
+        if isinstance(U, pid.PackedMasks):
+            bits = B[:200].cpu().numpy()
+        elif iso is not None:
+            bits = oracle.extract(U.cpu().to(torch.float64).numpy(), iso).astype(np.uint8)
+        elif U.dtype == torch.uint8:
+            bits = U.cpu().numpy()
+        else:
+            _check_against_oracle(U, "mean", out, "served soft mean")
+            continue
+        ref = oracle.binary_pid_mean(bits)
+        for key in ("mass", "in_in", "in_out", "depth"):
+            assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+        srv.release(t)
+    srv.pid_server_destroy()
