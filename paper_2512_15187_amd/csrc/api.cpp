@@ -132,21 +132,25 @@ pid_status resolve_scheme(const pid_ensemble* e, int kind, int gemm, int* scheme
 }
 
 // Extra workspace after the kernels' own: depth scratch (for ranks; two
-// arrays for the combined call) and the validation flag.
+// arrays for the combined call), the validation flag, and the scratch of the
+// sorting ranks (more than 2048 members).
 size_t extra_bytes(int64_t n, int ndepth = 1) {
-  return ((size_t)n * 8 * ndepth + 255) / 256 * 256 + 256 + 256;
+  return ((size_t)n * 8 * ndepth + 255) / 256 * 256 + 256 + 256 + (size_t)ndepth * pidk::rank_scratch_bytes(n);
 }
 
 struct Extras {
   double* depth;
   unsigned int* flag;
+  void* rank_scratch;   // nullptr when the ranks need none
 };
 
 Extras carve_extras(void* ws, size_t kernel_bytes, int64_t n, int ndepth = 1) {
   char* base = static_cast<char*>(ws) + ((kernel_bytes + 255) / 256) * 256;
   Extras x;
   x.depth = reinterpret_cast<double*>(base);
-  x.flag = reinterpret_cast<unsigned int*>(base + ((size_t)n * 8 * ndepth + 255) / 256 * 256);
+  const size_t dbytes = ((size_t)n * 8 * ndepth + 255) / 256 * 256;
+  x.flag = reinterpret_cast<unsigned int*>(base + dbytes);
+  x.rank_scratch = pidk::rank_scratch_bytes(n) ? base + dbytes + 256 : nullptr;
   return x;
 }
 
@@ -265,11 +269,11 @@ pid_status run_both(const pid_ensemble* ens, const pid_iso* iso, int gemm, const
   hipError_t err = pidk::launch_pid_pairs(p, *ens, kind, ex, po, ws, st, &mo);
   if (err != hipSuccess) return hip_fail(err, "pid_both launch");
   if (rank_p && rank_m) {
-    err = pidk::launch_rank2(po.depth, po.rank, po.order, mo.depth, mo.rank, mo.order, ens->n, st);
+    err = pidk::launch_rank2(po.depth, po.rank, po.order, mo.depth, mo.rank, mo.order, ens->n, st, x.rank_scratch);
     if (err != hipSuccess) return hip_fail(err, "rank launch");
   } else if (rank_p || rank_m) {
     const pid_out& r = rank_p ? po : mo;
-    err = pidk::launch_rank(r.depth, ens->n, r.rank, r.order, st);
+    err = pidk::launch_rank(r.depth, ens->n, r.rank, r.order, st, x.rank_scratch);
     if (err != hipSuccess) return hip_fail(err, "rank launch");
   }
   return PID_OK;
@@ -317,7 +321,7 @@ pid_status run(int variant, const pid_ensemble* ens, const pid_iso* iso, int gem
   if (err != hipSuccess)
     return hip_fail(err, variant == 0 ? "pid_all_pairs launch" : (variant == 3 ? "pid_pairs_depths launch" : "pid_mean launch"));
   if (want_rank) {
-    err = pidk::launch_rank(o.depth, ens->n, o.rank, o.order, st);
+    err = pidk::launch_rank(o.depth, ens->n, o.rank, o.order, st, x.rank_scratch);
     if (err != hipSuccess) return hip_fail(err, "rank launch");
   }
   return PID_OK;
@@ -378,7 +382,7 @@ pid_status pid_mean_weighted(const pid_ensemble* ens, const pid_iso* iso, const 
   hipError_t err = pidk::launch_pid_mean_weighted(*ens, kind, make_extract(iso), member_w, o, workspace, st);
   if (err != hipSuccess) return hip_fail(err, "pid_mean_weighted launch");
   if (want_rank) {
-    err = pidk::launch_rank(o.depth, ens->n, o.rank, o.order, st);
+    err = pidk::launch_rank(o.depth, ens->n, o.rank, o.order, st, x.rank_scratch);
     if (err != hipSuccess) return hip_fail(err, "rank launch");
   }
   return PID_OK;

@@ -1,6 +1,8 @@
 // Standalone extraction (Sec. 3.5), ranks by depth (Sec. 5.1) and the opt-in
 // value-range check of the inputs.
 #include "device_common.h"
+
+#include <climits>
 #include "pid_internal.h"
 #include "pid_timing.h"
 
@@ -215,25 +217,137 @@ __global__ __launch_bounds__(256) void rank_lds_kernel(RankArgs ra, int n) {
   }
 }
 
-static void launch_rank_kernel(const RankArgs& ra, int64_t n, int arrays, hipStream_t st) {
+// Ranks by sorting, for more than 2048 members when the caller's workspace
+// provides the scratch (rank_scratch_bytes per depth array).  The order of
+// the definition, "j comes before i" iff d_j > d_i or (d_j == d_i and j < i),
+// is the ascending order of the pairs (key(d_j), j) with key(d) decreasing in
+// d (the IEEE bits mapped to an order-preserving unsigned integer and
+// complemented; -0 is taken as +0).  Tiles of 2048 pairs are sorted in LDS by
+// a bitonic network (rank_tile_sort); then for every member and tile a
+// binary search counts the tile's pairs below the member's (rank_tile_count,
+// integer atomics, so the total does not depend on their order); the count
+// is the rank.
+constexpr int kSortTile = 2048;
+
+__device__ __forceinline__ unsigned long long depth_key(double d) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(d + 0.0);
+  const unsigned long long asc = (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+  return ~asc;
+}
+
+struct RankSort {
+  unsigned long long* key[2];
+  int32_t* idx[2];
+  int32_t* cnt[2];
+};
+
+__global__ __launch_bounds__(1024) void rank_tile_sort(RankArgs ra, RankSort rs, int n) {
+  __shared__ unsigned long long k[kSortTile];
+  __shared__ int32_t x[kSortTile];
+  const int a = blockIdx.y, t = threadIdx.x;
+  const double* __restrict__ d = ra.d[a];
+  const int base = blockIdx.x * kSortTile;
+  for (int e = t; e < kSortTile; e += 1024) {
+    const int i = base + e;
+    k[e] = i < n ? depth_key(d[i]) : ~0ull;      // padding sorts last
+    x[e] = i < n ? i : INT_MAX;
+    if (i < n) rs.cnt[a][i] = 0;
+  }
+  __syncthreads();
+  for (int size = 2; size <= kSortTile; size <<= 1) {
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      const int lo = (t / j) * 2 * j + (t % j), hi = lo + j;
+      const bool up = (lo & size) == 0;
+      const unsigned long long kl = k[lo], kh = k[hi];
+      const int xl = x[lo], xh = x[hi];
+      const bool gt = kl > kh || (kl == kh && xl > xh);
+      if (gt == up) {
+        k[lo] = kh; k[hi] = kl;
+        x[lo] = xh; x[hi] = xl;
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = t; e < kSortTile; e += 1024) {
+    rs.key[a][base + e] = k[e];
+    rs.idx[a][base + e] = x[e];
+  }
+}
+
+// Thread (member i, tile blockIdx.y): the tile's pairs below (key_i, i).
+__global__ __launch_bounds__(256) void rank_tile_count(RankArgs ra, RankSort rs, int n, int arrays) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int tile = blockIdx.y;
+  for (int a = 0; a < arrays; ++a) {
+    const unsigned long long ki = depth_key(ra.d[a][i]);
+    const unsigned long long* __restrict__ K = rs.key[a] + (size_t)tile * kSortTile;
+    const int32_t* __restrict__ X = rs.idx[a] + (size_t)tile * kSortTile;
+    int lo = 0, len = kSortTile;   // first position whose pair is not below (ki, i)
+    while (len > 0) {
+      const int half = len >> 1, mid = lo + half;
+      const unsigned long long km = K[mid];
+      if (km < ki || (km == ki && X[mid] < i)) {
+        lo = mid + 1;
+        len -= half + 1;
+      } else {
+        len = half;
+      }
+    }
+    if (lo) atomicAdd(&rs.cnt[a][i], lo);
+  }
+}
+
+__global__ __launch_bounds__(256) void rank_from_count(RankArgs ra, RankSort rs, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= n) return;
+  const int r = rs.cnt[a][i];
+  if (ra.rank[a]) ra.rank[a][i] = r;
+  if (ra.order[a]) ra.order[a][r] = i;
+}
+
+static RankSort carve_rank_sort(void* scratch, int64_t n, int arrays) {
+  RankSort rs{};
+  const size_t per = rank_scratch_bytes(n);
+  for (int a = 0; a < arrays; ++a) {
+    Carve c(static_cast<char*>(scratch) + (size_t)a * per);
+    const size_t tiles = (size_t)((n + kSortTile - 1) / kSortTile) * kSortTile;
+    rs.key[a] = c.take<unsigned long long>(tiles);
+    rs.idx[a] = c.take<int32_t>(tiles);
+    rs.cnt[a] = c.take<int32_t>((size_t)n);
+  }
+  return rs;
+}
+
+static void launch_rank_kernel(const RankArgs& ra, int64_t n, int arrays, hipStream_t st, void* scratch) {
+  if (n > 2048 && scratch) {
+    const RankSort rs = carve_rank_sort(scratch, n, arrays);
+    const unsigned nb = (unsigned)((n + kSortTile - 1) / kSortTile);
+    hipLaunchKernelGGL(rank_tile_sort, dim3(nb, arrays), 1024, 0, st, ra, rs, (int)n);
+    hipLaunchKernelGGL(rank_tile_count, dim3((unsigned)((n + 255) / 256), nb), 256, 0, st, ra, rs, (int)n, arrays);
+    hipLaunchKernelGGL(rank_from_count, dim3((unsigned)((n + 255) / 256), arrays), 256, 0, st, ra, rs, (int)n);
+    return;
+  }
   if (n <= 2048)
     hipLaunchKernelGGL((rank_kernel<1>), dim3((unsigned)((n + 3) / 4), arrays), 256, 0, st, ra, (int)n);
   else
     hipLaunchKernelGGL(rank_lds_kernel, dim3((unsigned)((n + 63) / 64), arrays), 256, 0, st, ra, (int)n);
 }
 
-hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st) {
+hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st,
+                       void* scratch) {
   KernelTimer tm("rank", st);
   RankArgs ra{{depth, nullptr}, {rank, nullptr}, {order, nullptr}};
-  launch_rank_kernel(ra, n, 1, st);
+  launch_rank_kernel(ra, n, 1, st, scratch);
   return hipGetLastError();
 }
 
 hipError_t launch_rank2(const double* d0, int32_t* rank0, int32_t* order0, const double* d1, int32_t* rank1,
-                        int32_t* order1, int64_t n, hipStream_t st) {
+                        int32_t* order1, int64_t n, hipStream_t st, void* scratch) {
   KernelTimer tm("rank", st);
   RankArgs ra{{d0, d1}, {rank0, rank1}, {order0, order1}};
-  launch_rank_kernel(ra, n, 2, st);
+  launch_rank_kernel(ra, n, 2, st, scratch);
   return hipGetLastError();
 }
 

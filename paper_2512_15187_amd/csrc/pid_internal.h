@@ -136,10 +136,18 @@ hipError_t launch_pid_pairs(const PairsPlan& p, const pid_ensemble& e, int iso_k
 // ---------------------------------------------------------------- misc
 hipError_t launch_extract(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, void* u_out,
                           int out_dtype, hipStream_t st);
-hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st);
+// Scratch bytes per depth array of the sorting ranks (0: n <= 2048, ranked
+// directly).
+size_t rank_scratch_bytes(int64_t n);
+// Ranks (and order) of depth; with scratch (rank_scratch_bytes(n) bytes per
+// array) more than 2048 members are ranked by sorting, otherwise by direct
+// comparison.
+hipError_t launch_rank(const double* depth, int64_t n, int32_t* rank, int32_t* order, hipStream_t st,
+                       void* scratch = nullptr);
 // Both rankings of pid_both in one launch.
 hipError_t launch_rank2(const double* d0, int32_t* rank0, int32_t* order0, const double* d1, int32_t* rank1,
-                        int32_t* order1, int64_t n, hipStream_t st);
+                        int32_t* order1, int64_t n, hipStream_t st,
+                        void* scratch = nullptr);
 // Contour-boxplot bands: one byte per point (pid_bands).
 hipError_t launch_bands(const pid_ensemble& e, int iso_kind, const ExtractHost& ex, const int32_t* order,
                         int64_t k_inner, int64_t k_outer, double threshold, uint8_t* out, hipStream_t st);

@@ -364,4 +364,15 @@ size_t mean_weighted_workspace(int64_t n, int64_t m, int dtype) {
   return c.off + 256;
 }
 
+// Sorting ranks: tiles of 2048 (key, index) pairs and a count per member.
+size_t rank_scratch_bytes(int64_t n) {
+  if (n <= 2048) return 0;
+  Carve c(nullptr);
+  const size_t tiles = (size_t)((n + 2047) / 2048) * 2048;
+  c.take<unsigned long long>(tiles);
+  c.take<int32_t>(tiles);
+  c.take<int32_t>((size_t)n);
+  return (c.off + 255) / 256 * 256;
+}
+
 }  // namespace pidk

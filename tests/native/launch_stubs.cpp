@@ -16,8 +16,8 @@ hipError_t launch_pid_pairs(const PairsPlan&, const pid_ensemble&, int, const Ex
 hipError_t launch_extract(const pid_ensemble&, int, const ExtractHost&, void*, int, hipStream_t) {
   return hipErrorNotSupported;
 }
-hipError_t launch_rank(const double*, int64_t, int32_t*, int32_t*, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_rank2(const double*, int32_t*, int32_t*, const double*, int32_t*, int32_t*, int64_t, hipStream_t) {
+hipError_t launch_rank(const double*, int64_t, int32_t*, int32_t*, hipStream_t, void*) { return hipErrorNotSupported; }
+hipError_t launch_rank2(const double*, int32_t*, int32_t*, const double*, int32_t*, int32_t*, int64_t, hipStream_t, void*) {
   return hipErrorNotSupported;
 }
 hipError_t launch_bands(const pid_ensemble&, int, const ExtractHost&, const int32_t*, int64_t, int64_t, double,

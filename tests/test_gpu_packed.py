@@ -179,3 +179,18 @@ def test_step_fields_mean_bitexact(n, m, dtype, side):
     ref = oracle.binary_pid_mean(B)
     assert_bitwise(res, ref, keys=KEYS, label=f"step {n}x{m} {dtype}")
     assert_ranks(res["rank"], ref["depth"], 0)
+
+
+@pytest.mark.parametrize("n,m", [(2049, 50), (10000, 40), (30000, 24)])
+def test_sorted_ranks_with_ties(n, m):
+    """Ranks of more than 2048 members come from the sorting path of the
+    library calls: on binary masks of few points many members tie, and the
+    ranks and order must equal the oracle's (ties by index) exactly."""
+    B = synth.random_binary(n, m, n + m)
+    res = pid.pid_mean(B.to(DEV))
+    ref = oracle.binary_pid_mean(B.numpy())
+    r, o = oracle.rank_order(ref["depth"])
+    assert np.array_equal(res["rank"].cpu().numpy(), r)
+    assert np.array_equal(res["order"].cpu().numpy(), o)
+    P = pid.pid_mean(pid.pid_pack_bits(B.to(DEV)))
+    assert torch.equal(P["rank"], res["rank"]) and torch.equal(P["order"], res["order"])

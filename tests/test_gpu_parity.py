@@ -296,8 +296,9 @@ def test_rank_entry_point():
 
 @pytest.mark.parametrize("n", [2048, 2049, 5003, 40000])
 def test_rank_large(n):
-    """Large ensembles (eight members per wave): exact ranks, with ties (depths
-    drawn from 600 values) broken by the member index."""
+    """pid_rank on large ensembles (no workspace: the comparison kernel, depth
+    tiles in LDS): exact ranks, with ties (depths drawn from 600 values) broken
+    by the member index."""
     rng = np.random.Generator(np.random.PCG64(n))
     d = torch.from_numpy(rng.integers(0, 600, size=n) / 600.0)
     rank, order = pid.pid_rank(_dev(d))
