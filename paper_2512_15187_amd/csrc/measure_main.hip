@@ -14,7 +14,10 @@
 //   bits [R]          binary PID-mean on N = 20000 masks on 50^3 (random 0/1
 //                     bytes), as U8 masks and packed by pid_pack_bits, R times each;
 //   fieldsbin [R]     PID-mean of the scalar-field workload thresholded at 0.5
-//                     (N = 128 FP32 fields on 128^3), R times.
+//                     (N = 128 FP32 fields on 128^3), R times;
+//   peaks [R]         achievable peaks, timed with events (best of R runs): a
+//                     copy of 1 GiB, a read of 1 GiB, and a loop of FP16 MFMA
+//                     32x32x16 instructions on registers.
 // It prints one line per mode with the bytes or the status.
 #include <hip/hip_runtime.h>
 
@@ -68,6 +71,40 @@ __global__ void fill_bits_kernel(uint8_t* u, size_t count) {
   h *= 2246822519u;
   h ^= h >> 13;
   u[i] = (uint8_t)((h >> 7) & 1u);
+}
+
+// Reads n4 16-byte vectors, grid-strided, and writes one sum per thread.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void read_kernel(const f32x4_t* __restrict__ src, size_t n4, float* __restrict__ out) {
+  float s = 0.f;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+    const f32x4_t v = __builtin_nontemporal_load(src + i);
+    s += v[0] + v[1] + v[2] + v[3];
+  }
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+// Four independent accumulators of v_mfma_f32_32x32x16_f16 per wave, iters
+// rounds; one value per thread is written so that nothing is folded away.
+__global__ __launch_bounds__(256) void mfma_loop_kernel(float* __restrict__ out, int iters) {
+  half8_t a, b;
+  for (int k = 0; k < 8; ++k) {
+    a[k] = (_Float16)((threadIdx.x + k) & 7);
+    b[k] = (_Float16)((threadIdx.x * 3 + k) & 5);
+  }
+  float16_t c0 = {}, c1 = {}, c2 = {}, c3 = {};
+  for (int i = 0; i < iters; ++i) {
+    c0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c3, 0, 0, 0);
+  }
+  float s = 0.f;
+  for (int r = 0; r < 16; ++r) s += c0[r] + c1[r] + c2[r] + c3[r];
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
 __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, size_t n4) {
@@ -292,15 +329,58 @@ int run_fieldsbin(int reps) {
   return 0;
 }
 
+int run_peaks(int reps) {
+  const size_t bytes = (size_t)1 << 30, count = bytes / 4;
+  float *src = nullptr, *dst = nullptr, *out = nullptr;
+  const int blocks = 256 * 32;
+  if (!ok(hipMalloc(&src, bytes), "hipMalloc") || !ok(hipMalloc(&dst, bytes), "hipMalloc") ||
+      !ok(hipMalloc(&out, (size_t)blocks * 256 * 4), "hipMalloc"))
+    return 1;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, 0, src, count);
+  hipEvent_t e0, e1;
+  if (!ok(hipEventCreate(&e0), "event") || !ok(hipEventCreate(&e1), "event")) return 1;
+  auto best_ms = [&](auto launch) -> float {
+    float best = 1e30f;
+    for (int r = 0; r < reps + 1; ++r) {   // (the first run warms up)
+      hipEventRecord(e0, 0);
+      launch();
+      hipEventRecord(e1, 0);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0 && ms < best) best = ms;
+    }
+    return best;
+  };
+  const float t_copy = best_ms([&] {
+    hipLaunchKernelGGL(copy_kernel, dim3(8192), dim3(256), 0, 0, reinterpret_cast<const float4*>(src),
+                       reinterpret_cast<float4*>(dst), count / 4);
+  });
+  const float t_read = best_ms([&] {
+    hipLaunchKernelGGL(read_kernel, dim3(blocks), dim3(256), 0, 0, reinterpret_cast<const f32x4_t*>(src), count / 4, out);
+  });
+  const int iters = 20000;
+  const int mblocks = 256 * 8;   // 4 waves each: 32 waves per CU
+  const float t_mfma = best_ms([&] { hipLaunchKernelGGL(mfma_loop_kernel, dim3(mblocks), dim3(256), 0, 0, out, iters); });
+  if (!ok(hipDeviceSynchronize(), "peaks")) return 1;
+  const double flops = (double)mblocks * 4 * 4 * iters * (2.0 * 32 * 32 * 16);
+  printf("peaks: copy %.1f GB/s (read + write of 2^30 B each), read %.1f GB/s, FP16 MFMA %.1f TFLOP/s (best of %d)\n",
+         2.0 * bytes / (t_copy * 1e-3) / 1e9, bytes / (t_read * 1e-3) / 1e9, flops / (t_mfma * 1e-3) / 1e12, reps);
+  hipFree(src);
+  hipFree(dst);
+  hipFree(out);
+  return 0;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
-  const char* modes[] = {"copy", "both", "fields", "mean3d", "bits", "fieldsbin"};
+  const char* modes[] = {"copy", "both", "fields", "mean3d", "bits", "fieldsbin", "peaks"};
   int mode = -1;
-  for (int k = 0; k < 6; ++k)
+  for (int k = 0; k < 7; ++k)
     if (argc >= 2 && strcmp(argv[1], modes[k]) == 0) mode = k;
   if (mode < 0) {
-    fprintf(stderr, "usage: %s copy|both|fields|mean3d|bits|fieldsbin [reps] [copies]\n", argv[0]);
+    fprintf(stderr, "usage: %s copy|both|fields|mean3d|bits|fieldsbin|peaks [reps] [copies]\n", argv[0]);
     return 2;
   }
   const int reps = argc > 2 ? atoi(argv[2]) : 3;
@@ -315,6 +395,7 @@ int main(int argc, char** argv) {
     case 2: return run_fields(reps);
     case 3: return run_mean3d(reps);
     case 4: return run_bits(reps);
-    default: return run_fieldsbin(reps);
+    case 5: return run_fieldsbin(reps);
+    default: return run_peaks(reps);
   }
 }
