@@ -104,8 +104,9 @@ static void rejects() {
   CHECK(pid_abi_version() == 3);
 }
 
-// Every shape, dtype, model, weighting, variant and scheme: a status and, when
-// accepted, a size that covers at least the per-member outputs.
+// Every shape, dtype (bit-packed masks included), model, weighting, variant and
+// scheme: a status and, when accepted, a size that covers at least the
+// per-member outputs.
 static void plans() {
   const int64_t ns[] = {1, 2, 31, 32, 33, 64, 127, 128, 129, 255, 256, 257, 1000, 4096, 20000,
                         32768, 32769, 100000, INT64_C(1) << 22, INT64_C(1) << 30};
@@ -116,10 +117,11 @@ static void plans() {
   int ok = 0, refused = 0;
   for (int64_t n : ns)
     for (int64_t m : ms)
-      for (int dt = 0; dt <= 4; ++dt)
+      for (int dt = 0; dt <= 5; ++dt)
         for (const pid_iso& iso : isos)
           for (int wtd = 0; wtd < 2; ++wtd) {
             pid_ensemble e = ens(n, m, dt, (const void*)0x1000, wtd ? (const float*)0x2000 : nullptr);
+            if (dt == PID_B1) e.ld = (m + 31) / 32 * 32;   // bit-packed rows: whole 32-bit words
             for (int variant = 0; variant < 5; ++variant)
               for (int g = 0; g <= 6; ++g) {
                 if (variant != 0 && variant != 2 && g) continue;
