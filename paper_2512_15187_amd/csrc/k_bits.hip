@@ -218,14 +218,17 @@ __global__ __launch_bounds__(256) void pack_bits_kernel(const uint8_t* __restric
 // ---------------------------------------------------------------- pass 1
 constexpr int kB1Group = 255;   // members per group of the column counts (8 planes)
 
-// U8 input (values 0 or 1).  Block = one wave for one chunk (blockIdx.x) and
-// one member group (blockIdx.y): packs the group's rows of the chunk into pk
-// and writes the 8 count planes of the group into gpart[g][k][w] (row
-// stride Wp).
-__global__ __launch_bounds__(64) void u8_count_pack_kernel(const uint8_t* __restrict__ U, int64_t ld, int n,
-                                                           int64_t m, int chunk, uint32_t* __restrict__ pk,
-                                                           int64_t ldp, int64_t Wp, uint32_t* __restrict__ gpart) {
-  const int lane = threadIdx.x;
+// U8 input (values 0 or 1).  Block = four waves on one chunk (blockIdx.x)
+// and one member group (blockIdx.y): wave q packs the group's rows q, q + 4,
+// ... of the chunk into pk and counts them (at most 64: 7 bits of its 8
+// planes); waves 1-3 pass their planes through LDS and wave 0 adds them
+// (bit-sliced ripple-carry, in wave order) into gpart[g][k][w] (row stride
+// Wp).
+__global__ __launch_bounds__(256) void u8_count_pack_kernel(const uint8_t* __restrict__ U, int64_t ld, int n,
+                                                            int64_t m, int chunk, uint32_t* __restrict__ pk,
+                                                            int64_t ldp, int64_t Wp, uint32_t* __restrict__ gpart) {
+  __shared__ uint32_t red[3][8][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t c = blockIdx.x;
   const int g = blockIdx.y;
   const int64_t W = (m + 31) / 32;
@@ -234,31 +237,49 @@ __global__ __launch_bounds__(64) void u8_count_pack_kernel(const uint8_t* __rest
   uint32_t P[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) P[k] = 0u;
-  int i = i0;
-  for (; i + 3 < i1; i += 4) {   // four rows in flight
+  int i = i0 + wave;
+  for (; i + 12 < i1; i += 16) {   // four rows in flight
     uint32_t wd[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wd[q] = chunk_word_u8<false>(U + (int64_t)(i + q) * ld, c, m, lane);
+    for (int q = 0; q < 4; ++q) wd[q] = chunk_word_u8<false>(U + (int64_t)(i + 4 * q) * ld, c, m, lane);
 #pragma unroll
     for (int q = 0; q < 4; ++q) count_add(P, wd[q]);
     if (wi < W) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) pk[(int64_t)(i + q) * ldp + wi] = wd[q];
+      for (int q = 0; q < 4; ++q) pk[(int64_t)(i + 4 * q) * ldp + wi] = wd[q];
     }
   }
-  for (; i < i1; ++i) {
+  for (; i < i1; i += 4) {
     const uint32_t w0 = chunk_word_u8<false>(U + (int64_t)i * ld, c, m, lane);
     count_add(P, w0);
     if (wi < W) pk[(int64_t)i * ldp + wi] = w0;
   }
-  if (wi < W) {
+  if (wave > 0) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) gpart[((int64_t)g * 8 + k) * Wp + wi] = P[k];
+    for (int k = 0; k < 8; ++k) red[wave - 1][k][lane] = P[k];
   }
+  __syncthreads();
+  if (wave != 0 || wi >= W) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    uint32_t cy = 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {   // counts of at most 255 in all: 8 planes
+      const uint32_t a = red[w][k][lane];
+      const uint32_t x = P[k] ^ a;
+      const uint32_t sum = x ^ cy;
+      cy = (P[k] & a) | (cy & x);
+      P[k] = sum;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) gpart[((int64_t)g * 8 + k) * Wp + wi] = P[k];
 }
 
-// Thresholded fields: as u8_count_pack_kernel, with the words formed by
-// chunk_word_step (ALIGNED: rows 16-byte aligned) or element by element.
+// Thresholded fields: packs and counts as u8_count_pack_kernel did with one
+// wave per block (the wave takes all rows of the group), with the words
+// formed by chunk_word_step (ALIGNED: rows 16-byte aligned) or element by
+// element.
 template <typename T, bool ALIGNED>
 __global__ __launch_bounds__(64) void step_count_pack_kernel(const T* __restrict__ U, int64_t ld, int n, int64_t m,
                                                              Extract ex, int chunk, uint32_t* __restrict__ pk,
@@ -336,15 +357,19 @@ __device__ __forceinline__ Words<V> load_words(const uint32_t* row, int64_t w0, 
   return r;
 }
 
-// Packed input.  Block = one wave; lane holds V consecutive words from
-// (blockIdx.x * 64 + lane) * V; member group blockIdx.y.  Bits past m in the
-// last word are masked off.
+// Packed input.  Block = four waves on V consecutive words per lane from
+// (blockIdx.x * 64 + lane) * V and member group blockIdx.y: wave q counts
+// the group's rows q, q + 4, ... (at most 64, so 7 bits of its 8 planes),
+// waves 1-3 pass their planes through LDS and wave 0 adds them (bit-sliced
+// ripple-carry, in wave order).  Bits past m in the last word are masked off.
 template <int V>
-__global__ __launch_bounds__(64) void b1_count_kernel(const uint32_t* __restrict__ U, int64_t ldw, int n, int64_t W,
-                                                      uint32_t lastmask, int chunk, int64_t Wp,
-                                                      uint32_t* __restrict__ gpart) {
-  const int64_t w0 = ((int64_t)blockIdx.x * 64 + threadIdx.x) * V;
-  if (w0 >= W) return;   // (no cross-lane operation in this kernel)
+__global__ __launch_bounds__(256) void b1_count_kernel(const uint32_t* __restrict__ U, int64_t ldw, int n, int64_t W,
+                                                       uint32_t lastmask, int chunk, int64_t Wp,
+                                                       uint32_t* __restrict__ gpart) {
+  __shared__ uint32_t red[3][8][64 * V];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t w0 = ((int64_t)blockIdx.x * 64 + lane) * V;
+  const bool live = w0 < W;   // (no early return: a barrier follows)
   const int g = blockIdx.y;
   const int i0 = g * chunk, i1 = min(n, i0 + chunk);
   uint32_t mask[V];
@@ -355,21 +380,45 @@ __global__ __launch_bounds__(64) void b1_count_kernel(const uint32_t* __restrict
   for (int q = 0; q < V; ++q)
 #pragma unroll
     for (int k = 0; k < 8; ++k) P[q][k] = 0u;
-  int i = i0;
-  for (; i + 3 < i1; i += 4) {   // four rows in flight
-    Words<V> a[4];
+  if (live) {
+    int i = i0 + wave;
+    for (; i + 12 < i1; i += 16) {   // four rows in flight
+      Words<V> a[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = load_words<V>(U + (int64_t)(i + r) * ldw, w0, W);
+      for (int r = 0; r < 4; ++r) a[r] = load_words<V>(U + (int64_t)(i + 4 * r) * ldw, w0, W);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int q = 0; q < V; ++q) count_add(P[q], a[r].v[q] & mask[q]);
+        for (int q = 0; q < V; ++q) count_add(P[q], a[r].v[q] & mask[q]);
+    }
+    for (; i < i1; i += 4) {
+      const Words<V> a = load_words<V>(U + (int64_t)i * ldw, w0, W);
+#pragma unroll
+      for (int q = 0; q < V; ++q) count_add(P[q], a.v[q] & mask[q]);
+    }
   }
-  for (; i < i1; ++i) {
-    const Words<V> a = load_words<V>(U + (int64_t)i * ldw, w0, W);
+  if (wave > 0) {
 #pragma unroll
-    for (int q = 0; q < V; ++q) count_add(P[q], a.v[q] & mask[q]);
+    for (int q = 0; q < V; ++q)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) red[wave - 1][k][lane * V + q] = P[q][k];
   }
+  __syncthreads();
+  if (wave != 0 || !live) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      uint32_t c = 0u;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {   // counts of at most 255 in all: 8 planes
+        const uint32_t a = red[w][k][lane * V + q];
+        const uint32_t x = P[q][k] ^ a;
+        const uint32_t sum = x ^ c;
+        c = (P[q][k] & a) | (c & x);
+        P[q][k] = sum;
+      }
+    }
 #pragma unroll
   for (int q = 0; q < V; ++q)
     if (w0 + q < W) {
@@ -663,10 +712,10 @@ hipError_t launch_b1_mean(const pid_ensemble& e, const pid_out& out, void* ws, h
   {
     KernelTimer tm("pidmean_colsum", st);
     if (aligned)
-      hipLaunchKernelGGL((b1_count_kernel<4>), dim3((unsigned)((p.W + 255) / 256), (unsigned)p.groups), 64, 0, st,
+      hipLaunchKernelGGL((b1_count_kernel<4>), dim3((unsigned)((p.W + 255) / 256), (unsigned)p.groups), 256, 0, st,
                          U, ldw, (int)e.n, p.W, lastmask, p.chunk, p.Wp, gpart);
     else
-      hipLaunchKernelGGL((b1_count_kernel<1>), dim3((unsigned)((p.W + 63) / 64), (unsigned)p.groups), 64, 0, st,
+      hipLaunchKernelGGL((b1_count_kernel<1>), dim3((unsigned)((p.W + 63) / 64), (unsigned)p.groups), 256, 0, st,
                          U, ldw, (int)e.n, p.W, lastmask, p.chunk, p.Wp, gpart);
     hipError_t err = b1_combine(p, gpart, planes, st);
     if (err != hipSuccess) return err;
@@ -701,7 +750,7 @@ hipError_t launch_mask_bits_mean(const pid_ensemble& e, int iso_kind, const Extr
     KernelTimer tm("pidmean_colsum", st);
     if (iso_kind == PID_ISO_NONE) {   // U8 0/1 masks
       const dim3 grid((unsigned)((e.m + 2047) / 2048), (unsigned)p.groups);
-      hipLaunchKernelGGL(u8_count_pack_kernel, grid, 64, 0, st, reinterpret_cast<const uint8_t*>(e.data), e.ld,
+      hipLaunchKernelGGL(u8_count_pack_kernel, grid, 256, 0, st, reinterpret_cast<const uint8_t*>(e.data), e.ld,
                          (int)e.n, e.m, p.chunk, pk, p.Wp, p.Wp, gpart);
     } else {                          // the sharp isovalue on stored values
       const Extract ex = __builtin_bit_cast(Extract, exh);
