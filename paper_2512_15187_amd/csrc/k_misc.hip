@@ -113,9 +113,9 @@ hipError_t launch_field_max(const pid_ensemble& e, double* out, hipStream_t st) 
 }
 
 // rank[i] = #{ j : d_j > d_i  or  (d_j == d_i and j < i) };  order[rank[i]] = i.
-// One wave per MPW members: lanes compare strided j against each of the
-// wave's members, popcounts of the ballots give the counts (exact integers,
-// so the result does not depend on the order of the comparisons).
+// One wave per member: lanes compare strided j against the member,
+// popcounts of the ballots give the count (an exact integer, so the result
+// does not depend on the order of the comparisons).
 // blockIdx.y selects one of two depth arrays (the second may be absent).
 struct RankArgs {
   const double* d[2];
@@ -123,21 +123,15 @@ struct RankArgs {
   int32_t* order[2];
 };
 
-template <int MPW>
 __global__ __launch_bounds__(256) void rank_kernel(RankArgs ra, int n) {
   const int lane = threadIdx.x & 63;
-  const int i0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * MPW;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const double* __restrict__ d = ra.d[blockIdx.y];
   int32_t* __restrict__ rank = ra.rank[blockIdx.y];
   int32_t* __restrict__ order = ra.order[blockIdx.y];
-  if (i0 >= n) return;                      // whole wave leaves together
-  double di[MPW];
-  int r[MPW];
-#pragma unroll
-  for (int q = 0; q < MPW; ++q) {
-    di[q] = (i0 + q < n) ? d[i0 + q] : 0.0;
-    r[q] = 0;
-  }
+  if (i >= n) return;                       // whole wave leaves together
+  const double di = d[i];
+  int r = 0;
   // four 64-member chunks per round: their loads are issued together
   for (int j0 = 0; j0 < n; j0 += 256) {
     double dj[4];
@@ -149,19 +143,13 @@ __global__ __launch_bounds__(256) void rank_kernel(RankArgs ra, int n) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int j = j0 + 64 * c + lane;
-#pragma unroll
-      for (int q = 0; q < MPW; ++q) {
-        const bool before = j < n && ((dj[c] > di[q]) || (dj[c] == di[q] && j < i0 + q));
-        r[q] += __popcll(__ballot(before));
-      }
+      const bool before = j < n && ((dj[c] > di) || (dj[c] == di && j < i));
+      r += __popcll(__ballot(before));
     }
   }
-#pragma unroll
-  for (int q = 0; q < MPW; ++q) {
-    if (lane == q && i0 + q < n) {
-      if (rank) rank[i0 + q] = r[q];
-      if (order) order[r[q]] = i0 + q;
-    }
+  if (lane == 0) {
+    if (rank) rank[i] = r;
+    if (order) order[r] = i;
   }
 }
 
@@ -330,7 +318,7 @@ static void launch_rank_kernel(const RankArgs& ra, int64_t n, int arrays, hipStr
     return;
   }
   if (n <= 2048)
-    hipLaunchKernelGGL((rank_kernel<1>), dim3((unsigned)((n + 3) / 4), arrays), 256, 0, st, ra, (int)n);
+    hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((n + 3) / 4), arrays), 256, 0, st, ra, (int)n);
   else
     hipLaunchKernelGGL(rank_lds_kernel, dim3((unsigned)((n + 63) / 64), arrays), 256, 0, st, ra, (int)n);
 }
