@@ -54,20 +54,25 @@ __device__ __forceinline__ double to_double(T v) { return (double)to_float(v); }
 
 // erfc(z) / 2 in FP32 by Abramowitz & Stegun 7.1.26: for x >= 0,
 //   erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x),
-// with |error| <= 1.5e-7, and erfc(-x) = 2 - erfc(x).  About a third of the
-// instructions of erfcf; with FP32 rounding and the hardware reciprocal and
-// exponential the result is within ~3e-7 of Phi, far below the FP16 rounding
-// of the values it feeds and the 1e-4 depth tolerance of the mixed-precision
-// paths.
-__device__ __forceinline__ float half_erfc_fast(float z) {
-  const float x = fabsf(z);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));   // 1 ulp
-  float q = fmaf(t, 1.061405429f, -1.453152027f);
-  q = fmaf(t, q, 1.421413741f);
-  q = fmaf(t, q, -0.284496736f);
-  q = fmaf(t, q, 0.254829592f);
-  const float h = 0.5f * t * q * __expf(-x * x);   // erfc(|z|) / 2
-  return z >= 0.0f ? h : 1.0f - h;
+// with |error| <= 1.5e-7, and erfc(-x) = 2 - erfc(x).  It takes zk = z k,
+// k = sqrt(log2 e) (the caller folds k into its scale factor), so that
+// exp(-z^2) = 2^(-zk^2) is one square and the hardware 2^x, t = 1 / (1 +
+// (p / k) |zk|), and the coefficients carry the factor 1/2.  About a third of
+// the instructions of erfcf; with FP32 rounding and the hardware reciprocal
+// and exponential the result is within ~3e-7 of Phi, far below the FP16
+// rounding of the values it feeds and the 1e-4 depth tolerance of the
+// mixed-precision paths.
+constexpr float kSqrtLog2e = 1.2011224087864498f;
+
+__device__ __forceinline__ float half_erfc_fast(float zk) {
+  const float x = fabsf(zk);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f / kSqrtLog2e, x, 1.0f));   // 1 ulp
+  float q = fmaf(t, 0.5f * 1.061405429f, 0.5f * -1.453152027f);
+  q = fmaf(t, q, 0.5f * 1.421413741f);
+  q = fmaf(t, q, 0.5f * -0.284496736f);
+  q = fmaf(t, q, 0.5f * 0.254829592f);
+  const float h = t * q * __builtin_amdgcn_exp2f(-x * x);   // erfc(|z|) / 2
+  return zk >= 0.0f ? h : 1.0f - h;
 }
 
 // Lets a kernel take as dynamic LDS all of the CU's 160 KB that its static
@@ -91,7 +96,7 @@ __device__ __forceinline__ float extract_f(T raw, const Extract& e) {
   if constexpr (MODE == MODE_NONE) {
     return f;
   } else if constexpr (MODE == MODE_GAUSS) {
-    if constexpr (FAST) return half_erfc_fast((f - e.cf) * e.af);
+    if constexpr (FAST) return half_erfc_fast((f - e.cf) * (e.af * kSqrtLog2e));
     else return 0.5f * erfcf((f - e.cf) * e.af);
   } else if constexpr (MODE == MODE_MODEL) {
     const float t = (f - e.cf) * e.af;
