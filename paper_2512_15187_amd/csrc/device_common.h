@@ -52,27 +52,30 @@ __device__ __forceinline__ double to_double(double v) { return v; }
 template <typename T>
 __device__ __forceinline__ double to_double(T v) { return (double)to_float(v); }
 
-// erfc(z) / 2 in FP32 by Abramowitz & Stegun 7.1.26: for x >= 0,
-//   erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x),
-// with |error| <= 1.5e-7, and erfc(-x) = 2 - erfc(x).  It takes zk = z k,
-// k = sqrt(log2 e) (the caller folds k into its scale factor), so that
-// exp(-z^2) = 2^(-zk^2) is one square and the hardware 2^x, t = 1 / (1 +
-// (p / k) |zk|), and the coefficients carry the factor 1/2.  About a third of
-// the instructions of erfcf; with FP32 rounding and the hardware reciprocal
-// and exponential the result is within ~3e-7 of Phi, far below the FP16
-// rounding of the values it feeds and the 1e-4 depth tolerance of the
-// mixed-precision paths.
-constexpr float kSqrtLog2e = 1.2011224087864498f;
+// erfc(z) / 2 in FP32 without a division, from the normal tail T(y) = 1 -
+// Phi(y) at y = sqrt(2) z (the caller folds sqrt(2) into its scale factor).
+// For y >= 0, T(y) = 2^(-1 - P(y)) with P(y) = a1 y + ... + a7 y^7: a
+// weighted minimax fit of -log2(2 T(y)) on [0, 6] (weights T ln 2, so that
+// the error is absolute; fit_normal_tail.py beside this file).  P(0) = 0 gives
+// T(0) = 1/2 exactly; beyond 6 the argument is clamped (T(6) < 1e-9).  With
+// FP32 rounding and the hardware 2^x the result is within 1.1e-7 of T and
+// 1.4e-7 of 1 - T: one exponential and eight multiply-adds per value, far
+// below the FP16 rounding of the values it feeds and the 1e-4 depth tolerance
+// of the mixed-precision paths.  erfc(-z) / 2 = 1 - erfc(z) / 2.
+constexpr float kSqrt2 = 1.41421356237309515f;
 
-__device__ __forceinline__ float half_erfc_fast(float zk) {
-  const float x = fabsf(zk);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f / kSqrtLog2e, x, 1.0f));   // 1 ulp
-  float q = fmaf(t, 0.5f * 1.061405429f, 0.5f * -1.453152027f);
-  q = fmaf(t, q, 0.5f * 1.421413741f);
-  q = fmaf(t, q, 0.5f * -0.284496736f);
-  q = fmaf(t, q, 0.5f * 0.254829592f);
-  const float h = t * q * __builtin_amdgcn_exp2f(-x * x);   // erfc(|z|) / 2
-  return zk >= 0.0f ? h : 1.0f - h;
+__device__ __forceinline__ float half_erfc_fast(float y) {
+  const float x = fminf(fabsf(y), 6.0f);
+  // -(1 + P(x)) in Horner form (the coefficients are -a_k)
+  float q = 9.856917131e-06f;
+  q = fmaf(x, q, -6.527679943e-05f);
+  q = fmaf(x, q, -3.862405429e-04f);
+  q = fmaf(x, q, 7.337194867e-03f);
+  q = fmaf(x, q, -5.265045911e-02f);
+  q = fmaf(x, q, -4.591701627e-01f);
+  q = fmaf(x, q, -1.151107550e+00f);
+  const float h = __builtin_amdgcn_exp2f(fmaf(x, q, -1.0f));   // T(|y|)
+  return y >= 0.0f ? h : 1.0f - h;
 }
 
 // Lets a kernel take as dynamic LDS all of the CU's 160 KB that its static
@@ -96,7 +99,7 @@ __device__ __forceinline__ float extract_f(T raw, const Extract& e) {
   if constexpr (MODE == MODE_NONE) {
     return f;
   } else if constexpr (MODE == MODE_GAUSS) {
-    if constexpr (FAST) return half_erfc_fast((f - e.cf) * (e.af * kSqrtLog2e));
+    if constexpr (FAST) return half_erfc_fast((f - e.cf) * (e.af * kSqrt2));
     else return 0.5f * erfcf((f - e.cf) * e.af);
   } else if constexpr (MODE == MODE_MODEL) {
     const float t = (f - e.cf) * e.af;

@@ -621,20 +621,28 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 // split's share are read with an offset beyond the buffer's range: they land
 // as zeros without a memory access, so no load sits under a branch that
 // depends on the data and the wait counts are constants.
-template <typename Tin, int MT, int MODE, int MAXT, bool WEIGHTED, int NB, int NT, int NW, bool GRP>
+template <typename Tin, int MT, int MODE, int MAXT, bool WEIGHTED, int NB, int NT, int NW, bool GRP, int SEG>
 __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   using TR = MTraits<MT>;
-  constexpr int SEG = 128;                    // bytes of a row per slab
+  // SEG: bytes of a row per slab.  128 for up to 256 rows; 256 (FP32 input,
+  // up to 128 rows) doubles the work between two barriers where the loader
+  // evaluates a probability model on every value.
+  static_assert(SEG == 128 || SEG == 256, "row segment");
   constexpr int EPC = 16 / (int)sizeof(Tin);  // elements per 16-byte chunk
   constexpr int KS = SEG / (int)sizeof(Tin);  // points per slab
   constexpr int ROWB = KS * TR::EB + 16;      // LDS tile row stride (padded)
   constexpr uint32_t OOB = 0x80000000u;
-  constexpr int RW = 256 / NW;                // staged rows per wave (32 or 16)
-  constexpr int LW = RW / 8;                  // row loads per slab and wave
+  constexpr int CPRW = SEG / 16;              // 16-byte chunks per row segment
+  constexpr int RPI = 64 / CPRW;              // rows per load instruction (8 or 4)
+  constexpr int RMAX = 256 * 128 / SEG;       // rows a workgroup stages at most
+  constexpr int RW = RMAX / NW;               // staged rows per wave
+  constexpr int LW = RW / RPI;                // row loads per slab and wave
   constexpr int NTH = 64 * NW;                // threads
   constexpr int DW = LW + (WEIGHTED ? 1 : 0); // loads per slab of wave 0 (rows, weights)
   static_assert(MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3, "16-bit MFMA types");
-  constexpr int CQ = (256 * 8 + 64 * NW - 1) / (64 * NW);   // chunks per thread at most
+  static_assert(KS <= 64, "weights of a slab: 64 per ring slot");
+  static_assert(!GRP || SEG == 128, "grouped sub-tiles stage 256 rows");
+  constexpr int CQ = (RMAX * CPRW + 64 * NW - 1) / (64 * NW);   // chunks per thread at most
   static_assert((NB - 2) * DW <= 63, "wait count");
   extern __shared__ __align__(16) unsigned char lds[];
 
@@ -717,7 +725,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   float* wsl = reinterpret_cast<float*>(lmass + rows);
 
   // --- loads: wave w streams staging rows [RW w, RW w + RW) (inside one
-  // 32-row block, so all in the I or the J range), eight rows per instruction
+  // 32-row block, so all in the I or the J range), RPI rows per instruction
   const bool loader = RW * wave < rows;
   const int g0 = loader ? grow(RW * wave) : 0;            // first global row of the wave
   const int nvalid = loader ? max(0, min(RW, a.n - g0)) : 0;
@@ -725,8 +733,8 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   const BufRes rsU = make_bufres(Ub, (uint32_t)(((int64_t)max(nvalid - 1, 0) * a.ld + a.m) * (int64_t)sizeof(Tin)));
   const BufRes rsW = make_bufres(a.w, (uint32_t)(a.m * (int64_t)sizeof(float)));
   const uint32_t ldb = (uint32_t)(a.ld * (int64_t)sizeof(Tin));
-  const int lr8 = lane >> 3;                 // row within an instruction
-  const int lc = lane & 7;                   // 16-byte chunk within the row segment
+  const int lr8 = lane / CPRW;               // row within an instruction
+  const int lc = lane % CPRW;                // 16-byte chunk within the row segment
   // Per lane, fixed across slabs: the byte offset of its chunk within row
   // block i (OOB for rows past n) and the number of points left of its chunk.
   // Per slab, in scalar registers: the slab's byte offset in a row (the
@@ -736,7 +744,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   uint32_t vrow[LW];
 #pragma unroll
   for (int i = 0; i < LW; ++i) {
-    const int r = 8 * i + lr8;
+    const int r = RPI * i + lr8;
     vrow[i] = (r < nvalid) ? (uint32_t)r * ldb + (uint32_t)lc * 16u : OOB;
   }
   const int plim = (int)a.m - lc * EPC;      // chunk in range: first point of the slab < plim
@@ -749,7 +757,7 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
       const bool pok = spt < plim;
 #pragma unroll
       for (int i = 0; i < LW; ++i)
-        dma_to_lds<16>(rsU, stage + ((size_t)(j % NB) * rows + RW * wave + 8 * i) * SEG, pok ? vrow[i] : OOB,
+        dma_to_lds<16>(rsU, stage + ((size_t)(j % NB) * rows + RW * wave + RPI * i) * SEG, pok ? vrow[i] : OOB,
                        sbyte);
     }
     if constexpr (WEIGHTED) {
@@ -769,9 +777,9 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
   auto wait_slab = [&]() { wait_slab_n(std::integral_constant<int, NB - 2>()); };
 
   // masses (diagonal super-tiles): a thread's chunks belong to the same rows
-  // in every slab (row = (tid + NTH ci) / 8), so each lane adds its chunk sum
-  // (FP32) to an FP64 register slab by slab; the 8 lanes of a row are added
-  // once at the end.
+  // in every slab (row = (tid + NTH ci) / CPRW), so each lane adds its chunk
+  // sum (FP32) to an FP64 register slab by slab; the CPRW lanes of a row are
+  // added once at the end.
   double accm[CQ];
 #pragma unroll
   for (int ci = 0; ci < CQ; ++ci) accm[ci] = 0.0;
@@ -784,26 +792,44 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
     const int64_t s = split + (int64_t)j * a.nsplit;
     const unsigned char* src = stage + (size_t)(j % NB) * rows * SEG;
     unsigned char* tile = tile_of(j);
+    // every chunk of the thread is read before the first is converted, so
+    // the LDS latency is paid once per slab
+    Vec16<Tin> raws[CQ];
 #pragma unroll
     for (int ci = 0; ci < CQ; ++ci) {
-      // whole waves (rows * 8 and NTH are multiples of 64): a scalar branch
-      if (NTH * ci + 64 * wave >= rows * 8) break;
+      // whole waves (rows * CPRW and NTH are multiples of 64): a scalar branch
+      if (NTH * ci + 64 * wave < rows * CPRW) {
+        const int qq = tid + NTH * ci;
+        raws[ci] = *reinterpret_cast<const Vec16<Tin>*>(src + (size_t)(qq / CPRW) * SEG + (qq % CPRW) * 16);
+      }
+    }
+#pragma unroll
+    for (int ci = 0; ci < CQ; ++ci) {
+      if (NTH * ci + 64 * wave >= rows * CPRW) break;
       const int qq = tid + NTH * ci;
-      const int row = qq >> 3, c = qq & 7;
-      const Vec16<Tin> raw = *reinterpret_cast<const Vec16<Tin>*>(src + (size_t)row * SEG + c * 16);
+      const int row = qq / CPRW, c = qq % CPRW;
+      const Vec16<Tin>& raw = raws[ci];
       const int64_t x0 = s * KS + c * EPC;
-      const bool rv = grow(row) < a.n;
-      const int lim = (int)min((int64_t)EPC, a.m - x0);   // points of the chunk inside M
       float msum = 0.f;
       float uv[EPC];
 #pragma unroll
-      for (int e = 0; e < EPC; ++e) {
-        float u = extract_f<MODE, Tin, true>(raw.v[e], a.ex);
-        if constexpr (MODE != MODE_NONE) {
-          // zeros read past the ends (a mask, so the model is not branched around)
-          const bool ok = rv && e < lim;
-          u = __int_as_float(__float_as_int(u) & (ok ? -1 : 0));
+      for (int e = 0; e < EPC; ++e) uv[e] = extract_f<MODE, Tin, true>(raw.v[e], a.ex);
+      if constexpr (MODE != MODE_NONE) {
+        // the zeros read past the ends of the rows and of M went through the
+        // model: cleared, in a wave-uniform branch that waves of inside
+        // chunks skip (the empty asm keeps the compiler from turning it back
+        // into selects on every value)
+        const bool rv = grow(row) < a.n;
+        const int lim = (int)min((int64_t)EPC, a.m - x0);   // points of the chunk inside M
+        if (__builtin_amdgcn_ballot_w64(!(rv && lim == EPC)) != 0) {
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) uv[e] = (rv && e < lim) ? uv[e] : 0.0f;
         }
+      }
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) {
+        const float u = uv[e];
         if constexpr (WEIGHTED) {
           const float wv = wsl[(size_t)(j % NB) * 64 + c * EPC + e];
           msum = (e == 0) ? wv * u : msum + wv * u;
@@ -884,15 +910,15 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
     }
   }
   vm_wait<0>();               // no load into LDS outlives the workgroup
-  // row sums to LDS: the 8 lanes of a row (fixed butterfly), then lane c = 0
+  // row sums to LDS: the CPRW lanes of a row (fixed butterfly), then lane c = 0
 #pragma unroll
   for (int ci = 0; ci < CQ; ++ci) {
-    if (NTH * ci + 64 * wave >= rows * 8) break;
+    if (NTH * ci + 64 * wave >= rows * CPRW) break;
     double t = accm[ci];
 #pragma unroll
-    for (int o = 1; o <= 4; o <<= 1) t += __shfl_xor(t, o, 64);
+    for (int o = 1; o < CPRW; o <<= 1) t += __shfl_xor(t, o, 64);
     const int qq = tid + NTH * ci;
-    if ((qq & 7) == 0) lmass[qq >> 3] = t;
+    if ((qq % CPRW) == 0) lmass[qq / CPRW] = t;
   }
 
   // --- partial sub-tiles
@@ -922,20 +948,21 @@ __global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
 }
 
 // LDS bytes of gram_dma_kernel for a workgroup of `rows` staged rows.
-template <typename Tin, int MT, int NT>
+template <typename Tin, int MT, int NT, int SEG>
 constexpr int gram_dma_nb() {
-  constexpr int KS = 128 / (int)sizeof(Tin);
+  constexpr int KS = SEG / (int)sizeof(Tin);
   constexpr int ROWB = KS * MTraits<MT>::EB + 16;
-  constexpr int fixed = NT * MTraits<MT>::PLANES * 256 * ROWB + 256 * 8 + 4 * 256;
-  constexpr int nb = (163840 - fixed) / (256 * 128 + 256);
+  constexpr int RMAX = 256 * 128 / SEG;
+  constexpr int fixed = NT * MTraits<MT>::PLANES * RMAX * ROWB + RMAX * 8 + 4 * 256;
+  constexpr int nb = (163840 - fixed) / (RMAX * SEG + 256);
   return nb > 4 ? 4 : nb;
 }
-template <typename Tin, int MT, int NT>
+template <typename Tin, int MT, int NT, int SEG>
 size_t gram_dma_lds(int rows, bool weighted) {
-  constexpr int KS = 128 / (int)sizeof(Tin);
+  constexpr int KS = SEG / (int)sizeof(Tin);
   constexpr int ROWB = KS * MTraits<MT>::EB + 16;
-  constexpr int NB = gram_dma_nb<Tin, MT, NT>();
-  return (size_t)NB * rows * 128 + (size_t)NT * MTraits<MT>::PLANES * rows * ROWB + (size_t)rows * 8 +
+  constexpr int NB = gram_dma_nb<Tin, MT, NT, SEG>();
+  return (size_t)NB * rows * SEG + (size_t)NT * MTraits<MT>::PLANES * rows * ROWB + (size_t)rows * 8 +
          (weighted ? (size_t)NB * 256 : 0);
 }
 
@@ -951,7 +978,6 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
     if (!ga0.vec || (ga0.m * eb) % 16 != 0) return false;
     if (((int64_t)31 * ga0.ld + ga0.m) * eb >= (INT64_C(1) << 31) || ga0.m * 4 >= (INT64_C(1) << 31)) return false;
     GramArgs ga = ga0;
-    ga.slabs = (ga0.m * eb + 127) / 128;   // 128-byte slabs of every row
     const bool w = ga.w != nullptr;
     auto go = [&](auto k, size_t lds, int threads) {
       static const bool attr = (allow_dynamic_lds((const void*)k) == hipSuccess);
@@ -961,18 +987,32 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
     // 16 waves, one conversion tile, a ring of NB slabs; sub-tiles per wave:
     // at most 36 over 16 waves (3)
     constexpr int NT = 1;
-    constexpr int NB = gram_dma_nb<Tin, MT, NT>();
+    constexpr int NB = gram_dma_nb<Tin, MT, NT, 128>();
     static_assert(NB >= 2, "LDS ring");
+    (void)maxt;
+    if constexpr (MODE != MODE_NONE && sizeof(Tin) == 4) {
+      // a model evaluated on FP32 values, at most 128 rows: 256-byte row
+      // segments (twice the values between two barriers)
+      if (rows <= 128) {
+        constexpr int NB2 = gram_dma_nb<Tin, MT, NT, 256>();
+        static_assert(NB2 >= 3, "LDS ring");
+        ga.slabs = (ga0.m * eb + 255) / 256;
+        const size_t lds = gram_dma_lds<Tin, MT, NT, 256>(rows, w);
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB2, NT, 16, false, 256>, lds, 1024);
+        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB2, NT, 16, false, 256>, lds, 1024);
+        return true;
+      }
+    }
+    ga.slabs = (ga0.m * eb + 127) / 128;   // 128-byte slabs of every row
     // eight row blocks in one diagonal super-tile: grouped sub-tiles
     const bool grp = ga.nsuper == 1 && ga.nbt == 8;
-    const size_t lds = gram_dma_lds<Tin, MT, NT>(rows, w);
-    (void)maxt;
+    const size_t lds = gram_dma_lds<Tin, MT, NT, 128>(rows, w);
     if (grp) {
-      if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true>, lds, 1024);
-      else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true>, lds, 1024);
+      if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true, 128>, lds, 1024);
+      else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true, 128>, lds, 1024);
     } else {
-      if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false>, lds, 1024);
-      else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false>, lds, 1024);
+      if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false, 128>, lds, 1024);
+      else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false, 128>, lds, 1024);
     }
     return true;
   }
