@@ -622,7 +622,9 @@ __global__ __launch_bounds__(512) void gram_kernel(GramArgs a) {
 // as zeros without a memory access, so no load sits under a branch that
 // depends on the data and the wait counts are constants.
 template <typename Tin, int MT, int MODE, int MAXT, bool WEIGHTED, int NB, int NT, int NW, bool GRP, int SEG>
-__global__ __launch_bounds__(64 * NW) void gram_dma_kernel(GramArgs a) {
+// (at least 4 waves per SIMD: at most 128 VGPRs, so that two 8-wave
+// workgroups can share a CU)
+__global__ __launch_bounds__(64 * NW, 4) void gram_dma_kernel(GramArgs a) {
   using TR = MTraits<MT>;
   // SEG: bytes of a row per slab.  128 for up to 256 rows; 256 (FP32 input,
   // up to 128 rows) doubles the work between two barriers where the loader
@@ -990,9 +992,21 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
     constexpr int NB = gram_dma_nb<Tin, MT, NT, 128>();
     static_assert(NB >= 2, "LDS ring");
     (void)maxt;
-    if constexpr (MODE != MODE_NONE && sizeof(Tin) == 4) {
-      // a model evaluated on FP32 values, at most 128 rows: 256-byte row
-      // segments (twice the values between two barriers)
+    ga.slabs = (ga0.m * eb + 127) / 128;   // 128-byte slabs of every row
+    if constexpr (MODE == MODE_GAUSS && sizeof(Tin) == 4) {
+      // the Gaussian model on FP32 values, at most 128 rows: 8 waves and
+      // about 76 KB of LDS, so that two workgroups share a CU (the plan
+      // doubles the splits); each thread converts two chunks per slab
+      if (rows <= 128) {
+        const size_t lds = gram_dma_lds<Tin, MT, NT, 128>(rows, w);
+        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 8, false, 128>, lds, 512);
+        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 8, false, 128>, lds, 512);
+        return true;
+      }
+    }
+    if constexpr (MODE == MODE_MODEL && sizeof(Tin) == 4) {
+      // the piecewise-linear models on FP32 values, at most 128 rows:
+      // 256-byte row segments (twice the values between two barriers)
       if (rows <= 128) {
         constexpr int NB2 = gram_dma_nb<Tin, MT, NT, 256>();
         static_assert(NB2 >= 3, "LDS ring");
@@ -1003,7 +1017,6 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
         return true;
       }
     }
-    ga.slabs = (ga0.m * eb + 127) / 128;   // 128-byte slabs of every row
     // eight row blocks in one diagonal super-tile: grouped sub-tiles
     const bool grp = ga.nsuper == 1 && ga.nbt == 8;
     const size_t lds = gram_dma_lds<Tin, MT, NT, 128>(rows, w);

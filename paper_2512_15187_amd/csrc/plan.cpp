@@ -123,9 +123,14 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
   p.ks = cpr * (16 / eb);
   p.slabs = (m + p.ks - 1) / p.ks;
   // splits: about one workgroup per CU, at least 2 slabs per split and at
-  // most 16384 points of FP32 accumulation per split.
+  // most 16384 points of FP32 accumulation per split.  FP32 values through
+  // the Gaussian model into a 16-bit MFMA type, one super-tile of at most 128
+  // rows: two (smaller) workgroups per CU, so that one evaluates the model
+  // while the other waits at a barrier.
   const int cus = device_cu_count();
-  int64_t want = std::max<int64_t>(1, (int64_t)cus / p.ntiles_super);
+  const bool two_per_cu = eb == 4 && iso_mode(iso_kind) == MODE_GAUSS &&
+                          (mt == MT_F16 || mt == MT_BF16 || mt == MT_BF16X3) && p.nsuper == 1 && p.sb <= 4;
+  int64_t want = std::max<int64_t>(1, (int64_t)cus * (two_per_cu ? 2 : 1) / p.ntiles_super);
   want = std::min<int64_t>(want, std::max<int64_t>(1, p.slabs / 2));
   const int64_t min_splits = (m + 16383) / 16384;
   if (mt != MT_I8 && mt != MT_F64) want = std::max(want, min_splits);
