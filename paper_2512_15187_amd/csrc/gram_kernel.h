@@ -641,7 +641,9 @@ __global__ __launch_bounds__(64 * NW, 4) void gram_dma_kernel(GramArgs a) {
   constexpr int LW = RW / RPI;                // row loads per slab and wave
   constexpr int NTH = 64 * NW;                // threads
   constexpr int DW = LW + (WEIGHTED ? 1 : 0); // loads per slab of wave 0 (rows, weights)
-  static_assert(MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3, "16-bit MFMA types");
+  static_assert(MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3 || MT == MT_I8, "MFMA types");
+  static_assert(MT != MT_I8 || (!WEIGHTED && MODE == MODE_STEP), "INT8: thresholded values, no weights");
+  static_assert(KS % TR::KK == 0, "whole k-steps per slab");
   static_assert(KS <= 64, "weights of a slab: 64 per ring slot");
   static_assert(!GRP || SEG == 128, "grouped sub-tiles stage 256 rows");
   constexpr int CQ = (RMAX * CPRW + 64 * NW - 1) / (64 * NW);   // chunks per thread at most
@@ -855,6 +857,11 @@ __global__ __launch_bounds__(64 * NW, 4) void gram_dma_kernel(GramArgs a) {
 #pragma unroll
         for (int e = 0; e < EPC; ++e) o[e] = f32_to_bf16_bits(uv[e]);
         store_lds<2 * EPC>(d, o);
+      } else if constexpr (MT == MT_I8) {
+        int8_t o[EPC];   // the thresholded values are 0 or 1
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) o[e] = (int8_t)(int)uv[e];
+        store_lds<EPC>(d, o);
       } else {
         uint16_t hi[EPC], lo[EPC];
 #pragma unroll
@@ -933,7 +940,8 @@ __global__ __launch_bounds__(64 * NW, 4) void gram_dma_kernel(GramArgs a) {
       for (int r = 0; r < 16; ++r) {
         const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int jj = lane & 31;
-        reinterpret_cast<float*>(a.part)[pidx + i * 32 + jj] = acc[t][r];
+        if constexpr (MT == MT_I8) reinterpret_cast<int*>(a.part)[pidx + i * 32 + jj] = acc[t][r];
+        else reinterpret_cast<float*>(a.part)[pidx + i * 32 + jj] = acc[t][r];
       }
     }
   }
@@ -973,7 +981,8 @@ size_t gram_dma_lds(int rows, bool weighted) {
 // offsets within 2^31); returns false otherwise.
 template <typename Tin, int MT, int MODE>
 bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStream_t st, const KernelTimer& tm) {
-  if constexpr (!((MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3) && sizeof(Tin) <= 4 && sizeof(Tin) >= 2)) {
+  if constexpr (!((MT == MT_F16 || MT == MT_BF16 || MT == MT_BF16X3 || (MT == MT_I8 && MODE == MODE_STEP)) &&
+                  sizeof(Tin) <= 4 && sizeof(Tin) >= 2)) {
     return false;
   } else {
     constexpr int eb = sizeof(Tin);
@@ -993,27 +1002,36 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
     static_assert(NB >= 2, "LDS ring");
     (void)maxt;
     ga.slabs = (ga0.m * eb + 127) / 128;   // 128-byte slabs of every row
+    // launch with or without point weights (INT8 runs are unweighted: its
+    // "weighted" kernel is the unweighted one, never launched as such)
+    constexpr bool WW = MT != MT_I8;
+    auto go_w = [&](auto kw, auto k, size_t lds, int threads) {
+      if constexpr (MT == MT_I8) go(k, lds, threads);
+      else if (w) go(kw, lds, threads);
+      else go(k, lds, threads);
+    };
     if constexpr (MODE == MODE_GAUSS && sizeof(Tin) == 4) {
       // the Gaussian model on FP32 values, at most 128 rows: 8 waves and
       // about 76 KB of LDS, so that two workgroups share a CU (the plan
       // doubles the splits); each thread converts two chunks per slab
       if (rows <= 128) {
         const size_t lds = gram_dma_lds<Tin, MT, NT, 128>(rows, w);
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 8, false, 128>, lds, 512);
-        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 8, false, 128>, lds, 512);
+        go_w(gram_dma_kernel<Tin, MT, MODE, 3, WW, NB, NT, 8, false, 128>,
+             gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 8, false, 128>, lds, 512);
         return true;
       }
     }
-    if constexpr (MODE == MODE_MODEL && sizeof(Tin) == 4) {
-      // the piecewise-linear models on FP32 values, at most 128 rows:
-      // 256-byte row segments (twice the values between two barriers)
+    if constexpr ((MODE == MODE_MODEL || MODE == MODE_STEP) && sizeof(Tin) == 4) {
+      // the piecewise-linear models or a threshold on FP32 values, at most
+      // 128 rows: 256-byte row segments (twice the values between two
+      // barriers)
       if (rows <= 128) {
         constexpr int NB2 = gram_dma_nb<Tin, MT, NT, 256>();
         static_assert(NB2 >= 3, "LDS ring");
         ga.slabs = (ga0.m * eb + 255) / 256;
         const size_t lds = gram_dma_lds<Tin, MT, NT, 256>(rows, w);
-        if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB2, NT, 16, false, 256>, lds, 1024);
-        else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB2, NT, 16, false, 256>, lds, 1024);
+        go_w(gram_dma_kernel<Tin, MT, MODE, 3, WW, NB2, NT, 16, false, 256>,
+             gram_dma_kernel<Tin, MT, MODE, 3, false, NB2, NT, 16, false, 256>, lds, 1024);
         return true;
       }
     }
@@ -1021,11 +1039,11 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
     const bool grp = ga.nsuper == 1 && ga.nbt == 8;
     const size_t lds = gram_dma_lds<Tin, MT, NT, 128>(rows, w);
     if (grp) {
-      if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, true, 128>, lds, 1024);
-      else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true, 128>, lds, 1024);
+      go_w(gram_dma_kernel<Tin, MT, MODE, 3, WW, NB, NT, 16, true, 128>,
+           gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true, 128>, lds, 1024);
     } else {
-      if (w) go(gram_dma_kernel<Tin, MT, MODE, 3, true, NB, NT, 16, false, 128>, lds, 1024);
-      else go(gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false, 128>, lds, 1024);
+      go_w(gram_dma_kernel<Tin, MT, MODE, 3, WW, NB, NT, 16, false, 128>,
+           gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false, 128>, lds, 1024);
     }
     return true;
   }
