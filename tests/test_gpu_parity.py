@@ -187,6 +187,49 @@ def test_all_pairs_binary_bitexact(n, m, kind):
     assert_ranks(res["rank"], ref["depth"], 0)
 
 
+# Rows ending on a 16-byte boundary take the LDS-staged Gram kernel in its
+# field variants: the Gaussian model in two 8-wave workgroups per CU (N <= 128),
+# the linear models and thresholds on 256-byte row segments (N <= 128), INT8
+# tiles for thresholded values on 128-byte segments (N > 128, grouped sub-tiles
+# for eight row blocks, several super-tiles past 256 rows; FP16 fields).  The
+# cases cover ragged N, a tail of M inside the last slab and point weights.
+STAGED_FIELD_CASES = [
+    # (kind, n, m, dtype, weighted)
+    ("gaussian", 100, 4132, torch.float32, True),
+    ("gaussian", 37, 2052, torch.float32, False),
+    ("gaussian", 160, 2056, torch.float32, True),
+    ("tent", 100, 4132, torch.float32, True),
+    ("step", 100, 4132, torch.float32, False),
+    ("step", 200, 2056, torch.float32, False),
+    ("step", 250, 2048, torch.float32, False),
+    ("step", 300, 1028, torch.float32, False),
+    ("step", 90, 4104, torch.float16, False),
+]
+
+
+@pytest.mark.parametrize("kind,n,m,dtype,weighted", STAGED_FIELD_CASES,
+                         ids=[f"{c[0]}-{c[1]}x{c[2]}-{str(c[3])[6:]}{'-w' if c[4] else ''}"
+                              for c in STAGED_FIELD_CASES])
+def test_all_pairs_staged_fields(kind, n, m, dtype, weighted):
+    F = _fields(n, m, 500 + n).to(dtype)
+    Fh = F.to(torch.float64).numpy()
+    if kind == "step":
+        iso = dict(kind="step", c=0.5, side=1)
+        res = pid.pid_all_pairs(_dev(F), iso=iso)           # AUTO -> INT8
+        B = oracle.extract(Fh, iso).astype(np.uint8)
+        ref = oracle.binary_pid(B)
+        assert_bitwise(res, ref, label=f"staged {kind}")
+        assert_ranks(res["rank"], ref["depth"], 0)
+        return
+    iso = (dict(kind="gaussian", c=0.5, sigma=0.05, side=-1) if kind == "gaussian"
+           else dict(kind="tent", c=0.5, width=0.1))
+    w = _weights(m, 7 + n) if weighted else None
+    res = pid.pid_all_pairs(_dev(F), None if w is None else _dev(w), iso=iso, gemm="f16")
+    ref = oracle.pid(oracle.extract(Fh, iso), None if w is None else w.numpy())
+    assert_close(res, ref, TOL_MIXED, label=f"staged {kind}")
+    assert_ranks(res["rank"], ref["depth"], TOL_MIXED, label=f"staged {kind}")
+
+
 def test_binary_reduces_to_eid_on_gpu():
     B = synth.random_binary(12, 700, 77)
     res = pid.pid_all_pairs(_dev(B))
