@@ -97,7 +97,9 @@ typedef enum {
 #define PID_FLAG_VALIDATE 1u  /* check values first (probabilities in [0,1], U8 in {0,1},
                                  finite fields, weights finite and >= 0); the call then
                                  synchronises `stream` and returns PID_ERR_VALUE_RANGE
-                                 without computing anything if a check fails            */
+                                 without computing anything if a check fails.  Without
+                                 it the values are trusted: one out of range (a NaN field
+                                 value, say) gives unspecified depths, not an error     */
 
 /* The ensemble: N members x M grid points, member-major.  Element (i, x) is at
  * data[i * ld + x] (ld >= M, in elements).  Rows whose byte address is a
