@@ -140,6 +140,23 @@ static void plans() {
           }
   CHECK(ok > 1000 && refused > 100);
   std::printf("plans: %d accepted, %d refused\n", ok, refused);
+
+  // FP32 values through the Gaussian model on at most 128 rows: two Gram
+  // workgroups per CU, so twice the K-splits (256 CUs without a GPU) and
+  // twice the partial sub-tiles (10 of 32 x 32 FP32 for 128 rows) of the
+  // same values without a model; 129 rows keep one workgroup per CU
+  {
+    const pid_iso gauss{PID_ISO_GAUSSIAN, 1, 0.5, 0.05}, none{PID_ISO_NONE, 1, 0, 0};
+    const pid_ensemble e128 = ens(128, INT64_C(1) << 21, PID_F32);
+    size_t bg = 0, bn = 0;
+    CHECK(pid_workspace_size(&e128, &gauss, 0, PID_GEMM_F16, &bg) == PID_OK);
+    CHECK(pid_workspace_size(&e128, &none, 0, PID_GEMM_F16, &bn) == PID_OK);
+    CHECK(bg >= bn + (size_t)256 * 10 * 4096);
+    const pid_ensemble e129 = ens(129, INT64_C(1) << 21, PID_F32);
+    CHECK(pid_workspace_size(&e129, &gauss, 0, PID_GEMM_F16, &bg) == PID_OK);
+    CHECK(pid_workspace_size(&e129, &none, 0, PID_GEMM_F16, &bn) == PID_OK);
+    CHECK(bg == bn);
+  }
 }
 
 static void server_without_gpu() {
