@@ -6,7 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 #include "pid_internal.h"
 
@@ -79,14 +81,23 @@ __device__ __forceinline__ float half_erfc_fast(float y) {
 }
 
 // Lets a kernel take as dynamic LDS all of the CU's 160 KB that its static
-// LDS leaves (call once per kernel before its first launch).  A failure is
-// returned and cleared, so that it does not surface at a later launch.
+// LDS leaves.  Called before a launch: the first call for a kernel sets the
+// attribute and records the outcome, later calls for it return that outcome
+// (a registry keyed by the kernel, so kernels of the same signature launched
+// from one call site are each set).  A failure is returned and cleared, so
+// that it does not surface at a later launch.
 inline hipError_t allow_dynamic_lds(const void* k) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, hipError_t> done;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto it = done.find(k);
+  if (it != done.end()) return it->second;
   hipFuncAttributes fa{};
   hipError_t e = hipFuncGetAttributes(&fa, k);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(163840 - fa.sharedSizeBytes));
   if (e != hipSuccess) (void)hipGetLastError();
+  done.emplace(k, e);
   return e;
 }
 

@@ -991,8 +991,7 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
     GramArgs ga = ga0;
     const bool w = ga.w != nullptr;
     auto go = [&](auto k, size_t lds, int threads) {
-      static const bool attr = (allow_dynamic_lds((const void*)k) == hipSuccess);
-      (void)attr;
+      (void)allow_dynamic_lds((const void*)k);   // set on the first launch of each kernel
       hipExtLaunchKernelGGL(k, dim3(grid), dim3(threads), (uint32_t)lds, st, tm.start(), tm.stop(), 0u, ga);
     };
     // 16 waves, one conversion tile, a ring of NB slabs; sub-tiles per wave:
@@ -1059,9 +1058,7 @@ void launch_gram_w(const GramArgs& ga, int maxt, int rows, int grid, size_t lds,
   constexpr int CH256 = (256 * CPR / 512) > 0 ? 256 * CPR / 512 : 1;   // chunk slots for 256 rows
   constexpr int CH128 = (128 * CPR / 512) > 0 ? 128 * CPR / 512 : 1;   // ... for 128 rows
   auto go = [&](auto k) {
-    // all the LDS the kernel's static LDS leaves, once per kernel
-    static const bool attr = (allow_dynamic_lds((const void*)k) == hipSuccess);
-    (void)attr;
+    (void)allow_dynamic_lds((const void*)k);   // set on the first launch of each kernel
     hipExtLaunchKernelGGL(k, dim3(grid), dim3(512), (uint32_t)lds, st, tm.start(), tm.stop(), 0u, ga);
   };
   if (maxt > 2) go(gram_kernel<Tin, MT, MODE, 5, CPR, CH256, W>);

@@ -840,9 +840,7 @@ static void launch_dma(const MeanPlan& p, const pid_ensemble& e, double* part, h
   const T* U = reinterpret_cast<const T*>(e.data);
   KernelTimer tm("pidmean", st, /*by_launch=*/true);
   auto go = [&](auto kern) {
-    // all the LDS the kernel's static LDS leaves, once per kernel
-    static const bool attr = (allow_dynamic_lds((const void*)kern) == hipSuccess);
-    (void)attr;
+    (void)allow_dynamic_lds((const void*)kern);   // set on the first launch of each kernel
     hipExtLaunchKernelGGL(kern, dim3(p.dma_grid), dim3(64 * p.dma_nwaves), (uint32_t)p.dma_lds, st, tm.start(),
                           tm.stop(), 0u, U, e.ld, (int)e.n, e.m,
                        e.weights, part);
