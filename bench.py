@@ -69,10 +69,16 @@ def read_traffic():
         return None
 
 
-def timed(fn, steps, warmup, torch):
+def timed(fn, steps, warmup, torch, pid=None):
+    """Seconds per call of fn over `steps` calls after `warmup` untimed ones.
+    With `pid`, the library's kernel events are switched on (totals cleared)
+    after the warm-up, so that the per-kernel averages leave out the first
+    launches (which load the kernels)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if pid is not None:
+        pid.pid_timing_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
@@ -298,8 +304,7 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
     # FP32 comparator and BF16 split on the same ensemble
     for scheme in ("f32", "bf16_split", "bf16"):
         call = pid.PreparedCall("pairs", U, gemm=scheme)
-        pid.pid_timing_enable(True)
-        t = timed(call.run, k, 2, torch)
+        t = timed(call.run, k, 2, torch, pid)
         g, _ = kernel_ms(pid, "gram")
         pid.pid_timing_enable(False)
         out[f"pairs_{scheme}_pp_per_s"] = n * n * m / t
@@ -307,8 +312,7 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
         if ref is not None:
             out[f"depth_err_pairs_{scheme}"] = float(np.max(np.abs(call.out["depth"].cpu().numpy() - ref["depth"])))
     pf16 = pid.PreparedCall("pairs", U, gemm="f16")
-    pid.pid_timing_enable(True)
-    t16 = timed(pf16.run, k, 2, torch)
+    t16 = timed(pf16.run, k, 2, torch, pid)
     g16, _ = kernel_ms(pid, "gram")
     pid.pid_timing_enable(False)
     out["pairs_f16_pp_per_s"] = n * n * m / t16
@@ -328,8 +332,7 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
     U3, w3 = synth.config3(device=dev)
     n3, m3 = U3.shape
     call = pid.PreparedCall("mean", U3, w3)
-    pid.pid_timing_enable(True)
-    t = timed(call.run, max(5, args.steps // 2), 2, torch)
+    t = timed(call.run, max(5, args.steps // 2), 2, torch, pid)
     km, _ = kernel_ms(pid, "pidmean")
     pid.pid_timing_enable(False)
     b3 = n3 * m3 * 2 + m3 * 4
@@ -339,8 +342,7 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
     out["mean3d_frac_hbm"] = out["mean3d_GBps"] / HBM_PEAK_GBPS
     out["mean3d_call_GBps"] = b3 / t / 1e9
     callu = pid.PreparedCall("mean", U3)
-    pid.pid_timing_enable(True)
-    timed(callu.run, max(5, args.steps // 2), 2, torch)
+    timed(callu.run, max(5, args.steps // 2), 2, torch, pid)
     kmu, _ = kernel_ms(pid, "pidmean")
     pid.pid_timing_enable(False)
     out["mean3d_unweighted_GBps"] = n3 * m3 * 2 / (kmu * 1e-3) / 1e9
@@ -362,13 +364,18 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
                        ("fields_pairs_i8", pid.PreparedCall("pairs", F, iso=siso, gemm="i8")),
                        ("fields_mean", pid.PreparedCall("mean", F, iso=giso)),
                        ("fields_mean_binary", pid.PreparedCall("mean", F, iso=siso))):
-        pid.pid_timing_enable(True)
-        t = timed(call.run, k, 2, torch)
-        kn = "gram" if "pairs" in name else "pidmean"
+        t = timed(call.run, k, 2, torch, pid)
+        # the kernels that read the fields: the Gram, the PID-mean pass, or
+        # for the sharp isovalue the bit path's first pass (threshold, pack
+        # and count; its row pass reads only the packed bits)
+        binary_mean = name == "fields_mean_binary"
+        kn = "gram" if "pairs" in name else ("pidmean_colsum" if binary_mean else "pidmean")
         kk, _ = kernel_ms(pid, kn)
         pid.pid_timing_enable(False)
         out[f"{name}_call_ms"] = t * 1e3
-        out[f"{name}_kernel_GBps"] = nf * mf * 4 / (kk * 1e-3) / 1e9
+        gbps = nf * mf * 4 / (kk * 1e-3) / 1e9
+        out[f"{name}_first_pass_GBps" if binary_mean else f"{name}_kernel_GBps"] = gbps
+        out[f"{name}_frac_hbm"] = round(gbps / HBM_PEAK_GBPS, 4)
         if "pairs" in name:
             out[f"{name}_pp_per_s"] = nf * nf * mf / t
     # the further probability models on the same fields: ramp (uniform
@@ -381,12 +388,13 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
     for mname, miso in models.items():
         for variant, kn in (("mean", "pidmean"), ("pairs", "gram")):
             call = pid.PreparedCall(variant, F, iso=miso, gemm="f16")
-            pid.pid_timing_enable(True)
-            t = timed(call.run, k, 2, torch)
+            t = timed(call.run, k, 2, torch, pid)
             kk, _ = kernel_ms(pid, kn)
             pid.pid_timing_enable(False)
             out[f"fields_{variant}_{mname}_call_ms"] = t * 1e3
-            out[f"fields_{variant}_{mname}_kernel_GBps"] = nf * mf * 4 / (kk * 1e-3) / 1e9
+            gbps = nf * mf * 4 / (kk * 1e-3) / 1e9
+            out[f"fields_{variant}_{mname}_kernel_GBps"] = gbps
+            out[f"fields_{variant}_{mname}_frac_hbm"] = round(gbps / HBM_PEAK_GBPS, 4)
     del F
 
     # all-pairs depths without the matrix (three streaming passes) against
