@@ -78,6 +78,24 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_soft_kernel(
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
     const int64_t x0 = tile * TP + (int64_t)lane * PPL;
     const bool full = (x0 + PPL <= m);
+    // A tile inside M on aligned rows (the same for the whole wave): every
+    // member's load is unconditional, so that they are all in flight
+    // together (a load under a branch of its own is waited for before the
+    // next one is issued); rows past n re-read row n - 1 and stay out of
+    // the sums.  Other tiles take guarded loads.
+    const bool fast = VEC && (tile + 1) * TP <= m;
+    Vec16<T> vv[MPW];
+    if (fast) {
+#pragma unroll
+      for (int r = 0; r < MPW; ++r) vv[r] = load16_nt(U + (int64_t)min(mbase + r, n - 1) * ld + x0);
+    } else {
+#pragma unroll
+      for (int r = 0; r < MPW; ++r) {
+        Vec16<T> v{};
+        if (mbase + r < n) v = load16_guarded(U + (int64_t)(mbase + r) * ld, x0, m);
+        vv[r] = v;
+      }
+    }
     Vec16<T> raw[KEEP_RAW ? MPW : 1];
     CT u[KEEP_RAW ? 1 : MPW][PPL];
     CT sp[PPL];
@@ -85,21 +103,17 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_soft_kernel(
     for (int p = 0; p < PPL; ++p) sp[p] = CT(0);
 #pragma unroll
     for (int r = 0; r < MPW; ++r) {
-      const int i = mbase + r;
-      Vec16<T> v{};
-      if (i < n) {
-        const T* row = U + (int64_t)i * ld;
-        if (VEC && full) v = load16_nt(row + x0);
-        else v = load16_guarded(row, x0, m);
-      }
+      const bool rv = mbase + r < n;   // (rows past n: their sums are never written)
       if constexpr (KEEP_RAW) {
-        raw[r] = v;
+        raw[r] = vv[r];
+        if (rv) {
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) sp[p] += extract_ct<MODE, T, CT>(v.v[p], ex);
+          for (int p = 0; p < PPL; ++p) sp[p] += extract_ct<MODE, T, CT>(vv[r].v[p], ex);
+        }
       } else {
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          CT val = (i < n) ? extract_ct<MODE, T, CT>(v.v[p], ex) : CT(0);
+          CT val = rv ? extract_ct<MODE, T, CT>(vv[r].v[p], ex) : CT(0);
           if (!full) val = (x0 + p < m) ? val : CT(0);
           u[r][p] = val;
           sp[p] += val;
@@ -114,8 +128,17 @@ __global__ __launch_bounds__(64 * NWMAX) void pidmean_soft_kernel(
     CT s[PPL];
     if constexpr (SFROM) {
       const CT* sg = reinterpret_cast<const CT*>(sglob);
+      if (fast) {   // PPL values, a multiple of 16 bytes at a 16-byte boundary
+        static_assert((PPL * sizeof(CT)) % 16 == 0, "whole 16-byte loads");
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) s[p] = (x0 + p < m) ? sg[x0 + p] : CT(0);
+        for (int q = 0; q < (int)(PPL * sizeof(CT) / 16); ++q) {
+          const uint4 t = *reinterpret_cast<const uint4*>(sg + x0 + q * (16 / sizeof(CT)));
+          __builtin_memcpy(&s[q * (16 / sizeof(CT))], &t, 16);
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) s[p] = (x0 + p < m) ? sg[x0 + p] : CT(0);
+      }
     } else {
       CT* sb = sbuf + (size_t)(it & 1) * nw * TP;
 #pragma unroll
