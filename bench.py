@@ -397,7 +397,7 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
             out[f"fields_{variant}_{mname}_frac_hbm"] = round(gbps / HBM_PEAK_GBPS, 4)
     del F
 
-    # all-pairs depths without the matrix (three streaming passes) against
+    # all-pairs depths without the matrix (streaming passes over the masks) against
     # the FP16 Gram at a large N, where the Gram's N^2 M work dominates
     log("large-N all-pairs depths: N=2048 on 256x256 (FP16 masks), Gram vs O(N M)")
     UL = synth.config1(device=dev, res=256, n=2048)[0].to(torch.float16)
@@ -409,7 +409,9 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
     out["largeN_n2048_m65536_gram_f16_call_ms"] = tg * 1e3
     out["largeN_n2048_m65536_linear_call_ms"] = td * 1e3
     out["largeN_linear_speedup"] = tg / td
-    out["largeN_linear_GBps_3_reads"] = 3 * nl * ml * 2 / td / 1e9
+    # four reads of the masks: column sums and row sums (masses, IN_in), then
+    # the column sums of u_j / m_j and the row sums against them
+    out["largeN_linear_GBps_4_reads"] = 4 * nl * ml * 2 / td / 1e9
     out["largeN_max_depth_diff_linear_vs_gram"] = float((gl.out["depth"] - dl.out["depth"]).abs().max())
     del UL, gl, dl
 

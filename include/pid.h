@@ -174,7 +174,8 @@ pid_status pid_all_pairs(const pid_ensemble* ens, const pid_iso* iso, int gemm,
  * B (IN_in stays exact).  out->inclusion is ignored; the other fields as
  * pid_all_pairs.  Workspace: pid_workspace_size(variant 3).  For large N, where
  * the Gram product's N^2 M work dominates, this reads the masks three times
- * instead. */
+ * instead (four beyond 256 members, where the PID-mean pass itself takes a
+ * column-sum read and a row-sum read). */
 pid_status pid_pairs_depths(const pid_ensemble* ens, const pid_iso* iso, const pid_out* out,
                             void* workspace, size_t ws_bytes, void* stream);
 
