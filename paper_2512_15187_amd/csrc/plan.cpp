@@ -260,6 +260,9 @@ MeanPlan mean_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighted)
   if (nw > max_waves) {
     p.two_pass = 1;
     nw = 8;
+    // 16-bit input: 8 members per wave (about 125 registers, two workgroups
+    // per CU) rather than 16 (about 210, one workgroup per CU)
+    if (eb == 2) mpw = 8;
     p.groups = (int)((n + (int64_t)nw * mpw - 1) / ((int64_t)nw * mpw));
     p.colsum_groups = colsum_groups(n, m, eb);
   }
@@ -295,7 +298,7 @@ MeanPlan rows_plan(int64_t n, int64_t m, int dtype) {
   const int eb = elem_bytes_of(dtype);
   const int64_t cus = device_cu_count();
   p.ntiles = (m + 64 * (16 / eb) - 1) / (64 * (16 / eb));
-  p.mpw = (n <= 32) ? 4 : (n <= 64 ? 8 : 16);
+  p.mpw = (n <= 32) ? 4 : ((n <= 64 || eb == 2) ? 8 : 16);   // (16-bit input: as in mean_plan)
   p.nwaves = (int)std::min<int64_t>(8, (n + p.mpw - 1) / p.mpw);
   p.two_pass = 1;
   p.groups = (int)((n + (int64_t)p.nwaves * p.mpw - 1) / ((int64_t)p.nwaves * p.mpw));
