@@ -663,8 +663,9 @@ __global__ __launch_bounds__(256) void pidmean_reduce(const double* __restrict__
   if (t == 0) out[(size_t)q * n + i] = red[0];
 }
 
-// One block: the total mass (fixed tree), then per member the ratios of
-// Sec. 4.1 and the depth.
+// One block per 256 members: every block forms the total mass with the
+// same fixed tree (the same value in each), then the ratios of Sec. 4.1 and
+// the depth of its members.
 __global__ __launch_bounds__(256) void pidmean_ratios(const double* __restrict__ red_v, int n,
                                                       double* __restrict__ m_out,
                                                       double* __restrict__ in_in,
@@ -681,7 +682,8 @@ __global__ __launch_bounds__(256) void pidmean_ratios(const double* __restrict__
     if (t < o) red[t] += red[t + o];
     __syncthreads();
   }
-  for (int i = t; i < n; i += 256) {
+  const int i = blockIdx.x * 256 + t;
+  if (i < n) {
     const double mm = red_v[i], a = red_v[n + i], tot = red[0];
     const double ii = (mm > 0.0) ? a / ((double)n * mm) : 0.0;
     const double oo = (tot > 0.0) ? a / tot : 0.0;
@@ -853,7 +855,7 @@ static hipError_t launch_mean_finalize(const MeanPlan& p, const pid_ensemble& e,
   KernelTimer tm("pidmean_finalize", st);
   dim3 rgrid((unsigned)e.n, 2);
   hipLaunchKernelGGL(pidmean_reduce, rgrid, 256, 0, st, (const double*)part, nparts, (int)e.n, (double*)red);
-  hipLaunchKernelGGL(pidmean_ratios, 1, 256, 0, st, (const double*)red, (int)e.n, out.mass, out.in_in, out.in_out,
+  hipLaunchKernelGGL(pidmean_ratios, (int)((e.n + 255) / 256), 256, 0, st, (const double*)red, (int)e.n, out.mass, out.in_in, out.in_out,
                      out.depth);
   return hipGetLastError();
 }
