@@ -16,7 +16,8 @@ variant, large 3D PID-mean in GB/s, 2D FP64).
 
 ``--mode serve`` runs the serving workload instead (Poisson arrivals of mixed
 requests) and prints p50/p99 latency and requests/s; ``--mode sweep`` times
-PID-mean on the shapes of the paper's scalability study.
+PID-mean on the shapes of the paper's scalability study; ``--mode largen`` runs
+only the large-N leg (all-pairs depths with and without the matrix).
 """
 from __future__ import annotations
 
@@ -397,23 +398,7 @@ def side_measurements(pid, torch, np, synth, U, args, ref):
             out[f"fields_{variant}_{mname}_frac_hbm"] = round(gbps / HBM_PEAK_GBPS, 4)
     del F
 
-    # all-pairs depths without the matrix (streaming passes over the masks) against
-    # the FP16 Gram at a large N, where the Gram's N^2 M work dominates
-    log("large-N all-pairs depths: N=2048 on 256x256 (FP16 masks), Gram vs O(N M)")
-    UL = synth.config1(device=dev, res=256, n=2048)[0].to(torch.float16)
-    nl, ml = UL.shape
-    gl = pid.PreparedCall("pairs", UL, gemm="f16")
-    dl = pid.PreparedCall("depths", UL)
-    tg = timed(gl.run, k, 2, torch)
-    td = timed(dl.run, k, 2, torch)
-    out["largeN_n2048_m65536_gram_f16_call_ms"] = tg * 1e3
-    out["largeN_n2048_m65536_linear_call_ms"] = td * 1e3
-    out["largeN_linear_speedup"] = tg / td
-    # four reads of the masks: column sums and row sums (masses, IN_in), then
-    # the column sums of u_j / m_j and the row sums against them
-    out["largeN_linear_GBps_4_reads"] = 4 * nl * ml * 2 / td / 1e9
-    out["largeN_max_depth_diff_linear_vs_gram"] = float((gl.out["depth"] - dl.out["depth"]).abs().max())
-    del UL, gl, dl
+    out.update(large_n(pid, torch, synth, dev, k))
 
     # contour-boxplot bands on the headline ensemble: median, 50 % and 100 %
     # groups of its all-pairs ranking (reads the 256 rows once, writes M bytes)
@@ -599,6 +584,39 @@ def sweep_rows(pid, torch, synth, shapes, reps=5):
     return rows
 
 
+def large_n(pid, torch, synth, dev, k):
+    """All-pairs depths without the matrix (streaming passes over the masks)
+    against the FP16 Gram at a large N, where the Gram's N^2 M work
+    dominates: N = 2048 on 256^2, FP16 masks."""
+    log("large-N all-pairs depths: N=2048 on 256x256 (FP16 masks), Gram vs O(N M)")
+    out = {}
+    UL = synth.config1(device=dev, res=256, n=2048)[0].to(torch.float16)
+    nl, ml = UL.shape
+    gl = pid.PreparedCall("pairs", UL, gemm="f16")
+    dl = pid.PreparedCall("depths", UL)
+    tg = timed(gl.run, k, 2, torch)
+    td = timed(dl.run, k, 2, torch)
+    out["largeN_n2048_m65536_gram_f16_call_ms"] = tg * 1e3
+    out["largeN_n2048_m65536_linear_call_ms"] = td * 1e3
+    out["largeN_linear_speedup"] = tg / td
+    # four reads of the masks: column sums and row sums (masses, IN_in), then
+    # the column sums of u_j / m_j and the row sums against them
+    out["largeN_linear_GBps_4_reads"] = 4 * nl * ml * 2 / td / 1e9
+    out["largeN_max_depth_diff_linear_vs_gram"] = float((gl.out["depth"] - dl.out["depth"]).abs().max())
+    del UL, gl, dl
+    return out
+
+
+def large_n_main(args):
+    """The large-N leg alone (for a kernel trace of it); one JSON line."""
+    import torch
+    import paper_2512_15187_amd as pid
+    import synth
+    res = large_n(pid, torch, synth, "cuda:0", max(3, args.steps // 4))
+    print(json.dumps({"metric": "all-pairs depths, N=2048 on 256^2 FP16 masks", "unit": "ms per call",
+                      "data": "synthetic", **res}), flush=True)
+
+
 SWEEP_SHAPES = [(n, 50) for n in (100, 1000, 10000, 20000, 40000)] + \
                [(50, r) for r in (128, 192, 256, 352, 512)]
 
@@ -620,7 +638,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["headline", "serve", "copycal", "sweep"], default="headline")
+    ap.add_argument("--mode", choices=["headline", "serve", "copycal", "sweep", "largen"], default="headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per run")
@@ -636,6 +654,8 @@ def main():
         copy_calibration(args)
     elif args.mode == "sweep":
         sweep(args)
+    elif args.mode == "largen":
+        large_n_main(args)
     else:
         headline(args)
 
