@@ -62,23 +62,14 @@ __device__ __forceinline__ int chunk_word(int lane) { return (lane & 1) ? 32 + (
 // points from 16l are the top 16 - a bits of its block's bits and the low a
 // bits of its right neighbour's; likewise from 1024 + 16l.  Neighbouring
 // lanes then swap one half-word.  Wave-uniform call.
+// Lane l's word from its two pieces hA, hB (blocks l and 64 + l of the
+// aligned-down run) and, when the chunk is not 16-byte aligned (a != 0, the
+// same for the whole wave), the neighbours' low bits shifted in; lane 63
+// takes them from hC (block 128).
 template <bool FOLD>
-__device__ __forceinline__ uint32_t chunk_word_u8(const uint8_t* row, int64_t c, int64_t m, int lane) {
-  const uint8_t* cp = row + c * 2048;
-  const int a = (int)(reinterpret_cast<uintptr_t>(cp) & 15);
-  const uint4* bp = reinterpret_cast<const uint4*>(cp - a);
-  const int64_t rem = m - c * 2048;   // points of the row from the chunk's first one
-  uint32_t hA, hB;
-  if (rem >= 2048) {   // a full chunk (wave-uniform): no guards on the loads
-    hA = nz16<FOLD>(bp[lane]);
-    hB = nz16<FOLD>(bp[64 + lane]);
-  } else {
-    hA = (16 * lane - a < rem) ? nz16<FOLD>(bp[lane]) : 0u;
-    hB = (16 * (64 + lane) - a < rem) ? nz16<FOLD>(bp[64 + lane]) : 0u;
-  }
+__device__ __forceinline__ uint32_t u8_assemble(uint32_t hA, uint32_t hB, uint32_t hC, int a, int64_t rem, int lane) {
   uint32_t lo = hA, hi = hB;
   if (a != 0) {   // wave-uniform: shift in the neighbours' low bits
-    const uint32_t hC = (lane == 63 && 16 * 128 - a < rem) ? nz16<FOLD>(bp[128]) : 0u;
     uint32_t nA = (uint32_t)__shfl_down((int)hA, 1, 64);
     uint32_t nB = (uint32_t)__shfl_down((int)hB, 1, 64);
     const uint32_t b0 = (uint32_t)__shfl((int)hB, 0, 64);
@@ -94,6 +85,50 @@ __device__ __forceinline__ uint32_t chunk_word_u8(const uint8_t* row, int64_t c,
   const int64_t left = rem - 32 * (int64_t)chunk_word(lane);   // points of the word below m
   if (left < 32) wd = left <= 0 ? 0u : (wd & ((1u << left) - 1u));
   return wd;
+}
+
+template <bool FOLD>
+__device__ __forceinline__ uint32_t chunk_word_u8(const uint8_t* row, int64_t c, int64_t m, int lane) {
+  const uint8_t* cp = row + c * 2048;
+  const int a = (int)(reinterpret_cast<uintptr_t>(cp) & 15);
+  const uint4* bp = reinterpret_cast<const uint4*>(cp - a);
+  const int64_t rem = m - c * 2048;   // points of the row from the chunk's first one
+  uint32_t hA, hB;
+  if (rem >= 2048) {   // a full chunk (wave-uniform): no guards on the loads
+    hA = nz16<FOLD>(bp[lane]);
+    hB = nz16<FOLD>(bp[64 + lane]);
+  } else {
+    hA = (16 * lane - a < rem) ? nz16<FOLD>(bp[lane]) : 0u;
+    hB = (16 * (64 + lane) - a < rem) ? nz16<FOLD>(bp[64 + lane]) : 0u;
+  }
+  const uint32_t hC = (a != 0 && lane == 63 && 16 * 128 - a < rem) ? nz16<FOLD>(bp[128]) : 0u;
+  return u8_assemble<FOLD>(hA, hB, hC, a, rem, lane);
+}
+
+// A chunk inside the row (m - 2048 c >= 2048): the three blocks a lane needs,
+// loaded without a branch, so that several rows' loads can be in flight
+// together.  Block 128 is one address for the whole wave (only lane 63 uses
+// it, and only when a != 0, where it holds a byte of the chunk); when the
+// chunk is aligned and ends the row it would lie past the row, and block 127
+// is read instead (unused).
+struct U8Blocks {
+  uint4 a, b, c;
+};
+__device__ __forceinline__ U8Blocks chunk_blocks_u8_full(const uint8_t* row, int64_t c, int64_t m, int lane) {
+  const uint8_t* cp = row + c * 2048;
+  const int a = (int)(reinterpret_cast<uintptr_t>(cp) & 15);
+  const uint4* bp = reinterpret_cast<const uint4*>(cp - a);
+  U8Blocks r;
+  r.a = bp[lane];
+  r.b = bp[64 + lane];
+  r.c = bp[(a != 0 || m - c * 2048 > 2048) ? 128 : 127];
+  return r;
+}
+template <bool FOLD>
+__device__ __forceinline__ uint32_t chunk_word_u8_full(const U8Blocks& k, const uint8_t* row, int64_t c, int64_t m,
+                                                       int lane) {
+  const int a = (int)(reinterpret_cast<uintptr_t>(row + c * 2048) & 15);
+  return u8_assemble<FOLD>(nz16<FOLD>(k.a), nz16<FOLD>(k.b), nz16<FOLD>(k.c), a, m - c * 2048, lane);
 }
 
 // Adds one bit per point to an 8-plane vertical counter.
@@ -200,6 +235,16 @@ __global__ __launch_bounds__(256) void pack_bits_kernel(const uint8_t* __restric
   const int64_t wi = c * 64 + chunk_word(lane);
   const int i1 = min(n, (int)blockIdx.y * 16 + 16);
   int i = blockIdx.y * 16;
+  if (m - c * 2048 >= 2048) {   // the chunk lies inside every row: four rows' blocks loaded first
+    for (; i + 3 < i1; i += 4) {
+      U8Blocks k[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) k[q] = chunk_blocks_u8_full(U + (int64_t)(i + q) * ld, c, m, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        out[(int64_t)(i + q) * ldw + wi] = chunk_word_u8_full<true>(k[q], U + (int64_t)(i + q) * ld, c, m, lane);
+    }
+  }
   for (; i + 3 < i1; i += 4) {   // four rows in flight
     uint32_t wd[4];
 #pragma unroll
@@ -238,6 +283,19 @@ __global__ __launch_bounds__(256) void u8_count_pack_kernel(const uint8_t* __res
 #pragma unroll
   for (int k = 0; k < 8; ++k) P[k] = 0u;
   int i = i0 + wave;
+  if (m - c * 2048 >= 2048) {   // the chunk lies inside every row: four rows' blocks loaded first
+    for (; i + 12 < i1; i += 16) {
+      U8Blocks k[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) k[q] = chunk_blocks_u8_full(U + (int64_t)(i + 4 * q) * ld, c, m, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t wd = chunk_word_u8_full<false>(k[q], U + (int64_t)(i + 4 * q) * ld, c, m, lane);
+        count_add(P, wd);
+        pk[(int64_t)(i + 4 * q) * ldp + wi] = wd;
+      }
+    }
+  }
   for (; i + 12 < i1; i += 16) {   // four rows in flight
     uint32_t wd[4];
 #pragma unroll
