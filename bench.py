@@ -22,6 +22,7 @@ only the large-N leg (all-pairs depths with and without the matrix).
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -78,6 +79,7 @@ def timed(fn, steps, warmup, torch, pid=None):
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    gc.collect()   # a collection of the previous legs' garbage falls outside the timed calls
     if pid is not None:
         pid.pid_timing_enable(True)
     t0 = time.perf_counter()
@@ -192,6 +194,7 @@ def headline(args):
         both.run()
 
     log("timing the step")
+    gc.collect()
     for _ in range(max(args.warmup, ROTATE)):
         step()
     torch.cuda.synchronize()
