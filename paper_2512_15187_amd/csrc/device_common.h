@@ -391,13 +391,14 @@ __device__ __forceinline__ float sum_from(float v) {
 }
 
 // ---- float -> 16-bit conversions (round to nearest even) ----
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
-  // Round-to-nearest-even on the upper 16 bits; inputs here are finite
-  // probabilities (NaN is not a valid membership value).
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// (the hardware conversion, v_cvt_pk_bf16_f32: round to nearest even)
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+// Two values in one conversion: a in the low half, b in the high half.
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2_bits(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2v{a, b}, bf16x2v));
+}
 
 }  // namespace pidk

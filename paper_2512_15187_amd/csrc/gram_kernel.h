@@ -853,9 +853,9 @@ __global__ __launch_bounds__(64 * NW, 4) void gram_dma_kernel(GramArgs a) {
         for (int e = 0; e < EPC; ++e) o[e] = PRODUCT ? to_f16_rounded(uv[e]) : (f16)uv[e];
         store_lds<2 * EPC>(d, o);
       } else if constexpr (MT == MT_BF16) {
-        uint16_t o[EPC];
+        uint32_t o[EPC / 2];   // pairs of values, one conversion each
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) o[e] = f32_to_bf16_bits(uv[e]);
+        for (int e = 0; e < EPC; e += 2) o[e / 2] = f32x2_to_bf16x2_bits(uv[e], uv[e + 1]);
         store_lds<2 * EPC>(d, o);
       } else if constexpr (MT == MT_I8) {
         int8_t o[EPC];   // the thresholded values are 0 or 1
@@ -863,11 +863,13 @@ __global__ __launch_bounds__(64 * NW, 4) void gram_dma_kernel(GramArgs a) {
         for (int e = 0; e < EPC; ++e) o[e] = (int8_t)(int)uv[e];
         store_lds<EPC>(d, o);
       } else {
-        uint16_t hi[EPC], lo[EPC];
+        // pairs of values: hi rounded, the exact remainder rounded again
+        uint32_t hi[EPC / 2], lo[EPC / 2];
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-          hi[e] = f32_to_bf16_bits(uv[e]);
-          lo[e] = f32_to_bf16_bits(uv[e] - bf16_bits_to_f32(hi[e]));
+        for (int e = 0; e < EPC; e += 2) {
+          const uint32_t h = f32x2_to_bf16x2_bits(uv[e], uv[e + 1]);
+          hi[e / 2] = h;
+          lo[e / 2] = f32x2_to_bf16x2_bits(uv[e] - __uint_as_float(h << 16), uv[e + 1] - __uint_as_float(h & 0xffff0000u));
         }
         store_lds<2 * EPC>(d, hi);
         store_lds<2 * EPC>(d + PLANE, lo);
@@ -1009,10 +1011,12 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
       else if (w) go(kw, lds, threads);
       else go(k, lds, threads);
     };
-    if constexpr (MODE == MODE_GAUSS && sizeof(Tin) == 4) {
+    if constexpr (MODE == MODE_GAUSS && sizeof(Tin) == 4 && MT != MT_BF16X3) {
       // the Gaussian model on FP32 values, at most 128 rows: 8 waves and
       // about 76 KB of LDS, so that two workgroups share a CU (the plan
-      // doubles the splits); each thread converts two chunks per slab
+      // doubles the splits); each thread converts two chunks per slab.
+      // (The BF16 split, with two tile planes, would not fit the 128
+      // registers that this needs.)
       if (rows <= 128) {
         const size_t lds = gram_dma_lds<Tin, MT, NT, 128>(rows, w);
         go_w(gram_dma_kernel<Tin, MT, MODE, 3, WW, NB, NT, 8, false, 128>,
@@ -1020,10 +1024,11 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
         return true;
       }
     }
-    if constexpr ((MODE == MODE_MODEL || MODE == MODE_STEP) && sizeof(Tin) == 4) {
+    if constexpr ((MODE == MODE_MODEL || MODE == MODE_STEP) && sizeof(Tin) == 4 && MT != MT_BF16X3) {
       // the piecewise-linear models or a threshold on FP32 values, at most
       // 128 rows: 256-byte row segments (twice the values between two
-      // barriers)
+      // barriers; not for the BF16 split, whose two planes of a 64-point
+      // tile would not fit the registers)
       if (rows <= 128) {
         constexpr int NB2 = gram_dma_nb<Tin, MT, NT, 256>();
         static_assert(NB2 >= 3, "LDS ring");

@@ -129,7 +129,7 @@ PairsPlan pairs_plan(int64_t n, int64_t m, int dtype, int iso_kind, bool weighte
   // while the other waits at a barrier.
   const int cus = device_cu_count();
   const bool two_per_cu = eb == 4 && iso_mode(iso_kind) == MODE_GAUSS &&
-                          (mt == MT_F16 || mt == MT_BF16 || mt == MT_BF16X3) && p.nsuper == 1 && p.sb <= 4;
+                          (mt == MT_F16 || mt == MT_BF16) && p.nsuper == 1 && p.sb <= 4;
   int64_t want = std::max<int64_t>(1, (int64_t)cus * (two_per_cu ? 2 : 1) / p.ntiles_super);
   want = std::min<int64_t>(want, std::max<int64_t>(1, p.slabs / 2));
   const int64_t min_splits = (m + 16383) / 16384;

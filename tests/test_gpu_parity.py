@@ -194,23 +194,25 @@ def test_all_pairs_binary_bitexact(n, m, kind):
 # for eight row blocks, several super-tiles past 256 rows; FP16 fields).  The
 # cases cover ragged N, a tail of M inside the last slab and point weights.
 STAGED_FIELD_CASES = [
-    # (kind, n, m, dtype, weighted)
-    ("gaussian", 100, 4132, torch.float32, True),
-    ("gaussian", 37, 2052, torch.float32, False),
-    ("gaussian", 160, 2056, torch.float32, True),
-    ("tent", 100, 4132, torch.float32, True),
-    ("step", 100, 4132, torch.float32, False),
-    ("step", 200, 2056, torch.float32, False),
-    ("step", 250, 2048, torch.float32, False),
-    ("step", 300, 1028, torch.float32, False),
-    ("step", 90, 4104, torch.float16, False),
+    # (kind, n, m, dtype, weighted, scheme of the soft kinds)
+    ("gaussian", 100, 4132, torch.float32, True, "f16"),
+    ("gaussian", 37, 2052, torch.float32, False, "f16"),
+    ("gaussian", 160, 2056, torch.float32, True, "f16"),
+    ("gaussian", 100, 4132, torch.float32, True, "bf16_split"),
+    ("tent", 100, 4132, torch.float32, True, "f16"),
+    ("tent", 100, 4132, torch.float32, False, "bf16_split"),
+    ("step", 100, 4132, torch.float32, False, None),
+    ("step", 200, 2056, torch.float32, False, None),
+    ("step", 250, 2048, torch.float32, False, None),
+    ("step", 300, 1028, torch.float32, False, None),
+    ("step", 90, 4104, torch.float16, False, None),
 ]
 
 
-@pytest.mark.parametrize("kind,n,m,dtype,weighted", STAGED_FIELD_CASES,
-                         ids=[f"{c[0]}-{c[1]}x{c[2]}-{str(c[3])[6:]}{'-w' if c[4] else ''}"
+@pytest.mark.parametrize("kind,n,m,dtype,weighted,scheme", STAGED_FIELD_CASES,
+                         ids=[f"{c[0]}-{c[1]}x{c[2]}-{str(c[3])[6:]}{'-w' if c[4] else ''}{'-' + c[5] if c[5] else ''}"
                               for c in STAGED_FIELD_CASES])
-def test_all_pairs_staged_fields(kind, n, m, dtype, weighted):
+def test_all_pairs_staged_fields(kind, n, m, dtype, weighted, scheme):
     F = _fields(n, m, 500 + n).to(dtype)
     Fh = F.to(torch.float64).numpy()
     if kind == "step":
@@ -224,9 +226,9 @@ def test_all_pairs_staged_fields(kind, n, m, dtype, weighted):
     iso = (dict(kind="gaussian", c=0.5, sigma=0.05, side=-1) if kind == "gaussian"
            else dict(kind="tent", c=0.5, width=0.1))
     w = _weights(m, 7 + n) if weighted else None
-    res = pid.pid_all_pairs(_dev(F), None if w is None else _dev(w), iso=iso, gemm="f16")
+    res = pid.pid_all_pairs(_dev(F), None if w is None else _dev(w), iso=iso, gemm=scheme)
     ref = oracle.pid(oracle.extract(Fh, iso), None if w is None else w.numpy())
-    assert_close(res, ref, TOL_MIXED, label=f"staged {kind}")
+    assert_close(res, ref, TOL_OF[scheme], label=f"staged {kind} {scheme}")
     assert_ranks(res["rank"], ref["depth"], TOL_MIXED, label=f"staged {kind}")
 
 
