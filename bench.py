@@ -76,10 +76,10 @@ def timed(fn, steps, warmup, torch, pid=None):
     With `pid`, the library's kernel events are switched on (totals cleared)
     after the warm-up, so that the per-kernel averages leave out the first
     launches (which load the kernels)."""
+    gc.collect()   # the previous legs' garbage is collected here, before the warm-up calls
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    gc.collect()   # a collection of the previous legs' garbage falls outside the timed calls
     if pid is not None:
         pid.pid_timing_enable(True)
     t0 = time.perf_counter()
