@@ -1039,13 +1039,21 @@ bool launch_gram_dma(const GramArgs& ga0, int maxt, int rows, int grid, hipStrea
         return true;
       }
     }
-    // eight row blocks in one diagonal super-tile: grouped sub-tiles
+    // eight row blocks in one diagonal super-tile: grouped sub-tiles.  There
+    // the BF16 split takes two conversion tiles (slab j + 1 is converted
+    // while the three products of slab j run, one barrier per slab), which
+    // leaves LDS for two ring slots: 64 against 74 us on 256 FP32 masks of
+    // 512^2.  (The ungrouped kernels would spill with two tiles.)
     const bool grp = ga.nsuper == 1 && ga.nbt == 8;
-    const size_t lds = gram_dma_lds<Tin, MT, NT, 128>(rows, w);
     if (grp) {
-      go_w(gram_dma_kernel<Tin, MT, MODE, 3, WW, NB, NT, 16, true, 128>,
-           gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, true, 128>, lds, 1024);
+      constexpr int NTG = (MT == MT_BF16X3) ? 2 : NT;
+      constexpr int NBG = gram_dma_nb<Tin, MT, NTG, 128>();
+      static_assert(NBG >= 2, "LDS ring");
+      const size_t lds = gram_dma_lds<Tin, MT, NTG, 128>(rows, w);
+      go_w(gram_dma_kernel<Tin, MT, MODE, 3, WW, NBG, NTG, 16, true, 128>,
+           gram_dma_kernel<Tin, MT, MODE, 3, false, NBG, NTG, 16, true, 128>, lds, 1024);
     } else {
+      const size_t lds = gram_dma_lds<Tin, MT, NT, 128>(rows, w);
       go_w(gram_dma_kernel<Tin, MT, MODE, 3, WW, NB, NT, 16, false, 128>,
            gram_dma_kernel<Tin, MT, MODE, 3, false, NB, NT, 16, false, 128>, lds, 1024);
     }
